@@ -1,0 +1,150 @@
+"""Second, independent oracle for tiny inputs: pure-Python loops that follow
+the paper's algorithms in their printed order, with sets and lists only.
+
+TEST INFRASTRUCTURE ONLY.  Distances come in as a callable dist(a, b), so the
+same code serves exact integer and fp64 data.  Ties are broken by node id
+(reading R4), and the readings R1, R2, R5, R11 and R12 apply as in the C oracle.
+
+* knn_search:            Algorithm 1 (KnnSearch), C a plain Python set.
+* adjusted_graph:        Algorithm 2 (ConstructAdjustedGraph).
+* adjust_path/has_path:  Algorithms 4 and 5 (AdjustPath, HasPath).
+* paper_visited:         Algorithms 6 and 7 (Set, IsSet) as a class.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def _key(d, i):
+    return (d, i)
+
+
+def knn_search(neigh, dist_to_q, seeds, k, thr_fn, ep=math.inf):
+    """Algorithm 1.  neigh[s] is the edge list of s sorted by length;
+    dist_to_q(n) is d(n, q); thr_fn(r) returns r(1+eps) in the reading's
+    arithmetic.  Returns (R sorted by (d, id), distance computations, hops)."""
+    C = set()
+    S = []                               # list of (d, id)
+    R = []                               # list of (d, id)
+    r = math.inf
+    dc = 0
+    for s in seeds:                      # R2: seeds de-duplicated, offered to R
+        if s in C:
+            continue
+        C.add(s)
+        d = dist_to_q(s)
+        dc += 1
+        S.append((d, s))
+        if d <= r:
+            R.append((d, s))
+            if len(R) > k:
+                R.remove(max(R))
+            if len(R) == k:
+                r = max(R)[0]
+    hops = 0
+    while S:
+        s = min(S)                       # argmin over S by (d, id)
+        S.remove(s)
+        if s[0] > thr_fn(r):
+            return sorted(R), dc, hops
+        hops += 1
+        p = 1
+        M = list(neigh[s[1]])            # already ascending by length
+        while M and p <= ep:
+            n = M.pop(0)
+            if n not in C:
+                C.add(n)
+                d = dist_to_q(n)
+                dc += 1
+                if d <= thr_fn(r):
+                    S.append((d, n))
+                if d <= r:
+                    R.append((d, n))
+                    if len(R) > k:
+                        R.remove(max(R))
+                    if len(R) == k:
+                        r = max(R)[0]
+            p += 1
+    return sorted(R), dc, hops
+
+
+def adjusted_graph(knn, knn_d, e_o, e_i):
+    """Algorithm 2 with the loop guard read as "p <= e_o or p <= e_i" (R1).
+    knn[o] lists o's neighbours, knn_d[o] their distances.  Returns per-node
+    lists of (len, id) sorted ascending."""
+    n = len(knn)
+    Ge = [dict() for _ in range(n)]      # id -> length, per node
+    for o in range(n):
+        S = [(knn_d[o][t], knn[o][t]) for t in range(len(knn[o])) if knn[o][t] >= 0]
+        p = 1
+        while S and (p <= e_o or p <= e_i):
+            dn = min(S)
+            S.remove(dn)
+            d, nn = dn
+            if p <= e_o and nn not in Ge[o]:
+                Ge[o][nn] = d
+            if p <= e_i and o not in Ge[nn]:
+                Ge[nn][o] = d
+            p += 1
+    return [sorted((l, i) for i, l in Ge[o].items()) for o in range(n)]
+
+
+def has_path(Gp, ns, nd, d_ns_nd):
+    """Algorithm 5 with edge lengths as distances."""
+    for c, _ in Gp[ns]:
+        for m, lcm in Gp[c]:
+            if m == nd and lcm < d_ns_nd:
+                return True
+    return False
+
+
+def adjust_path(G):
+    """Algorithm 4.  G: per-node lists of (len, id).  Returns G_p as per-node
+    lists of (id, len) in insertion order."""
+    n = len(G)
+    Gt = [sorted(G[v]) for v in range(n)]
+    Gp = [[] for _ in range(n)]
+    Vt = [v for v in range(n) if Gt[v]]
+    while Vt:
+        for v in list(Vt):               # ascending id, immediate visibility (R11)
+            ln, nd = min(Gt[v])
+            if not has_path(Gp, v, nd, ln):
+                Gp[v].append((nd, ln))
+            Gt[v].remove((ln, nd))
+            if not Gt[v]:
+                Vt.remove(v)
+    return Gp
+
+
+class PaperVisited:
+    """Algorithms 6 and 7: table b of size s plus collision lists L."""
+
+    def __init__(self, n, b=11):
+        lg = int(n).bit_length() - 1
+        self.s = 1 << ((lg + b) // 2)
+        self.b = [None] * self.s
+        self.L = [set() for _ in range(self.s)]
+
+    def set(self, i):
+        h = i % self.s
+        if self.b[h] is None:
+            self.b[h] = i
+        elif self.b[h] != i:
+            self.L[h].add(i)
+
+    def isset(self, i):
+        h = i % self.s
+        if self.b[h] == i:
+            return True
+        return i in self.L[h]
+
+
+def brute_topk(D: np.ndarray, k: int, exclude_diag: bool = False):
+    """k smallest (d, j) per row of a dense distance matrix via a stable sort."""
+    D = np.array(D, dtype=np.float64, copy=True)
+    if exclude_diag:
+        np.fill_diagonal(D, np.inf)
+    order = np.argsort(D, axis=1, kind="stable")[:, :k]
+    return order.astype(np.int32), np.take_along_axis(D, order, axis=1)

@@ -1,0 +1,350 @@
+"""NumPy-facing wrapper of the plain C oracle (onng_oracle.c) plus the oracle's
+own small helpers (search-range factor, e_p of dynamic degree adjustment,
+recall, predictor features, label generation).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the
+benchmark's CPU-baseline leg.  Nothing in the product package imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libonng_oracle.so")
+
+U8, F32, F16, BF16, FP8 = 0, 1, 2, 3, 4
+L2SQ, COS = 0, 1
+NFEAT = 14
+INF_EP = 0xFFFFFFFF
+
+
+class _Vecs(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("scale", C.c_void_p), ("n", C.c_int64),
+                ("dim", C.c_int32), ("pitch", C.c_int64), ("dtype", C.c_int32),
+                ("metric", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build_oracle  # noqa: F401  (package-relative when imported as oracle.oracle)
+            build_oracle.build()
+        _lib = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        _lib.or_decode.restype = C.c_double
+        _lib.or_decode.argtypes = [C.c_int32, C.c_uint32]
+        for nm in ("or_encode_f16", "or_encode_bf16", "or_encode_fp8"):
+            getattr(_lib, nm).restype = C.c_uint32
+            getattr(_lib, nm).argtypes = [C.c_float]
+        _lib.or_encode_rows.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, P, C.c_int64, P]
+        _lib.or_dist.restype = C.c_double
+        _lib.or_dist.argtypes = [P, C.c_int64, P, C.c_int64]
+        _lib.or_topk.argtypes = [P, P, C.c_int64, P, P, C.c_int64, C.c_int32, C.c_int32, P, P,
+                                 C.c_int32]
+        _lib.or_adjust_degree.argtypes = [P, P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, P,
+                                          P, P, C.c_int64, P]
+        _lib.or_adjust_path.argtypes = [P, P, P, C.c_int64, P, P, P, P]
+        _lib.or_search.argtypes = [P, P, P, C.c_int64, P, C.c_int64, P, C.c_int32, P, P, P, P,
+                                   P, C.c_int32, P, P, P, P, P, P, C.c_int32]
+        _lib.or_hash_size.restype = C.c_int64
+        _lib.or_hash_size.argtypes = [C.c_int64, C.c_int32]
+        _lib.or_visited_replay.argtypes = [C.c_int64, P, C.c_int64, P]
+        _lib.or_rerank.argtypes = [P, P, P, C.c_int32, C.c_int64, C.c_int32, P, P]
+        _lib.or_mlp_forward.argtypes = [P, C.c_int32, C.c_int32, P, P, C.c_int32, P, P,
+                                        C.c_int32, P, P]
+        _lib.or_mlp_loss_grad.restype = C.c_double
+        _lib.or_mlp_loss_grad.argtypes = [P, P, P, C.c_int32, C.c_int32, P, P, C.c_int32, P, P,
+                                          C.c_int32, P, P, P, P]
+        _lib.or_adam_step.argtypes = [P, P, P, P, C.c_int64, C.c_double, C.c_double,
+                                      C.c_double, C.c_double, C.c_int32]
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def nthreads() -> int:
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+class Vectors:
+    """Rows as stored (u8 / f32 / f16 / bf16 / fp8 codes) plus the metric."""
+
+    def __init__(self, data: np.ndarray, dtype: int, metric: int, dim: int | None = None,
+                 scale: np.ndarray | None = None):
+        data = np.ascontiguousarray(data)
+        self.data = data
+        self.dtype = dtype
+        self.metric = metric
+        esz = {U8: 1, F32: 4, F16: 2, BF16: 2, FP8: 1}[dtype]
+        self.pitch = data.shape[1] * data.dtype.itemsize
+        self.dim = dim if dim is not None else self.pitch // esz
+        self.n = data.shape[0]
+        self.scale = None if scale is None else np.ascontiguousarray(scale, dtype=np.float32)
+        self._s = _Vecs(data.ctypes.data, _ptr(self.scale), self.n, self.dim, self.pitch, dtype,
+                        metric)
+
+    @property
+    def ref(self):
+        return C.byref(self._s)
+
+    @staticmethod
+    def from_array(x: np.ndarray, metric: int) -> "Vectors":
+        if x.dtype == np.uint8:
+            return Vectors(x, U8, metric)
+        return Vectors(np.ascontiguousarray(x, dtype=np.float32), F32, metric)
+
+
+# ---------------------------------------------------------------- codecs --
+
+def decode(dtype: int, code: int) -> float:
+    return lib().or_decode(dtype, code)
+
+
+def encode_scalar(dtype: int, x: float) -> int:
+    fn = {F16: lib().or_encode_f16, BF16: lib().or_encode_bf16, FP8: lib().or_encode_fp8}[dtype]
+    return fn(float(x))
+
+
+def encode_rows(x: np.ndarray, dtype: int, pitch: int | None = None):
+    """fp32 rows -> stored rows of `dtype` (uint8 view, `pitch` bytes), fp8 scales."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    n, dim = x.shape
+    esz = {F32: 4, F16: 2, BF16: 2, FP8: 1}[dtype]
+    pitch = dim * esz if pitch is None else pitch
+    out = np.zeros((n, pitch), dtype=np.uint8)
+    scale = np.zeros(n, dtype=np.float32) if dtype == FP8 else None
+    rc = lib().or_encode_rows(x.ctypes.data, n, dim, dtype, out.ctypes.data, pitch, _ptr(scale))
+    assert rc == 0
+    return out, scale
+
+
+# --------------------------------------------------------------- top-k ----
+
+def topk(Q: Vectors, B: Vectors, k: int, q_rows=None, cand=None, exclude_self=False,
+         threads: int | None = None):
+    nq = Q.n if q_rows is None else len(q_rows)
+    qr = None if q_rows is None else np.ascontiguousarray(q_rows, dtype=np.int64)
+    cd = None if cand is None else np.ascontiguousarray(cand, dtype=np.int32)
+    ids = np.empty((nq, k), dtype=np.int32)
+    ds = np.empty((nq, k), dtype=np.float64)
+    rc = lib().or_topk(Q.ref, _ptr(qr), nq, B.ref, _ptr(cd), 0 if cd is None else len(cd), k,
+                       int(exclude_self), ids.ctypes.data, ds.ctypes.data,
+                       threads or nthreads())
+    assert rc == 0
+    return ids, ds
+
+
+def knn_graph(B: Vectors, k: int, rows=None, threads=None):
+    """Exact kNN of base rows among the base, self excluded by index."""
+    return topk(B, B, k, q_rows=rows, exclude_self=True, threads=threads)
+
+
+# ----------------------------------------------------- graph adjustment ---
+
+def adjust_degree(knn_ids, knn_d, e_o: int, e_i: int):
+    knn_ids = np.ascontiguousarray(knn_ids, dtype=np.int32)
+    knn_d = np.ascontiguousarray(knn_d, dtype=np.float64)
+    n, k = knn_ids.shape
+    nnz = C.c_int64(0)
+    rc = lib().or_adjust_degree(knn_ids.ctypes.data, knn_d.ctypes.data, n, k, e_o, e_i, None,
+                                None, None, 0, C.byref(nnz))
+    assert rc == 0
+    off = np.empty(n + 1, dtype=np.int64)
+    nb = np.empty(max(1, nnz.value), dtype=np.int32)
+    ln = np.empty(max(1, nnz.value), dtype=np.float64)
+    rc = lib().or_adjust_degree(knn_ids.ctypes.data, knn_d.ctypes.data, n, k, e_o, e_i,
+                                off.ctypes.data, nb.ctypes.data, ln.ctypes.data, nnz.value,
+                                C.byref(nnz))
+    assert rc == 0
+    return off, nb[:nnz.value], ln[:nnz.value]
+
+
+def adjust_path(off, nbrs, lens):
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    nbrs = np.ascontiguousarray(nbrs, dtype=np.int32)
+    lens = np.ascontiguousarray(lens, dtype=np.float64)
+    n = len(off) - 1
+    nnz = C.c_int64(0)
+    oo = np.empty(n + 1, dtype=np.int64)
+    on = np.empty(max(1, len(nbrs)), dtype=np.int32)
+    ol = np.empty(max(1, len(nbrs)), dtype=np.float64)
+    rc = lib().or_adjust_path(off.ctypes.data, nbrs.ctypes.data, lens.ctypes.data, n,
+                              oo.ctypes.data, on.ctypes.data, ol.ctypes.data, C.byref(nnz))
+    assert rc == 0
+    return oo, on[:nnz.value], ol[:nnz.value]
+
+
+# ---------------------------------------------------------------- search --
+
+def range_factor(eps: float, metric: int) -> np.float32:
+    """Reading R5: fp32((1+eps)^2) on squared L2, fp32(1+eps) on cosine."""
+    t = 1.0 + float(np.float32(eps))
+    return np.float32(t * t if metric == L2SQ else t)
+
+
+def dynamic_ep(eps: float, e0: float = 30.0, we: float = 20.0) -> int:
+    """Equation 1, e_p = 10^(w_e eps) + e_0, floored to an edge count."""
+    v = math.floor(10.0 ** (we * float(np.float32(eps))) + e0)
+    return int(min(v, INF_EP))
+
+
+def _per_query(v, nq, dtype):
+    a = np.asarray(v, dtype=dtype)
+    if a.ndim == 0:
+        a = np.full(nq, a, dtype=dtype)
+    return np.ascontiguousarray(a)
+
+
+def search(base: Vectors, off, nbrs, queries: Vectors, seeds, k, eps, ep=INF_EP, eps1=None,
+           ep1=None, k_stride=None, want_features=False, threads=None):
+    """Algorithm 1 for every query.  Returns dict with ids, dists, dc, hops, margin[, feat]."""
+    nq = queries.n
+    seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+    kk = _per_query(k, nq, np.int32)
+    ee = _per_query(eps, nq, np.float32)
+    pp = _per_query(ep, nq, np.uint32)
+    e1 = None if eps1 is None else _per_query(eps1, nq, np.float32)
+    p1 = None if ep1 is None else _per_query(ep1, nq, np.uint32)
+    ks = int(kk.max()) if k_stride is None else k_stride
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    nbrs = np.ascontiguousarray(nbrs, dtype=np.int32)
+    ids = np.empty((nq, ks), dtype=np.int32)
+    ds = np.empty((nq, ks), dtype=np.float64)
+    dc = np.empty(nq, dtype=np.int64)
+    hops = np.empty(nq, dtype=np.int64)
+    margin = np.empty(nq, dtype=np.float64)
+    feat = np.zeros((nq, NFEAT), dtype=np.float64) if want_features else None
+    rc = lib().or_search(base.ref, off.ctypes.data, nbrs.ctypes.data, base.n, queries.ref, nq,
+                         seeds.ctypes.data, seeds.shape[1], kk.ctypes.data, ee.ctypes.data,
+                         pp.ctypes.data, _ptr(e1), _ptr(p1), ks, ids.ctypes.data,
+                         ds.ctypes.data, dc.ctypes.data, hops.ctypes.data, margin.ctypes.data,
+                         _ptr(feat), threads or nthreads())
+    assert rc == 0, rc
+    out = dict(ids=ids, dists=ds, dc=dc, hops=hops, margin=margin)
+    if want_features:
+        out["feat"] = feat
+    return out
+
+
+def hash_size(n: int, b: int = 11) -> int:
+    return int(lib().or_hash_size(n, b))
+
+
+def visited_replay(n: int, ops) -> np.ndarray:
+    ops = np.ascontiguousarray(ops, dtype=np.int64)
+    ans = np.empty(int((ops < 0).sum()), dtype=np.int32)
+    rc = lib().or_visited_replay(n, ops.ctypes.data, len(ops), ans.ctypes.data)
+    assert rc == 0
+    return ans
+
+
+def rerank(Q: Vectors, B: Vectors, pool, k: int):
+    pool = np.ascontiguousarray(pool, dtype=np.int32)
+    nq, psz = pool.shape
+    ids = np.empty((nq, k), dtype=np.int32)
+    ds = np.empty((nq, k), dtype=np.float64)
+    rc = lib().or_rerank(Q.ref, B.ref, pool.ctypes.data, psz, nq, k, ids.ctypes.data,
+                         ds.ctypes.data)
+    assert rc == 0
+    return ids, ds
+
+
+# ---------------------------------------------------------------- recall --
+
+def recall_at_k(res_ids, res_d, gt_d, k: int) -> np.ndarray:
+    """Tie-tolerant recall@k: |{x in R : d(x,q) <= d_k^GT(q)}| / k, per query.
+
+    The paper's precision is the fraction of returned objects that are true
+    k nearest neighbours; with |R| = k that is recall@k.  Objects tied with
+    the k-th true distance count as correct."""
+    res_ids = np.asarray(res_ids)[:, :k]
+    res_d = np.asarray(res_d, dtype=np.float64)[:, :k]
+    kth = np.asarray(gt_d, dtype=np.float64)[:, k - 1:k]
+    ok = (res_ids >= 0) & (res_d <= kth)
+    return ok.sum(axis=1) / float(k)
+
+
+# --------------------------------------------------- learned search range --
+
+def feature_transform(feat: np.ndarray, metric: int) -> np.ndarray:
+    """Raw first-expansion state -> predictor inputs (before z-scoring).
+
+    Distances enter as log(d + c) with c = 1 for squared L2 on u8 data scale
+    and c = 1e-3 on cosine; the 7 further seed distances as differences of
+    those logs to the nearest seed; counts as log(1 + n)."""
+    feat = np.asarray(feat, dtype=np.float64)
+    c = 1e-3 if metric == COS else 1.0
+    x = np.empty_like(feat)
+    lg = np.log(np.maximum(feat[:, :8], 0.0) + c)
+    x[:, 0] = lg[:, 0]
+    x[:, 1:8] = lg[:, 1:8] - lg[:, :1]
+    x[:, 8] = np.log1p(feat[:, 8])
+    for j in (9, 10, 11, 12):
+        x[:, j] = np.log(np.maximum(feat[:, j], 0.0) + c) - lg[:, 0]
+    x[:, 13] = np.log1p(feat[:, 13])
+    return x
+
+
+def labels_from_sweep(recalls: np.ndarray, eps_grid, targets) -> np.ndarray:
+    """label[q, t] = smallest grid eps whose per-query recall reaches targets[t]
+    (the largest grid eps when none does).  recalls: (n_eps, nq)."""
+    recalls = np.asarray(recalls)
+    grid = np.asarray(eps_grid, dtype=np.float64)
+    out = np.empty((recalls.shape[1], len(targets)), dtype=np.float64)
+    for t, tgt in enumerate(targets):
+        ok = recalls >= tgt - 1e-12
+        first = np.where(ok.any(axis=0), ok.argmax(axis=0), len(grid) - 1)
+        out[:, t] = grid[first]
+    return out
+
+
+# ------------------------------------------------------------------ MLP ---
+
+def mlp_forward(X, W1, b1, W2, b2):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    B, F = X.shape
+    H = W1.shape[0]
+    T = W2.shape[0]
+    hid = np.empty((B, H))
+    Y = np.empty((B, T))
+    args = [np.ascontiguousarray(a, dtype=np.float64) for a in (W1, b1, W2, b2)]
+    rc = lib().or_mlp_forward(X.ctypes.data, B, F, args[0].ctypes.data, args[1].ctypes.data, H,
+                              args[2].ctypes.data, args[3].ctypes.data, T, hid.ctypes.data,
+                              Y.ctypes.data)
+    assert rc == 0
+    return hid, Y
+
+
+def mlp_loss_grad(X, target, W1, b1, W2, b2, w=None):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    target = np.ascontiguousarray(target, dtype=np.float64)
+    B, F = X.shape
+    H = W1.shape[0]
+    T = W2.shape[0]
+    W1, b1, W2, b2 = [np.ascontiguousarray(a, dtype=np.float64) for a in (W1, b1, W2, b2)]
+    wt = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    g = [np.empty_like(a) for a in (W1, b1, W2, b2)]
+    loss = lib().or_mlp_loss_grad(X.ctypes.data, target.ctypes.data, _ptr(wt), B, F,
+                                  W1.ctypes.data, b1.ctypes.data, H, W2.ctypes.data,
+                                  b2.ctypes.data, T, *[a.ctypes.data for a in g])
+    return loss, g
+
+
+def adam_step(p, g, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+    for a in (p, g, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib().or_adam_step(p.ctypes.data, g.ctypes.data, m.ctypes.data, v.ctypes.data, p.size, lr,
+                       beta1, beta2, eps, t)
