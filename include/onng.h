@@ -1,0 +1,327 @@
+/*
+ * onng.h — C-ABI of the MI355X (gfx950) implementation of the adjusted
+ * k-nearest-neighbour-graph index and search of Iwasaki & Miyazaki,
+ * "Optimization of Indexing Based on k-Nearest Neighbor Graph for Proximity
+ * Search in High-dimensional Data" (arXiv 1810.07355).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every buffer pointer is DEVICE memory owned by the caller, unless the
+ *    comment says "host".  The library keeps no pointer after a call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls enqueue their kernels on it and return after argument validation;
+ *    results are valid once the stream is synchronised.  Calls that return a
+ *    count to a host pointer (onng_adjust_degree, onng_adjust_path)
+ *    synchronise the stream themselves.
+ *  - Scratch memory comes from the caller: `ws`/`ws_bytes`, sized by the
+ *    matching *_workspace_size function.  The library allocates no device
+ *    memory of its own (the tuning cache is host memory).
+ *  - Errors are return codes; nothing throws or aborts across the ABI.
+ *    Argument errors are detected before any kernel is enqueued, and then no
+ *    output is touched.  onng_last_error() gives a message for the calling
+ *    thread.  A HIP runtime failure is ONNG_ERR_DEVICE.
+ *  - Distances: squared Euclidean (ONNG_L2SQ) or cosine distance 1 - <x, y>
+ *    (ONNG_COSINE, meant for unit vectors).  On u8 data with ONNG_L2SQ every
+ *    distance is an exact integer and is stored as int32; everything else is
+ *    stored as float.  This is the "distance type" of the data set.
+ *  - Ties are broken by node id: every ordering uses the pair (distance, id).
+ *  - Calls on distinct streams with distinct workspaces may run concurrently.
+ */
+#ifndef ONNG_H
+#define ONNG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ONNG_OK = 0,
+    ONNG_ERR_INVALID_ARG = -1,   /* null pointer, bad size, k > n-1, ... */
+    ONNG_ERR_UNSUPPORTED = -2,   /* dtype/metric combination not provided */
+    ONNG_ERR_CAPACITY = -3,      /* an output capacity is too small */
+    ONNG_ERR_WORKSPACE = -4,     /* ws_bytes below the *_workspace_size value */
+    ONNG_ERR_DEVICE = -5         /* HIP runtime error */
+} onng_status;
+
+typedef enum {
+    ONNG_U8 = 0,        /* uint8 components */
+    ONNG_F32 = 1,       /* IEEE binary32 */
+    ONNG_F16 = 2,       /* IEEE binary16, round-to-nearest-even from f32 */
+    ONNG_BF16 = 3,      /* bfloat16, round-to-nearest-even from f32 */
+    ONNG_FP8_E4M3 = 4   /* OCP e4m3fn with a per-row f32 scale: x = code * scale */
+} onng_dtype;
+
+typedef enum { ONNG_L2SQ = 0, ONNG_COSINE = 1 } onng_metric;
+
+/* A set of vectors: n rows of `dim` components, `pitch_bytes` apart (a
+ * multiple of 16 and at least dim * element size; bytes past the last
+ * component must be zero).  `scale` is the per-row f32 scale of FP8 rows and
+ * NULL otherwise.  The objects of the paper's Section 2 problem statement. */
+typedef struct {
+    const void *data;
+    const float *scale;
+    int64_t n;
+    int32_t dim;
+    int32_t dtype;        /* onng_dtype */
+    int64_t pitch_bytes;
+    int32_t metric;       /* onng_metric */
+    int32_t reserved;
+} onng_vectors;
+
+/* A neighbourhood graph in CSR form: the edges of node v are
+ * nbrs[offsets[v] .. offsets[v+1]), sorted ascending by (length, id), and
+ * lens holds each edge's length d(v, nbrs[e]) in the distance type.  This is
+ * the graph of Section 2 whose edges are kept sorted by length. */
+typedef struct {
+    const int64_t *offsets;   /* [n + 1] */
+    const int32_t *nbrs;      /* [nnz] */
+    const void *lens;         /* [nnz] int32 or float; may be NULL for onng_search */
+    int64_t n;
+    int64_t nnz;
+} onng_graph;
+
+/* ------------------------------------------------------------------------ */
+/* Exact k-nearest neighbours (brute force, matrix cores)                   */
+/* ------------------------------------------------------------------------ */
+
+/* The exact k-NN graph of `base`: for every row i the k rows j != i with the
+ * smallest (d(i, j), j), ascending.  It stands in for the approximate KNNG that
+ * ConstructGraph (Algorithm 8) derives from an ANNG; Section 2.6 notes that
+ * the exact graph is the costly ideal.
+ * ids: [n][k] int32; dists: [n][k] in the distance type.  Requires
+ * 1 <= k <= n - 1 and k <= 256.  On float data the distances are computed in
+ * f32 on the matrix cores (|x|^2 + |y|^2 - 2<x, y>), so rows can differ from an
+ * exact computation by rounding near ties.  u8 data is exact. */
+onng_status onng_build_knn(const onng_vectors *base, int32_t k, int32_t *ids, void *dists,
+                           void *ws, size_t ws_bytes, void *stream);
+
+/* General form: for each query row the k smallest (d(q, j), j) over the base
+ * rows, or over the candidate ids `cand` (device [n_cand]) when it is not
+ * NULL.  exclude_self skips j == query row index (queries == base).  Used for
+ * seeds (the nearest pivots), ground truth and the k-NN graph.  Rows with
+ * fewer than k candidates are padded with id -1 and distance INT32_MAX or
+ * +inf. */
+onng_status onng_topk(const onng_vectors *queries, const onng_vectors *base,
+                      const int32_t *cand, int64_t n_cand, int32_t k, int32_t exclude_self,
+                      int32_t *ids, void *dists, void *ws, size_t ws_bytes, void *stream);
+size_t onng_topk_workspace_size(const onng_vectors *queries, const onng_vectors *base,
+                                int64_t n_cand, int32_t k);
+
+/* ------------------------------------------------------------------------ */
+/* Static degree adjustment — Algorithm 2 (ConstructAdjustedGraph)          */
+/* ------------------------------------------------------------------------ */
+
+/* From a k-NN table (rows sorted by (dist, id), padded with -1), build G_e:
+ * node o keeps its first min(e_o, k) edges and receives the reverse of every
+ * edge m -> o among the first min(e_i, k) edges of m (Algorithm 2, with the
+ * loop running while p <= e_o or p <= e_i).  An edge produced both ways is
+ * kept once, with the length of the copy Algorithm 2 inserts first (its loop
+ * runs over nodes in ascending id): the reverse copy when the far end has the
+ * smaller id, else the forward copy.  Each list is sorted by (length, id), so
+ * the result equals a sequential run of Algorithm 2 on the same table.
+ * knn_dists and lens are in the distance type of `data_dtype`/`metric`.
+ * offsets: [n+1] int64; nbrs/lens: capacity nnz_capacity.
+ * nnz_out (host): edge count.  ONNG_ERR_CAPACITY when it exceeds
+ * nnz_capacity (then *nnz_out is the size needed and the outputs are
+ * unspecified).  n * (min(e_o,k) + min(e_i,k)) always suffices. */
+onng_status onng_adjust_degree(const int32_t *knn_ids, const void *knn_dists, int64_t n, int32_t k,
+                               int32_t data_dtype, int32_t metric, int32_t e_o, int32_t e_i,
+                               int64_t *offsets, int32_t *nbrs, void *lens, int64_t nnz_capacity,
+                               int64_t *nnz_out, void *ws, size_t ws_bytes, void *stream);
+size_t onng_adjust_degree_workspace_size(int64_t n, int32_t k, int32_t e_o, int32_t e_i);
+
+/* ------------------------------------------------------------------------ */
+/* Path adjustment — Algorithms 4 (AdjustPath) and 5 (HasPath)              */
+/* ------------------------------------------------------------------------ */
+
+/* G_p from G: rounds j = 0, 1, ... visit every node n with more than j edges
+ * in ascending id; n's j-th edge n -> n_d is kept unless G_p (including
+ * edges kept earlier in the same round) has an edge n -> c and an edge
+ * c -> n_d with len(c, n_d) < len(n, n_d).  Result: an order-preserving
+ * subset of each list.  `in` must have lens.  Output capacity is in->nnz.
+ * nnz_out (host): edges kept. */
+onng_status onng_adjust_path(const onng_graph *in, int32_t data_dtype, int32_t metric,
+                             int64_t *offsets, int32_t *nbrs, void *lens, int64_t *nnz_out,
+                             void *ws, size_t ws_bytes, void *stream);
+size_t onng_adjust_path_workspace_size(int64_t n, int64_t nnz);
+
+/* ------------------------------------------------------------------------ */
+/* Search — Algorithm 1 (KnnSearch)                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Optional learned search range: a 2-layer MLP (F -> H ReLU -> T heads) that
+ * maps the state after the first expansion to log10(eps + 0.01) for each
+ * target recall.  Weights are bf16 (w1: [H][F], w2: [T][H]); biases, feature
+ * statistics and shifts are f32.  Not part of the paper. */
+typedef struct {
+    const uint16_t *w1_bf16;
+    const float *b1;
+    const uint16_t *w2_bf16;
+    const float *b2;
+    const float *feat_mean;        /* [F] z-scoring of the transformed features */
+    const float *feat_std;         /* [F] */
+    const float *shift;            /* [T] calibration shift added to each head, or NULL */
+    const int32_t *head_per_query; /* [nq] head index per query, or NULL: use `head` */
+    int32_t head;
+    int32_t n_features;            /* must be ONNG_NFEAT */
+    int32_t hidden;                /* <= 64 */
+    int32_t n_heads;               /* <= 8 */
+    float eps_min, eps_max;        /* predicted eps is clamped to this range */
+    float e0, we;                  /* e_p = floor(10^(we*eps) + e0) (Equation 1); we < 0: use e_p */
+} onng_predictor;
+
+#define ONNG_NFEAT 14
+
+/* Launch shape of the search kernel (0 = library default for a field). */
+typedef struct {
+    int32_t waves_per_block;   /* 1..8 */
+    int32_t lanes_per_row;     /* 4, 8, 16 or 32: lanes that share one vector */
+    int32_t s_capacity;        /* candidate-set entries held on chip per query */
+    int32_t visited_log2;      /* on-chip visited table has 2^visited_log2 slots */
+    int32_t pool_capacity;     /* rerank pool entries held on chip per query */
+    int32_t blocks;            /* persistent grid size; 0 = one wave per query */
+} onng_launch_config;
+
+typedef struct {
+    int32_t k;                     /* results per query when k_per_query is NULL */
+    int32_t k_stride;              /* row length of ids/dists, >= every k, <= 256 */
+    const int32_t *k_per_query;    /* [nq] or NULL */
+    float epsilon;                 /* search range eps when eps_per_query is NULL */
+    const float *eps_per_query;    /* [nq] or NULL */
+    uint32_t e_p;                  /* explored-edge limit when ep_per_query is NULL;
+                                      0xFFFFFFFF = unlimited (Equation 1's e_p) */
+    const uint32_t *ep_per_query;  /* [nq] or NULL */
+    /* Two-phase mode: when two_phase != 0 the first expansion uses an
+     * unlimited range and e_p = ep_first; the search range of every later
+     * step comes from the predictor (if set) or from eps/e_p above. */
+    int32_t two_phase;
+    uint32_t ep_first;
+    const onng_predictor *predictor;   /* requires two_phase */
+    float *features_out;           /* [nq][ONNG_NFEAT] raw state after the first
+                                      expansion (two_phase only), or NULL */
+    /* Rerank: search on the stored (possibly low-precision) rows, keep the
+     * pool_factor*k best visited ids, recompute their distances from
+     * rerank_base (f32 rows of the same objects) and return the best k. */
+    const onng_vectors *rerank_base;   /* NULL = no rerank */
+    int32_t pool_factor;
+    const onng_launch_config *launch;  /* NULL = tuned or default shape */
+} onng_search_params;
+
+/* Per-query statistics written by onng_search. */
+typedef struct {
+    int32_t dc;        /* distance computations (seeds included) */
+    int32_t hops;      /* expansions (pops that passed the range test) */
+    int32_t flags;     /* ONNG_QF_* bits */
+    uint32_t e_p;      /* explored-edge limit used after the first expansion */
+    float eps;         /* search range used after the first expansion */
+    int32_t reserved[3];
+} onng_query_stats;
+
+#define ONNG_QF_PADDED 1      /* fewer than k results were reachable */
+#define ONNG_QF_SPILLED 2     /* exceeded on-chip capacity, finished by the exact off-chip pass */
+#define ONNG_QF_CAPACITY 4    /* exceeded even the off-chip capacity: result not exact */
+
+/* Batched KnnSearch (Algorithm 1) for every query row: best-first expansion
+ * from the seeds with search range r(1 + eps), at most e_p edges per node,
+ * visited set C, result set R of size k (radius r).  Seeds: [nq][n_seeds]
+ * node ids (duplicates and ids < 0 ignored); each seed is a distance
+ * computation, is marked visited and is offered to R.  Outputs: ids
+ * [nq][k_stride], dists [nq][k_stride] in the distance type (or f32 after a
+ * rerank), ascending, padded with -1 / INT32_MAX or +inf; stats [nq].
+ * With range factor f = (1+eps)^2 for ONNG_L2SQ and 1+eps for ONNG_COSINE
+ * (rounded to f32), a node is pushed to the candidate set when
+ * d <= f32(r * f) and the search stops when the nearest candidate is beyond it. */
+onng_status onng_search(const onng_vectors *base, const onng_graph *graph,
+                        const onng_vectors *queries, const int32_t *seeds, int32_t n_seeds,
+                        const onng_search_params *params, int32_t *ids, void *dists,
+                        onng_query_stats *stats, void *ws, size_t ws_bytes, void *stream);
+size_t onng_search_workspace_size(const onng_vectors *base, int64_t n_queries,
+                                  const onng_search_params *params);
+
+/* ------------------------------------------------------------------------ */
+/* Low-precision storage and exact rerank (not part of the paper)           */
+/* ------------------------------------------------------------------------ */
+
+/* f32 rows [n][dim] (row stride dim) -> rows of `dtype`, dst_pitch bytes
+ * apart, padding zero.  Round-to-nearest-even; FP8 saturates at +-448 after
+ * dividing by the per-row scale maxabs/448 (scale 1 for an all-zero row),
+ * written to `scale` [n]. */
+onng_status onng_encode(const float *src, int64_t n, int32_t dim, int32_t dtype, void *dst,
+                        int64_t dst_pitch, float *scale, void *stream);
+
+/* For each query the k best (d, id) among pool ids [nq][pool_size] (ids < 0
+ * skipped), with distances recomputed from `base` in f32 (use_f64 = 0) or
+ * f64 (use_f64 = 1).  dists: f32 or f64 [nq][k]. */
+onng_status onng_rerank(const onng_vectors *queries, const onng_vectors *base,
+                        const int32_t *pool, int32_t pool_size, int32_t k, int32_t use_f64,
+                        int32_t *ids, void *dists, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Learned search range: training kernels (not part of the paper)           */
+/* ------------------------------------------------------------------------ */
+
+/* Y = W2 relu(W1 X + b1) + b2, all f32 row-major; hidden [batch][H] optional. */
+onng_status onng_mlp_forward(const float *X, int32_t batch, int32_t F, const float *W1,
+                             const float *b1, int32_t H, const float *W2, const float *b2,
+                             int32_t T, float *hidden, float *Y, void *stream);
+/* Gradients of mean(w * (Y - target)^2) over batch*T (w NULL = all ones) and
+ * the loss itself (device scalar).  Sums over the batch run in a fixed order
+ * (deterministic).  ws: onng_mlp_backward_workspace_size(batch, H, T) bytes. */
+onng_status onng_mlp_backward(const float *X, const float *target, const float *w, int32_t batch,
+                              int32_t F, const float *W1, const float *b1, int32_t H,
+                              const float *W2, const float *b2, int32_t T, float *gW1,
+                              float *gb1, float *gW2, float *gb2, float *loss, void *ws,
+                              size_t ws_bytes, void *stream);
+size_t onng_mlp_backward_workspace_size(int32_t batch, int32_t H, int32_t T);
+/* One Adam step with bias correction (t >= 1). */
+onng_status onng_adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr,
+                           float beta1, float beta2, float eps, int32_t t, void *stream);
+/* raw features [n][ONNG_NFEAT] -> predictor inputs, the transform the search
+ * kernel applies before z-scoring. */
+onng_status onng_feature_transform(const float *raw, int64_t n, int32_t metric, float *out,
+                                   void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Launch tuning and graph capture (not part of the paper)                  */
+/* ------------------------------------------------------------------------ */
+
+/* Times candidate launch shapes of onng_search on the given calibration
+ * batch and writes the fastest to *best (host).  Results are cached in host
+ * memory per (dtype, dim, n, k_stride, rerank); *best is then returned at once. */
+onng_status onng_autotune_search(const onng_vectors *base, const onng_graph *graph,
+                                 const onng_vectors *queries, const int32_t *seeds,
+                                 int32_t n_seeds, const onng_search_params *params,
+                                 int32_t *ids, void *dists, onng_query_stats *stats, void *ws,
+                                 size_t ws_bytes, void *stream, onng_launch_config *best);
+
+/* Captures the query pipeline (seed selection against `pivots`, search with
+ * its predictor and rerank) for a fixed batch into a HIP graph, returned
+ * in *handle (host).  All pointers must stay valid while the handle lives. */
+typedef struct onng_pipeline onng_pipeline;
+onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *graph,
+                                 const onng_vectors *queries, const int32_t *pivots,
+                                 int64_t n_pivots, int32_t n_seeds, int32_t *seeds,
+                                 const onng_search_params *params, int32_t *ids, void *dists,
+                                 onng_query_stats *stats, void *ws, size_t ws_bytes,
+                                 void *stream, onng_pipeline **handle);
+size_t onng_pipeline_workspace_size(const onng_vectors *base, const onng_vectors *queries,
+                                    int64_t n_pivots, int32_t n_seeds,
+                                    const onng_search_params *params);
+onng_status onng_pipeline_launch(onng_pipeline *handle, void *stream);
+onng_status onng_pipeline_destroy(onng_pipeline *handle);
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics                                                              */
+/* ------------------------------------------------------------------------ */
+
+const char *onng_status_string(onng_status st);
+const char *onng_last_error(void);          /* calling thread's last message */
+int32_t onng_version(void);                 /* major*10000 + minor*100 + patch */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ONNG_H */

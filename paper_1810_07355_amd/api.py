@@ -1,0 +1,398 @@
+"""Python binding of libonng.so: argument marshalling only.
+
+Torch tensors provide device memory and the current HIP stream; every step of
+the path runs in the library's kernels.  Function names follow the C-ABI
+(include/onng.h) without the `onng_` prefix."""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import math
+
+import torch
+
+from . import _lib as L
+
+_DTYPE_BYTES = {L.U8: 1, L.F32: 4, L.F16: 2, L.BF16: 2, L.FP8_E4M3: 1}
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def row_pitch(dim: int, dtype: int) -> int:
+    """Smallest 16-byte multiple holding `dim` elements of `dtype`."""
+    return (dim * _DTYPE_BYTES[dtype] + 15) // 16 * 16
+
+
+class Vectors:
+    """Device rows of one storage type.  `data` is a uint8/float tensor
+    [n, pitch_bytes / element size]; `scale` the FP8 per-row scale."""
+
+    def __init__(self, data: torch.Tensor, dtype: int, metric: int, dim: int,
+                 scale: torch.Tensor | None = None):
+        assert data.is_cuda and data.is_contiguous()
+        self.data = data
+        self.dtype = dtype
+        self.metric = metric
+        self.dim = dim
+        self.n = data.shape[0]
+        self.pitch = data.shape[1] * data.element_size() if data.dim() == 2 else 0
+        self.scale = scale
+        self._s = L.Vectors_t(data.data_ptr(), _ptr(scale), self.n, dim, dtype, self.pitch,
+                              metric, 0)
+
+    @property
+    def ref(self):
+        return C.byref(self._s)
+
+    @property
+    def dist_dtype(self):
+        return torch.int32 if (self.dtype == L.U8 and self.metric == L.L2SQ) else torch.float32
+
+    @staticmethod
+    def from_tensor(x: torch.Tensor, metric: int) -> "Vectors":
+        """u8 or f32 rows, padded to a 16-byte pitch with zeros."""
+        n, dim = x.shape
+        dtype = L.U8 if x.dtype == torch.uint8 else L.F32
+        esz = _DTYPE_BYTES[dtype]
+        cols = row_pitch(dim, dtype) // esz
+        if cols != dim:
+            buf = torch.zeros((n, cols), dtype=x.dtype, device=x.device)
+            buf[:, :dim] = x
+            x = buf
+        return Vectors(x.contiguous(), dtype, metric, dim)
+
+
+@dataclasses.dataclass
+class Graph:
+    offsets: torch.Tensor
+    nbrs: torch.Tensor
+    lens: torch.Tensor | None
+
+    @property
+    def n(self):
+        return self.offsets.numel() - 1
+
+    @property
+    def nnz(self):
+        return self.nbrs.numel()
+
+    def struct(self):
+        return L.Graph_t(self.offsets.data_ptr(), self.nbrs.data_ptr(), _ptr(self.lens), self.n,
+                         self.nnz)
+
+
+# ------------------------------------------------------------------ top-k --
+
+def topk(queries: Vectors, base: Vectors, k: int, cand: torch.Tensor | None = None,
+         exclude_self: bool = False):
+    dev = queries.data.device
+    ids = torch.empty((queries.n, k), dtype=torch.int32, device=dev)
+    d = torch.empty((queries.n, k), dtype=queries.dist_dtype, device=dev)
+    nc = 0 if cand is None else cand.numel()
+    ws_n = L.load().onng_topk_workspace_size(queries.ref, base.ref, nc, k)
+    ws = _workspace(ws_n, dev)
+    L.call("onng_topk", queries.ref, base.ref, _ptr(cand), nc, k, int(exclude_self),
+           ids.data_ptr(), d.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    return ids, d
+
+
+def build_knn(base: Vectors, k: int):
+    dev = base.data.device
+    ids = torch.empty((base.n, k), dtype=torch.int32, device=dev)
+    d = torch.empty((base.n, k), dtype=base.dist_dtype, device=dev)
+    ws_n = L.load().onng_topk_workspace_size(base.ref, base.ref, 0, k)
+    ws = _workspace(ws_n, dev)
+    L.call("onng_build_knn", base.ref, k, ids.data_ptr(), d.data_ptr(), ws.data_ptr(),
+           ws.numel(), _stream())
+    return ids, d
+
+
+# ------------------------------------------------------------ adjustments --
+
+def adjust_degree(knn_ids: torch.Tensor, knn_d: torch.Tensor, dtype: int, metric: int, e_o: int,
+                  e_i: int) -> Graph:
+    n, k = knn_ids.shape
+    dev = knn_ids.device
+    cap = n * (min(e_o, k) + min(e_i, k))
+    off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    nb = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    ln = torch.empty(max(cap, 1), dtype=knn_d.dtype, device=dev)
+    ws = _workspace(L.load().onng_adjust_degree_workspace_size(n, k, e_o, e_i), dev)
+    nnz = C.c_int64(0)
+    L.call("onng_adjust_degree", knn_ids.data_ptr(), knn_d.data_ptr(), n, k, dtype, metric, e_o,
+           e_i, off.data_ptr(), nb.data_ptr(), ln.data_ptr(), cap, C.byref(nnz), ws.data_ptr(),
+           ws.numel(), _stream())
+    return Graph(off, nb[:nnz.value].clone(), ln[:nnz.value].clone())
+
+
+def adjust_path(g: Graph, dtype: int, metric: int) -> Graph:
+    dev = g.offsets.device
+    off = torch.empty_like(g.offsets)
+    nb = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=dev)
+    ln = torch.empty(max(g.nnz, 1), dtype=g.lens.dtype, device=dev)
+    ws = _workspace(L.load().onng_adjust_path_workspace_size(g.n, g.nnz), dev)
+    gs = g.struct()
+    nnz = C.c_int64(0)
+    L.call("onng_adjust_path", C.byref(gs), dtype, metric, off.data_ptr(), nb.data_ptr(),
+           ln.data_ptr(), C.byref(nnz), ws.data_ptr(), ws.numel(), _stream())
+    return Graph(off, nb[:nnz.value].clone(), ln[:nnz.value].clone())
+
+
+# ----------------------------------------------------------------- search --
+
+@dataclasses.dataclass
+class Predictor:
+    """Weights of the search-range predictor (bf16 matrices, f32 vectors)."""
+    w1_bf16: torch.Tensor
+    b1: torch.Tensor
+    w2_bf16: torch.Tensor
+    b2: torch.Tensor
+    mean: torch.Tensor
+    std: torch.Tensor
+    shift: torch.Tensor | None = None
+    head: int = 0
+    head_per_query: torch.Tensor | None = None
+    eps_min: float = 0.0
+    eps_max: float = 0.5
+    e0: float = 30.0
+    we: float = -1.0
+
+    def struct(self):
+        return L.Predictor_t(self.w1_bf16.data_ptr(), self.b1.data_ptr(), self.w2_bf16.data_ptr(),
+                             self.b2.data_ptr(), self.mean.data_ptr(), self.std.data_ptr(),
+                             _ptr(self.shift), _ptr(self.head_per_query), self.head, L.NFEAT,
+                             self.b1.numel(), self.b2.numel(), self.eps_min, self.eps_max,
+                             self.e0, self.we)
+
+
+def launch_config(waves_per_block=0, lanes_per_row=0, s_capacity=0, visited_log2=0,
+                  pool_capacity=0, blocks=0):
+    return L.LaunchConfig_t(waves_per_block, lanes_per_row, s_capacity, visited_log2,
+                            pool_capacity, blocks)
+
+
+class SearchRequest:
+    """Holds the C parameter block and every buffer it points to."""
+
+    def __init__(self, base: Vectors, graph: Graph, queries: Vectors, seeds: torch.Tensor, k=10,
+                 k_stride=None, eps=0.0, ep=L.EP_INF, two_phase=False, ep_first=L.EP_INF,
+                 predictor: Predictor | None = None, want_features=False,
+                 rerank_base: Vectors | None = None, pool_factor=4, launch=None):
+        dev = queries.data.device
+        nq = queries.n
+        self.base, self.graph, self.queries = base, graph, queries
+        self.seeds = seeds.contiguous()
+        self._keep = []
+        kq = None
+        if torch.is_tensor(k):
+            kq = k.to(device=dev, dtype=torch.int32).contiguous()
+            kmax = int(kq.max()) if nq else 1
+            k = kmax
+        self.k_stride = k_stride or int(k)
+        epsq = None
+        if torch.is_tensor(eps):
+            epsq = eps.to(device=dev, dtype=torch.float32).contiguous()
+            eps = 0.0
+        epq = None
+        if torch.is_tensor(ep):
+            epq = ep.to(device=dev, dtype=torch.int64).to(torch.int32).contiguous()
+            ep = 1
+        self._keep += [kq, epsq, epq]
+        self.predictor = predictor
+        self._pred_s = predictor.struct() if predictor else None
+        self.features = (torch.zeros((nq, L.NFEAT), dtype=torch.float32, device=dev)
+                         if want_features else None)
+        self.rerank_base = rerank_base
+        self._launch = launch
+        self.params = L.SearchParams_t(
+            int(k), self.k_stride, _ptr(kq), float(eps), _ptr(epsq), int(ep) & 0xFFFFFFFF,
+            _ptr(epq), int(two_phase), int(ep_first) & 0xFFFFFFFF,
+            C.cast(C.byref(self._pred_s), C.c_void_p) if predictor else None,
+            _ptr(self.features),
+            C.cast(rerank_base.ref, C.c_void_p) if rerank_base else None,
+            int(pool_factor), C.cast(C.byref(launch), C.c_void_p) if launch is not None else None)
+        self.gs = graph.struct()
+        out_dt = torch.float32 if rerank_base is not None else base.dist_dtype
+        self.ids = torch.empty((nq, self.k_stride), dtype=torch.int32, device=dev)
+        self.dists = torch.empty((nq, self.k_stride), dtype=out_dt, device=dev)
+        self.stats = torch.empty((nq, 8), dtype=torch.int32, device=dev)
+        self.ws_bytes = L.load().onng_search_workspace_size(base.ref, nq, C.byref(self.params))
+        if self.ws_bytes == 0:
+            raise L.OnngError("onng_search_workspace_size", L.ERR_INVALID_ARG,
+                              L.load().onng_last_error().decode())
+        self.ws = _workspace(self.ws_bytes, dev)
+
+    def run(self):
+        L.call("onng_search", self.base.ref, C.byref(self.gs), self.queries.ref,
+               self.seeds.data_ptr(), self.seeds.shape[1], C.byref(self.params),
+               self.ids.data_ptr(), self.dists.data_ptr(), self.stats.data_ptr(),
+               self.ws.data_ptr(), self.ws.numel(), _stream())
+        return self
+
+    def autotune(self):
+        best = L.LaunchConfig_t()
+        L.call("onng_autotune_search", self.base.ref, C.byref(self.gs), self.queries.ref,
+               self.seeds.data_ptr(), self.seeds.shape[1], C.byref(self.params),
+               self.ids.data_ptr(), self.dists.data_ptr(), self.stats.data_ptr(),
+               self.ws.data_ptr(), self.ws.numel(), _stream(), C.byref(best))
+        # the tuned shape may need a different workspace
+        self.ws_bytes = L.load().onng_search_workspace_size(self.base.ref, self.queries.n,
+                                                            C.byref(self.params))
+        if self.ws_bytes > self.ws.numel():
+            self.ws = _workspace(self.ws_bytes, self.ws.device)
+        return best
+
+    @property
+    def dc(self):
+        return self.stats[:, 0]
+
+    @property
+    def hops(self):
+        return self.stats[:, 1]
+
+    @property
+    def flags(self):
+        return self.stats[:, 2]
+
+    @property
+    def ep_used(self):
+        return self.stats[:, 3].to(torch.int64) & 0xFFFFFFFF
+
+    @property
+    def eps_used(self):
+        return self.stats[:, 4].view(torch.float32)
+
+
+def search(base, graph, queries, seeds, **kw) -> SearchRequest:
+    return SearchRequest(base, graph, queries, seeds, **kw).run()
+
+
+# ------------------------------------------------------ codecs and rerank --
+
+def encode(x: torch.Tensor, dtype: int, metric: int, pitch: int | None = None) -> Vectors:
+    """f32 rows -> stored rows of `dtype` (Vectors with uint8 storage)."""
+    x = x.contiguous().to(torch.float32)
+    n, dim = x.shape
+    pitch = pitch or row_pitch(dim, dtype)
+    out = torch.empty((n, pitch), dtype=torch.uint8, device=x.device)
+    scale = torch.empty(n, dtype=torch.float32, device=x.device) if dtype == L.FP8_E4M3 else None
+    L.call("onng_encode", x.data_ptr(), n, dim, dtype, out.data_ptr(), pitch, _ptr(scale),
+           _stream())
+    return Vectors(out, dtype, metric, dim, scale)
+
+
+def rerank(queries: Vectors, base: Vectors, pool: torch.Tensor, k: int, use_f64=False):
+    pool = pool.contiguous().to(torch.int32)
+    nq, psz = pool.shape
+    ids = torch.empty((nq, k), dtype=torch.int32, device=pool.device)
+    d = torch.empty((nq, k), dtype=torch.float64 if use_f64 else torch.float32,
+                    device=pool.device)
+    L.call("onng_rerank", queries.ref, base.ref, pool.data_ptr(), psz, k, int(use_f64),
+           ids.data_ptr(), d.data_ptr(), _stream())
+    return ids, d
+
+
+def ground_truth(queries: Vectors, base: Vectors, k: int, screen: int = 64):
+    """Exact top-k: u8 directly; float by f32 screening of k+screen, then f64."""
+    if base.dtype == L.U8:
+        return topk(queries, base, k)
+    kk = min(k + screen, 256, base.n)
+    pool, _ = topk(queries, base, kk)
+    return rerank(queries, base, pool, k, use_f64=True)
+
+
+# -------------------------------------------------------------------- MLP --
+
+def mlp_forward(X, W1, b1, W2, b2, want_hidden=False):
+    B, F = X.shape
+    H, T = W1.shape[0], W2.shape[0]
+    Y = torch.empty((B, T), dtype=torch.float32, device=X.device)
+    hid = torch.empty((B, H), dtype=torch.float32, device=X.device) if want_hidden else None
+    L.call("onng_mlp_forward", X.data_ptr(), B, F, W1.data_ptr(), b1.data_ptr(), H,
+           W2.data_ptr(), b2.data_ptr(), T, _ptr(hid), Y.data_ptr(), _stream())
+    return (Y, hid) if want_hidden else Y
+
+
+def mlp_backward(X, target, W1, b1, W2, b2, w=None):
+    B, F = X.shape
+    H, T = W1.shape[0], W2.shape[0]
+    g = [torch.empty_like(t) for t in (W1, b1, W2, b2)]
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    ws = _workspace(L.load().onng_mlp_backward_workspace_size(B, H, T), X.device)
+    L.call("onng_mlp_backward", X.data_ptr(), target.data_ptr(), _ptr(w), B, F, W1.data_ptr(),
+           b1.data_ptr(), H, W2.data_ptr(), b2.data_ptr(), T, *[t.data_ptr() for t in g],
+           loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    return loss, g
+
+
+def adam_step(p, g, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+    L.call("onng_adam_step", p.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), p.numel(),
+           lr, beta1, beta2, eps, t, _stream())
+
+
+def feature_transform(raw: torch.Tensor, metric: int) -> torch.Tensor:
+    out = torch.empty_like(raw)
+    L.call("onng_feature_transform", raw.data_ptr(), raw.shape[0], metric, out.data_ptr(),
+           _stream())
+    return out
+
+
+def to_bf16_bits(w: torch.Tensor) -> torch.Tensor:
+    """f32 weights -> bf16 bit patterns (round to nearest even) via onng_encode."""
+    flat = w.reshape(1, -1).contiguous().to(torch.float32)
+    v = encode(flat, L.BF16, L.L2SQ, pitch=row_pitch(flat.shape[1], L.BF16))
+    return v.data.view(torch.int16)[0, :flat.shape[1]].contiguous().view(w.shape)
+
+
+# --------------------------------------------------------------- pipeline --
+
+class Pipeline:
+    """Seeding (nearest pivots) + search (+ predictor, + rerank) captured once
+    into a HIP graph and replayed."""
+
+    def __init__(self, base: Vectors, graph: Graph, queries: Vectors, pivots: torch.Tensor,
+                 n_seeds: int, seed_base: Vectors | None = None, **kw):
+        dev = queries.data.device
+        self.seeds = torch.empty((queries.n, n_seeds), dtype=torch.int32, device=dev)
+        self.req = SearchRequest(base, graph, queries, self.seeds, **kw)
+        self.pivots = pivots.contiguous()
+        n_bytes = L.load().onng_pipeline_workspace_size(base.ref, queries.ref,
+                                                        self.pivots.numel(), n_seeds,
+                                                        C.byref(self.req.params))
+        if n_bytes == 0:
+            raise L.OnngError("onng_pipeline_workspace_size", L.ERR_INVALID_ARG,
+                              L.load().onng_last_error().decode())
+        self.ws = _workspace(n_bytes, dev)
+        self.stream = torch.cuda.Stream(device=dev)
+        self.handle = C.c_void_p()
+        torch.cuda.synchronize()
+        L.call("onng_pipeline_create", base.ref, C.byref(self.req.gs), queries.ref,
+               self.pivots.data_ptr(), self.pivots.numel(), n_seeds, self.seeds.data_ptr(),
+               C.byref(self.req.params), self.req.ids.data_ptr(), self.req.dists.data_ptr(),
+               self.req.stats.data_ptr(), self.ws.data_ptr(), self.ws.numel(),
+               self.stream.cuda_stream, C.byref(self.handle))
+
+    def launch(self):
+        L.call("onng_pipeline_launch", self.handle, _stream())
+        return self.req
+
+    def close(self):
+        if self.handle:
+            L.load().onng_pipeline_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

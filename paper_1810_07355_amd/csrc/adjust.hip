@@ -1,0 +1,436 @@
+// Graph adjustment on the GPU:
+//   static degree adjustment, ConstructAdjustedGraph (Algorithm 2), and
+//   path adjustment, AdjustPath with HasPath (Algorithms 4 and 5).
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <type_traits>
+#include <cstdint>
+#include <vector>
+
+#include "onng_internal.h"
+#include "wave.h"
+
+namespace onng {
+
+namespace {
+
+template <typename LenT>
+__device__ __forceinline__ uint32_t len_ord(LenT v) {
+    if constexpr (std::is_integral<LenT>::value) return (uint32_t)v;   // int32 lengths
+    else return ord_f32((float)v);
+}
+
+// ------------------------------------------------------------ Algorithm 2 --
+// Row o of the kNN table gives, in order, the edges S of Algorithm 2.  With the
+// loop guard "p <= e_o or p <= e_i", step p of node o adds o -> n (p <= e_o) and
+// n -> o (p <= e_i).  As sets: N(o) = F(o) u Rv(o), F(o) = first e_o of row o,
+// Rv(o) = {m : o among the first e_i of row m}.  An edge present in both
+// ways is inserted once, by whichever step comes first in the loop (node
+// ascending, then p): the reverse copy when the far end has the smaller id,
+// and it keeps that copy's length.
+
+__device__ __forceinline__ int row_len(const int32_t *row, int k) {
+    int l = 0;
+    while (l < k && row[l] >= 0) l++;
+    return l;
+}
+
+// position of `x` among the first `lim` ids of `row`, or -1
+__device__ __forceinline__ int find_in(const int32_t *row, int lim, int32_t x) {
+    for (int t = 0; t < lim; t++)
+        if (row[t] == x) return t;
+    return -1;
+}
+
+__global__ void sa_count_kernel(const int32_t *knn, int64_t n, int k, int eo, int ei,
+                                int64_t *count) {
+    int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const int32_t *row = knn + m * k;
+    int len = row_len(row, k);
+    atomicAdd((unsigned long long *)&count[m], (unsigned long long)min(eo, len));
+    int lim = min(ei, len);
+    for (int t = 0; t < lim; t++) {
+        int32_t o = row[t];
+        if (o >= n) continue;
+        const int32_t *orow = knn + (int64_t)o * k;
+        int olen = row_len(orow, k);
+        // reverse edge o -> m, unless m is already a forward edge of o
+        if (find_in(orow, min(eo, olen), (int32_t)m) < 0)
+            atomicAdd((unsigned long long *)&count[o], 1ull);
+    }
+}
+
+template <typename LenT>
+__global__ void sa_scatter_kernel(const int32_t *knn, const LenT *kd, int64_t n, int k, int eo,
+                                  int ei, const int64_t *off, int32_t *cursor, uint64_t *keys) {
+    int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const int32_t *row = knn + m * k;
+    int len = row_len(row, k);
+    // forward edges of m
+    int fwd = min(eo, len);
+    for (int t = 0; t < fwd; t++) {
+        int32_t nn = row[t];
+        LenT l = kd[m * k + t];
+        if (nn < m && nn < n) {
+            // also a reverse edge inserted earlier (while processing nn)?
+            const int32_t *nrow = knn + (int64_t)nn * k;
+            int pos = find_in(nrow, min(ei, row_len(nrow, k)), (int32_t)m);
+            if (pos >= 0) l = kd[(int64_t)nn * k + pos];
+        }
+        keys[off[m] + t] = make_key(len_ord(l), (uint32_t)nn);
+    }
+    // reverse edges o -> m
+    int lim = min(ei, len);
+    for (int t = 0; t < lim; t++) {
+        int32_t o = row[t];
+        if (o >= n) continue;
+        const int32_t *orow = knn + (int64_t)o * k;
+        int olen = row_len(orow, k);
+        if (find_in(orow, min(eo, olen), (int32_t)m) >= 0) continue;   // forward edge of o
+        int ofwd = min(eo, olen);
+        int slot = atomicAdd(&cursor[o], 1);
+        keys[off[o] + ofwd + slot] = make_key(len_ord(kd[m * k + t]), (uint32_t)m);
+    }
+}
+
+// Sort each list by (length, id): rank of every key among the keys of its list.
+template <typename LenT>
+__global__ void __launch_bounds__(256) segment_rank_sort_kernel(const int64_t *off, int64_t n,
+                                                                const uint64_t *keys,
+                                                                int32_t *nbrs, LenT *lens) {
+    extern __shared__ uint64_t sk[];
+    int64_t v = blockIdx.x;
+    if (v >= n) return;
+    int64_t b = off[v], e = off[v + 1];
+    int m = (int)(e - b);
+    const int cap = 4096;
+    const uint64_t *src = keys + b;
+    if (m <= cap) {
+        for (int i = threadIdx.x; i < m; i += blockDim.x) sk[i] = src[i];
+        __syncthreads();
+        src = sk;
+    }
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        uint64_t x = src[i];
+        int rank = 0;
+        for (int j = 0; j < m; j++) rank += src[j] < x;
+        nbrs[b + rank] = (int32_t)(uint32_t)x;
+        uint32_t lo = (uint32_t)(x >> 32);
+        if constexpr (std::is_integral<LenT>::value) lens[b + rank] = (LenT)lo;
+        else lens[b + rank] = unord_f32(lo);
+    }
+}
+
+// --------------------------------------------------------- Algorithms 4/5 --
+// Round j visits every node with more than j edges.  Node n's j-th edge
+// n -> nd (length L) is removed when HasPath finds c in N(G_p, n) with
+// nd in N(G_p, c) and len(c, nd) < L.  In Algorithm 4 nodes are visited in
+// ascending id and G_p changes immediately, so G_p at n's turn is the graph
+// at the start of round j plus the round-j edges kept by nodes c < n.  The
+// GPU evaluates the start-of-round graph for all nodes at once (Jacobi
+// kernel), then settles the remaining dependence — a node c < n in
+// N(G_p, n) whose own round-j edge also goes to nd, is shorter than L and was
+// kept — by repeated passes in which a node is decided as soon as all such
+// c are (the smallest undecided node always is).
+
+constexpr int8_t ST_UNDECIDED = 0, ST_KEPT = 1, ST_REMOVED = 2;
+
+template <typename LenT>
+__global__ void pa_jacobi_kernel(const int64_t *off, const int32_t *nbrs, const LenT *lens,
+                                 const int32_t *active, int64_t n_active, int j,
+                                 const int32_t *gp_nb, const LenT *gp_len, const int32_t *gp_cnt,
+                                 int8_t *status) {
+    int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    int lane = lane_id();
+    if (w >= n_active) return;
+    int32_t v = active[w];
+    int64_t e = off[v] + j;
+    int32_t nd = nbrs[e];
+    LenT L = lens[e];
+    int cn = gp_cnt[v];
+    bool found = false;
+    for (int c0 = 0; c0 < cn && !found; c0 += WAVE) {
+        bool hit = false;
+        if (c0 + lane < cn) {
+            int32_t c = gp_nb[off[v] + c0 + lane];
+            int64_t cb = off[c];
+            int cc = gp_cnt[c];
+            for (int t = 0; t < cc; t++) {
+                if (!(gp_len[cb + t] < L)) break;
+                if (gp_nb[cb + t] == nd) { hit = true; break; }
+            }
+        }
+        found = ballot(hit) != 0;
+    }
+    if (lane == 0) status[v] = found ? ST_REMOVED : ST_UNDECIDED;
+}
+
+template <typename LenT>
+__global__ void pa_settle_kernel(const int64_t *off, const int32_t *nbrs, const LenT *lens,
+                                 const int32_t *active, int64_t n_active, int j,
+                                 const int32_t *gp_nb, const int32_t *gp_cnt, int8_t *status,
+                                 int32_t *undecided) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_active) return;
+    int32_t v = active[i];
+    if (status[v] != ST_UNDECIDED) return;
+    int64_t e = off[v] + j;
+    int32_t nd = nbrs[e];
+    LenT L = lens[e];
+    int cn = gp_cnt[v];
+    bool kept_witness = false, pending = false;
+    for (int t = 0; t < cn; t++) {
+        int32_t c = gp_nb[off[v] + t];
+        if (c >= v) continue;
+        int64_t cdeg = off[c + 1] - off[c];
+        if (cdeg <= j) continue;
+        int64_t ce = off[c] + j;
+        if (nbrs[ce] != nd || !(lens[ce] < L)) continue;
+        int8_t sc = __atomic_load_n(&status[c], __ATOMIC_RELAXED);
+        if (sc == ST_KEPT) { kept_witness = true; break; }
+        if (sc == ST_UNDECIDED) pending = true;
+    }
+    if (kept_witness) status[v] = ST_REMOVED;
+    else if (!pending) status[v] = ST_KEPT;
+    else atomicAdd(undecided, 1);
+}
+
+template <typename LenT>
+__global__ void pa_apply_kernel(const int64_t *off, const int32_t *nbrs, const LenT *lens,
+                                const int32_t *active, int64_t n_active, int j,
+                                int32_t *gp_nb, LenT *gp_len, int32_t *gp_cnt,
+                                const int8_t *status) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_active) return;
+    int32_t v = active[i];
+    if (status[v] != ST_KEPT) return;
+    int64_t e = off[v] + j;
+    int c = gp_cnt[v];
+    gp_nb[off[v] + c] = nbrs[e];
+    gp_len[off[v] + c] = lens[e];
+    gp_cnt[v] = c + 1;
+}
+
+__global__ void degree_hist_kernel(const int64_t *off, int64_t n, int32_t *deg,
+                                   unsigned long long *hist) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int64_t d64 = off[v + 1] - off[v];
+    int d = d64 < (1 << 20) - 1 ? (int)d64 : (1 << 20) - 1;   // last bin flags overflow
+    deg[v] = d;
+    atomicAdd(&hist[d], 1ull);
+}
+
+// nodes by degree, descending: position = (#nodes with larger degree) + slot
+__global__ void order_by_degree_kernel(const int32_t *deg, int64_t n, const int64_t *start,
+                                       int32_t *cursor, int32_t *order) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int d = deg[v];
+    int slot = atomicAdd(&cursor[d], 1);
+    order[start[d] + slot] = (int32_t)v;
+}
+
+template <typename LenT>
+__global__ void pa_compact_kernel(const int64_t *off, const int64_t *out_off, int64_t n,
+                                  const int32_t *gp_nb, const LenT *gp_len,
+                                  int32_t *out_nb, LenT *out_len) {
+    int64_t v = blockIdx.x;
+    if (v >= n) return;
+    int64_t b = off[v], ob = out_off[v], m = out_off[v + 1] - ob;
+    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) {
+        out_nb[ob + t] = gp_nb[b + t];
+        out_len[ob + t] = gp_len[b + t];
+    }
+}
+
+__global__ void cnt_to_i64_kernel(const int32_t *c, int64_t n, int64_t *o) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) o[v] = c[v];
+    if (v == n) o[n] = 0;
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+size_t scan_temp_bytes(int64_t n) {
+    size_t bytes = 0;
+    hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, (int64_t *)nullptr, (int64_t *)nullptr,
+                                     (int)n);
+    return bytes;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- host side --
+
+size_t adjust_degree_ws(int64_t n, int32_t k, int32_t e_o, int32_t e_i) {
+    int64_t cap = n * (int64_t)(std::min(e_o, k) + std::min(e_i, k));
+    Carver c(nullptr);
+    c.take<int64_t>(n + 1);            // counts / offsets
+    c.take<int32_t>(n);                // cursors
+    c.take<uint64_t>(cap);             // keys
+    c.take<char>(scan_temp_bytes(n + 1));
+    return c.size() + 256;
+}
+
+template <typename LenT>
+static onng_status adjust_degree_impl(const int32_t *knn, const LenT *kd, int64_t n, int32_t k,
+                                      int32_t e_o, int32_t e_i, int64_t *offsets, int32_t *nbrs,
+                                      LenT *lens, int64_t nnz_cap, int64_t *nnz_out, void *ws,
+                                      hipStream_t st) {
+    int eo = std::min(e_o, k), ei = std::min(e_i, k);
+    int64_t cap = n * (int64_t)(eo + ei);
+    Carver c(ws);
+    int64_t *cnt = c.take<int64_t>(n + 1);
+    int32_t *cursor = c.take<int32_t>(n);
+    uint64_t *keys = c.take<uint64_t>(cap);
+    size_t tb = scan_temp_bytes(n + 1);
+    void *tmp = c.take<char>(tb);
+    ONNG_HIP(hipMemsetAsync(cnt, 0, sizeof(int64_t) * (n + 1), st));
+    ONNG_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * n, st));
+    hipLaunchKernelGGL(sa_count_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, knn, n, k, eo,
+                       ei, cnt);
+    ONNG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt, offsets, (int)(n + 1), st));
+    ONNG_HIP(hipMemcpyAsync(nnz_out, offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    ONNG_HIP(hipStreamSynchronize(st));
+    if (*nnz_out > nnz_cap) {
+        set_error("onng_adjust_degree: nnz_capacity too small");
+        return ONNG_ERR_CAPACITY;
+    }
+    hipLaunchKernelGGL((sa_scatter_kernel<LenT>), dim3(blocks_for(n, 256)), dim3(256), 0, st, knn,
+                       kd, n, k, eo, ei, offsets, cursor, keys);
+    if (n > 0)
+        hipLaunchKernelGGL((segment_rank_sort_kernel<LenT>), dim3((unsigned)n), dim3(256),
+                           4096 * sizeof(uint64_t), st, offsets, n, keys, nbrs, lens);
+    ONNG_HIP(hipGetLastError());
+    ONNG_HIP(hipStreamSynchronize(st));
+    return ONNG_OK;
+}
+
+onng_status adjust_degree_launch(const int32_t *knn, const void *kd, int64_t n, int32_t k,
+                                 bool int_len, int32_t e_o, int32_t e_i, int64_t *offsets,
+                                 int32_t *nbrs, void *lens, int64_t nnz_cap, int64_t *nnz_out,
+                                 void *ws, hipStream_t st) {
+    if (int_len)
+        return adjust_degree_impl<int32_t>(knn, static_cast<const int32_t *>(kd), n, k, e_o, e_i,
+                                           offsets, nbrs, static_cast<int32_t *>(lens), nnz_cap,
+                                           nnz_out, ws, st);
+    return adjust_degree_impl<float>(knn, static_cast<const float *>(kd), n, k, e_o, e_i, offsets,
+                                     nbrs, static_cast<float *>(lens), nnz_cap, nnz_out, ws, st);
+}
+
+size_t adjust_path_ws(int64_t n, int64_t nnz) {
+    Carver c(nullptr);
+    c.take<int32_t>(nnz);          // gp_nb
+    c.take<int32_t>(nnz);          // gp_len (4-byte lengths)
+    c.take<int32_t>(n);            // gp_cnt
+    c.take<int8_t>(n);             // status
+    c.take<int32_t>(n);            // degrees
+    c.take<int32_t>(n);            // order
+    c.take<int32_t>(4);            // undecided counter
+    c.take<unsigned long long>(1 << 20);   // degree histogram (max degree < 2^20)
+    c.take<int64_t>(1 << 20);      // start per degree
+    c.take<int32_t>(1 << 20);      // cursor per degree
+    c.take<int64_t>(n + 1);        // out counts
+    c.take<char>(scan_temp_bytes(n + 1));
+    return c.size() + 256;
+}
+
+template <typename LenT>
+static onng_status adjust_path_impl(const onng_graph *g, int64_t *out_off, int32_t *out_nb,
+                                    LenT *out_len, int64_t *nnz_out, void *ws, hipStream_t st) {
+    const int64_t n = g->n, nnz = g->nnz;
+    const LenT *lens = static_cast<const LenT *>(g->lens);
+    constexpr int MAXD = 1 << 20;
+    Carver c(ws);
+    int32_t *gp_nb = c.take<int32_t>(nnz);
+    LenT *gp_len = reinterpret_cast<LenT *>(c.take<int32_t>(nnz));
+    int32_t *gp_cnt = c.take<int32_t>(n);
+    int8_t *status = c.take<int8_t>(n);
+    int32_t *deg = c.take<int32_t>(n);
+    int32_t *order = c.take<int32_t>(n);
+    int32_t *undecided = c.take<int32_t>(4);
+    unsigned long long *hist = c.take<unsigned long long>(MAXD);
+    int64_t *start = c.take<int64_t>(MAXD);
+    int32_t *cursor = c.take<int32_t>(MAXD);
+    int64_t *ocnt = c.take<int64_t>(n + 1);
+    size_t tb = scan_temp_bytes(n + 1);
+    void *tmp = c.take<char>(tb);
+
+    ONNG_HIP(hipMemsetAsync(gp_cnt, 0, sizeof(int32_t) * n, st));
+    ONNG_HIP(hipMemsetAsync(hist, 0, sizeof(unsigned long long) * MAXD, st));
+    ONNG_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * MAXD, st));
+    hipLaunchKernelGGL(degree_hist_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, g->offsets,
+                       n, deg, hist);
+    std::vector<unsigned long long> h(MAXD);
+    ONNG_HIP(hipMemcpyAsync(h.data(), hist, sizeof(unsigned long long) * MAXD,
+                            hipMemcpyDeviceToHost, st));
+    ONNG_HIP(hipStreamSynchronize(st));
+    if (h[MAXD - 1]) {
+        set_error("onng_adjust_path: a node has 2^20 - 1 or more edges");
+        return ONNG_ERR_UNSUPPORTED;
+    }
+    int maxdeg = 0;
+    for (int d = 0; d < MAXD; d++)
+        if (h[d]) maxdeg = d;
+    // start[d] = number of nodes with degree > d; active(j) = start[j] nodes
+    std::vector<int64_t> s(MAXD, 0);
+    int64_t acc = 0;
+    for (int d = maxdeg; d >= 0; d--) {
+        s[d] = acc;
+        acc += (int64_t)h[d];
+    }
+    ONNG_HIP(hipMemcpyAsync(start, s.data(), sizeof(int64_t) * (maxdeg + 1), hipMemcpyHostToDevice,
+                            st));
+    hipLaunchKernelGGL(order_by_degree_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, deg, n,
+                       start, cursor, order);
+    for (int j = 0; j < maxdeg; j++) {
+        int64_t n_act = s[j];    // nodes with degree > j
+        if (n_act == 0) break;
+        hipLaunchKernelGGL((pa_jacobi_kernel<LenT>), dim3(blocks_for(n_act * WAVE, 256)),
+                           dim3(256), 0, st, g->offsets, g->nbrs, lens, order, n_act, j, gp_nb,
+                           gp_len, gp_cnt, status);
+        for (int it = 0;; it++) {
+            ONNG_HIP(hipMemsetAsync(undecided, 0, sizeof(int32_t), st));
+            hipLaunchKernelGGL((pa_settle_kernel<LenT>), dim3(blocks_for(n_act, 256)), dim3(256),
+                               0, st, g->offsets, g->nbrs, lens, order, n_act, j, gp_nb, gp_cnt,
+                               status, undecided);
+            int32_t und = 0;
+            ONNG_HIP(hipMemcpyAsync(&und, undecided, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            ONNG_HIP(hipStreamSynchronize(st));
+            if (und == 0) break;
+            if (it > n_act + 2) {
+                set_error("onng_adjust_path: same-round dependences did not settle");
+                return ONNG_ERR_DEVICE;
+            }
+        }
+        hipLaunchKernelGGL((pa_apply_kernel<LenT>), dim3(blocks_for(n_act, 256)), dim3(256), 0, st,
+                           g->offsets, g->nbrs, lens, order, n_act, j, gp_nb, gp_len, gp_cnt,
+                           status);
+    }
+    hipLaunchKernelGGL(cnt_to_i64_kernel, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st, gp_cnt,
+                       n, ocnt);
+    ONNG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, ocnt, out_off, (int)(n + 1), st));
+    if (n > 0)
+        hipLaunchKernelGGL((pa_compact_kernel<LenT>), dim3((unsigned)n), dim3(64), 0, st,
+                           g->offsets, out_off, n, gp_nb, gp_len, out_nb, out_len);
+    ONNG_HIP(hipGetLastError());
+    ONNG_HIP(hipMemcpyAsync(nnz_out, out_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    ONNG_HIP(hipStreamSynchronize(st));
+    return ONNG_OK;
+}
+
+onng_status adjust_path_launch(const onng_graph *g, bool int_len, int64_t *offsets,
+                               int32_t *nbrs, void *lens, int64_t *nnz_out, void *ws,
+                               hipStream_t st) {
+    if (int_len)
+        return adjust_path_impl<int32_t>(g, offsets, nbrs, static_cast<int32_t *>(lens), nnz_out,
+                                         ws, st);
+    return adjust_path_impl<float>(g, offsets, nbrs, static_cast<float *>(lens), nnz_out, ws, st);
+}
+
+}  // namespace onng

@@ -1,0 +1,738 @@
+// C-ABI entry points: argument validation, launch shapes, workspace layout,
+// launch tuning and graph capture.  Kernels live in the other sources.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "onng_internal.h"
+#include "search_args.h"
+
+namespace onng {
+
+// kernels implemented elsewhere
+onng_status adjust_degree_launch(const int32_t *knn, const void *kd, int64_t n, int32_t k,
+                                 bool int_len, int32_t e_o, int32_t e_i, int64_t *offsets,
+                                 int32_t *nbrs, void *lens, int64_t nnz_cap, int64_t *nnz_out,
+                                 void *ws, hipStream_t st);
+size_t adjust_degree_ws(int64_t n, int32_t k, int32_t e_o, int32_t e_i);
+onng_status adjust_path_launch(const onng_graph *g, bool int_len, int64_t *offsets,
+                               int32_t *nbrs, void *lens, int64_t *nnz_out, void *ws,
+                               hipStream_t st);
+size_t adjust_path_ws(int64_t n, int64_t nnz);
+onng_status encode_launch(const float *src, int64_t n, int32_t dim, int32_t dtype, void *dst,
+                          int64_t pitch, float *scale, hipStream_t st);
+onng_status rerank_launch(const onng_vectors *Q, const onng_vectors *B, const int32_t *pool,
+                          int32_t psz, int32_t k, int32_t use_f64, int32_t *ids, void *dists,
+                          hipStream_t st);
+size_t mlp_backward_ws(int32_t batch, int32_t H, int32_t T);
+onng_status mlp_forward_launch(const float *X, int32_t batch, int32_t F, const float *W1,
+                               const float *b1, int32_t H, const float *W2, const float *b2,
+                               int32_t T, float *hidden, float *Y, hipStream_t st);
+onng_status mlp_backward_launch(const float *X, const float *target, const float *w,
+                                int32_t batch, int32_t F, const float *W1, const float *b1,
+                                int32_t H, const float *W2, const float *b2, int32_t T,
+                                float *gW1, float *gb1, float *gW2, float *gb2, float *loss,
+                                void *ws, hipStream_t st);
+onng_status adam_launch(float *p, const float *g, float *m, float *v, int64_t n, float lr,
+                        float b1, float b2, float eps, int32_t t, hipStream_t st);
+onng_status feature_transform_launch(const float *raw, int64_t n, int32_t metric, float *out,
+                                     hipStream_t st);
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+const char *get_error() { return g_err.c_str(); }
+
+int device_cu_count() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 256;
+    return cus > 0 ? cus : 256;
+}
+
+onng_status check_vectors(const onng_vectors *v, const char *what) {
+    std::string w(what);
+    if (!v) { set_error(w + " is null"); return ONNG_ERR_INVALID_ARG; }
+    if (v->n < 0 || v->dim <= 0) { set_error(w + ": bad n or dim"); return ONNG_ERR_INVALID_ARG; }
+    if (v->n > 0 && !v->data) { set_error(w + ": data is null"); return ONNG_ERR_INVALID_ARG; }
+    if (v->dtype < ONNG_U8 || v->dtype > ONNG_FP8_E4M3) {
+        set_error(w + ": unknown dtype");
+        return ONNG_ERR_INVALID_ARG;
+    }
+    if (v->metric != ONNG_L2SQ && v->metric != ONNG_COSINE) {
+        set_error(w + ": unknown metric");
+        return ONNG_ERR_INVALID_ARG;
+    }
+    if (v->pitch_bytes < (int64_t)v->dim * elem_bytes(v->dtype) || v->pitch_bytes % 16 != 0) {
+        set_error(w + ": pitch_bytes must be a multiple of 16 and hold dim elements");
+        return ONNG_ERR_INVALID_ARG;
+    }
+    if (reinterpret_cast<uintptr_t>(v->data) % 16 != 0) {
+        set_error(w + ": data must be 16-byte aligned");
+        return ONNG_ERR_INVALID_ARG;
+    }
+    if (v->dtype == ONNG_FP8_E4M3 && !v->scale && v->n > 0) {
+        set_error(w + ": FP8 rows need a scale array");
+        return ONNG_ERR_INVALID_ARG;
+    }
+    if (v->dtype == ONNG_U8 && v->metric != ONNG_L2SQ) {
+        set_error(w + ": u8 data supports squared L2 only");
+        return ONNG_ERR_UNSUPPORTED;
+    }
+    if (v->n > 0x7fffffffLL) { set_error(w + ": more than 2^31-1 rows"); return ONNG_ERR_UNSUPPORTED; }
+    return ONNG_OK;
+}
+
+#define ONNG_TRY(x)                        \
+    do {                                   \
+        onng_status s_ = (x);              \
+        if (s_ != ONNG_OK) return s_;      \
+    } while (0)
+
+// ------------------------------------------------------------- search -----
+
+struct SearchPlan {
+    const void *fn = nullptr;
+    int L = 8, s_cap = 256, vis_log2 = 11, pool_cap = 64, wpb = 4, blocks = 0;
+    int lds_per_wave = 0;
+    int off_pool, off_s, off_stage, off_stage2, off_ids, off_vis, off_misc;
+    int64_t gbits_words = 0;
+    int vlog_cap = 16384, spill_cap = 8192;
+    int slots = 0;
+    size_t ws = 0;
+};
+
+static int ppl_for(int dtype) { return dtype == ONNG_U8 ? 2 : dtype == ONNG_F32 ? 4 : 2; }
+
+static int align16(int x) { return (x + 15) / 16 * 16; }
+
+static onng_status make_plan(const onng_vectors *base, int64_t nq, const onng_search_params *p,
+                             const onng_launch_config *cfg, SearchPlan *plan) {
+    SearchPlan P;
+    P.fn = search_kernel_ptr(base->dtype, base->metric);
+    if (!P.fn) {
+        set_error("onng_search: unsupported dtype/metric");
+        return ONNG_ERR_UNSUPPORTED;
+    }
+    const int n16 = (int)(base->pitch_bytes / 16);
+    const int ppl = ppl_for(base->dtype);
+    int L = cfg && cfg->lanes_per_row ? cfg->lanes_per_row : 0;
+    if (!L) {
+        L = 4;
+        while (L < 64 && (n16 + L - 1) / L > std::min(ppl, 2)) L <<= 1;
+    }
+    if (L != 2 && L != 4 && L != 8 && L != 16 && L != 32 && L != 64) {
+        set_error("onng_search: lanes_per_row must be a power of two in [2, 64]");
+        return ONNG_ERR_INVALID_ARG;
+    }
+    if ((n16 + L - 1) / L > ppl) {
+        set_error("onng_search: row too wide for lanes_per_row (use more lanes per row)");
+        return ONNG_ERR_UNSUPPORTED;
+    }
+    P.L = L;
+    P.s_cap = cfg && cfg->s_capacity ? cfg->s_capacity : 256;
+    // the fused rerank collects its k best in the candidate array
+    if (p->rerank_base) P.s_cap = std::max(P.s_cap, (p->k_stride + 63) / 64 * 64);
+    P.vis_log2 = cfg && cfg->visited_log2 >= 0 && cfg->visited_log2 != 0 ? cfg->visited_log2 : 11;
+    if (cfg && cfg->visited_log2 < 0) P.vis_log2 = 0;   // negative: global bitset only
+    if (P.s_cap < 64 || P.s_cap % 64 || P.s_cap > 8192) {
+        set_error("onng_search: s_capacity must be a multiple of 64 in [64, 8192]");
+        return ONNG_ERR_INVALID_ARG;
+    }
+    if (P.vis_log2 != 0 && (P.vis_log2 < 8 || P.vis_log2 > 15)) {
+        set_error("onng_search: visited_log2 must be in [8, 15] (or negative for off-chip)");
+        return ONNG_ERR_INVALID_ARG;
+    }
+    int want_pool = p->k_stride;
+    if (p->rerank_base) want_pool = std::max(p->k_stride, p->pool_factor * p->k_stride);
+    if (cfg && cfg->pool_capacity) want_pool = std::max(want_pool, cfg->pool_capacity);
+    P.pool_cap = (want_pool + 63) / 64 * 64;
+    if (P.pool_cap > 1024) {
+        set_error("onng_search: pool (k_stride * pool_factor) above 1024");
+        return ONNG_ERR_UNSUPPORTED;
+    }
+    P.wpb = cfg && cfg->waves_per_block ? cfg->waves_per_block : 4;
+    if (P.wpb < 1 || P.wpb > 8) {
+        set_error("onng_search: waves_per_block must be in [1, 8]");
+        return ONNG_ERR_INVALID_ARG;
+    }
+    int o = 0;
+    P.off_pool = o; o = align16(o + P.pool_cap * 8);
+    P.off_s = o; o = align16(o + P.s_cap * 8);
+    P.off_stage = o; o = align16(o + 64 * 8);
+    P.off_stage2 = o; o = align16(o + 64 * 8);
+    P.off_ids = o; o = align16(o + 64 * 4);
+    P.off_vis = o; o = align16(o + (P.vis_log2 ? (4 << P.vis_log2) : 0));
+    P.off_misc = o; o = align16(o + 72 * 4);
+    P.lds_per_wave = o;
+    size_t lds = (size_t)o * P.wpb;
+    if (lds > 160 * 1024) {
+        set_error("onng_search: on-chip state above 160 KiB per block");
+        return ONNG_ERR_UNSUPPORTED;
+    }
+    if (hipFuncSetAttribute(P.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+        hipSuccess) {
+        set_error("onng_search: cannot set shared memory size");
+        return ONNG_ERR_DEVICE;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, P.fn, P.wpb * 64, lds) !=
+            hipSuccess ||
+        per_cu <= 0)
+        per_cu = 1;
+    int want = cfg && cfg->blocks ? cfg->blocks : per_cu * device_cu_count();
+    int need = (int)std::min<int64_t>((nq + P.wpb - 1) / P.wpb, 1 << 20);
+    P.blocks = std::max(1, std::min(want, std::max(need, 1)));
+    P.slots = P.blocks * P.wpb;
+    P.gbits_words = (base->n + 31) / 32;
+    Carver c(nullptr);
+    c.take<int32_t>(64);
+    c.take<uint32_t>((size_t)P.slots * P.gbits_words);
+    c.take<int32_t>((size_t)P.slots * P.vlog_cap);
+    c.take<uint64_t>((size_t)P.slots * 2 * P.spill_cap);
+    P.ws = c.size() + 256;
+    *plan = P;
+    return ONNG_OK;
+}
+
+static onng_status validate_search(const onng_vectors *base, const onng_graph *g,
+                                   const onng_vectors *queries, const int32_t *seeds,
+                                   int32_t n_seeds, const onng_search_params *p) {
+    ONNG_TRY(check_vectors(base, "base"));
+    ONNG_TRY(check_vectors(queries, "queries"));
+    ONNG_CHECK_ARG(p, "params is null");
+    ONNG_CHECK_ARG(g && g->offsets && (g->nbrs || g->nnz == 0), "graph is null");
+    ONNG_CHECK_ARG(g->n == base->n, "graph and base sizes differ");
+    ONNG_CHECK_ARG(queries->dim == base->dim, "query and base dims differ");
+    ONNG_CHECK_ARG(queries->metric == base->metric, "query and base metrics differ");
+    if (base->dtype == ONNG_U8) ONNG_CHECK_ARG(queries->dtype == ONNG_U8, "u8 base needs u8 queries");
+    else ONNG_CHECK_ARG(queries->dtype == ONNG_F32, "float base needs f32 queries");
+    ONNG_CHECK_ARG(base->n > 0, "empty base");
+    ONNG_CHECK_ARG(seeds || queries->n == 0, "seeds is null");
+    ONNG_CHECK_ARG(n_seeds >= 1 && n_seeds <= 64, "n_seeds must be in [1, 64]");
+    ONNG_CHECK_ARG(p->k_stride >= 1 && p->k_stride <= 256, "k_stride must be in [1, 256]");
+    ONNG_CHECK_ARG(p->k_per_query || (p->k >= 1 && p->k <= p->k_stride), "k must be in [1, k_stride]");
+    ONNG_CHECK_ARG(p->eps_per_query || p->epsilon >= 0.0f, "epsilon must be >= 0");
+    ONNG_CHECK_ARG(p->ep_per_query || p->e_p >= 1, "e_p must be >= 1");
+    if (p->rerank_base) {
+        ONNG_TRY(check_vectors(p->rerank_base, "rerank_base"));
+        ONNG_CHECK_ARG(base->dtype != ONNG_U8, "rerank needs float data");
+        ONNG_CHECK_ARG(p->rerank_base->dtype == ONNG_F32 && p->rerank_base->n == base->n &&
+                           p->rerank_base->dim == base->dim,
+                       "rerank_base must be f32 rows of the same objects");
+        ONNG_CHECK_ARG(p->pool_factor >= 1, "pool_factor must be >= 1");
+    }
+    if (p->predictor) {
+        const onng_predictor *pr = p->predictor;
+        ONNG_CHECK_ARG(p->two_phase, "a predictor needs two_phase");
+        ONNG_CHECK_ARG(pr->n_features == ONNG_NFEAT, "predictor n_features must be ONNG_NFEAT");
+        ONNG_CHECK_ARG(pr->hidden >= 1 && pr->hidden <= 64, "predictor hidden must be in [1, 64]");
+        ONNG_CHECK_ARG(pr->n_heads >= 1 && pr->n_heads <= 8, "predictor n_heads must be in [1, 8]");
+        ONNG_CHECK_ARG(pr->w1_bf16 && pr->b1 && pr->w2_bf16 && pr->b2 && pr->feat_mean && pr->feat_std,
+                       "predictor weights missing");
+        ONNG_CHECK_ARG(pr->head_per_query || (pr->head >= 0 && pr->head < pr->n_heads),
+                       "predictor head out of range");
+        ONNG_CHECK_ARG(pr->eps_min >= 0.0f && pr->eps_max >= pr->eps_min, "bad eps clamp");
+    }
+    if (p->two_phase) ONNG_CHECK_ARG(p->ep_first >= 1, "ep_first must be >= 1");
+    return ONNG_OK;
+}
+
+static onng_status run_search(const onng_vectors *base, const onng_graph *g,
+                              const onng_vectors *queries, const int32_t *seeds, int32_t n_seeds,
+                              const onng_search_params *p, int32_t *ids, void *dists,
+                              onng_query_stats *stats, void *ws, size_t ws_bytes, hipStream_t st,
+                              const onng_launch_config *cfg) {
+    ONNG_TRY(validate_search(base, g, queries, seeds, n_seeds, p));
+    ONNG_CHECK_ARG(ids && dists && stats, "outputs are null");
+    if (queries->n == 0) return ONNG_OK;
+    SearchPlan P;
+    ONNG_TRY(make_plan(base, queries->n, p, cfg, &P));
+    if (p->two_phase && (int64_t)p->ep_first + n_seeds > P.s_cap) {
+        set_error("onng_search: ep_first + n_seeds must fit the on-chip candidate set");
+        return ONNG_ERR_INVALID_ARG;
+    }
+    if (!ws || ws_bytes < P.ws) {
+        set_error("onng_search: workspace too small (" + std::to_string(P.ws) + " bytes needed)");
+        return ONNG_ERR_WORKSPACE;
+    }
+    Carver c(ws);
+    SearchKArgs a{};
+    a.counter = c.take<int32_t>(64);
+    a.gbits = c.take<uint32_t>((size_t)P.slots * P.gbits_words);
+    a.vlog = c.take<int32_t>((size_t)P.slots * P.vlog_cap);
+    a.spill = c.take<uint64_t>((size_t)P.slots * 2 * P.spill_cap);
+    a.base = static_cast<const uint8_t *>(base->data);
+    a.base_scale = base->scale;
+    a.base_pitch = base->pitch_bytes;
+    a.n_base = base->n;
+    a.dim = base->dim;
+    a.n16 = (int)(base->pitch_bytes / 16);
+    a.offsets = g->offsets;
+    a.nbrs = g->nbrs;
+    a.qry = static_cast<const uint8_t *>(queries->data);
+    a.q_pitch = queries->pitch_bytes;
+    a.nq = (int32_t)queries->n;
+    a.seeds = seeds;
+    a.n_seeds = n_seeds;
+    a.k = p->k;
+    a.k_pq = p->k_per_query;
+    a.k_stride = p->k_stride;
+    a.eps = p->epsilon;
+    a.eps_pq = p->eps_per_query;
+    a.ep = p->e_p;
+    a.ep_pq = p->ep_per_query;
+    a.two_phase = p->two_phase;
+    a.ep_first = p->ep_first;
+    a.has_pred = p->predictor != nullptr;
+    if (p->predictor) {
+        const onng_predictor *pr = p->predictor;
+        a.pred.w1 = pr->w1_bf16;
+        a.pred.b1 = pr->b1;
+        a.pred.w2 = pr->w2_bf16;
+        a.pred.b2 = pr->b2;
+        a.pred.mean = pr->feat_mean;
+        a.pred.stdv = pr->feat_std;
+        a.pred.shift = pr->shift;
+        a.pred.head_pq = pr->head_per_query;
+        a.pred.head = pr->head;
+        a.pred.F = pr->n_features;
+        a.pred.H = pr->hidden;
+        a.pred.T = pr->n_heads;
+        a.pred.eps_min = pr->eps_min;
+        a.pred.eps_max = pr->eps_max;
+        a.pred.e0 = pr->e0;
+        a.pred.we = pr->we;
+    }
+    a.feat_out = p->two_phase ? p->features_out : nullptr;
+    a.has_rr = p->rerank_base != nullptr;
+    if (a.has_rr) {
+        a.rr_base = static_cast<const uint8_t *>(p->rerank_base->data);
+        a.rr_pitch = p->rerank_base->pitch_bytes;
+        a.pool_factor = p->pool_factor;
+    }
+    a.out_ids = ids;
+    a.out_d = dists;
+    a.stats = stats;
+    a.gbits_words = P.gbits_words;
+    a.vlog_cap = P.vlog_cap;
+    a.spill_cap = P.spill_cap;
+    a.lanes_per_row = P.L;
+    a.s_cap = P.s_cap;
+    a.vis_log2 = P.vis_log2;
+    a.pool_cap = P.pool_cap;
+    a.waves_per_block = P.wpb;
+    a.lds_per_wave = P.lds_per_wave;
+    a.off_pool = P.off_pool;
+    a.off_s = P.off_s;
+    a.off_stage = P.off_stage;
+    a.off_stage2 = P.off_stage2;
+    a.off_ids = P.off_ids;
+    a.off_vis = P.off_vis;
+    a.off_misc = P.off_misc;
+    void *cargs[] = {&a.counter};
+    ONNG_HIP(hipLaunchKernel(reset_counter_kernel_ptr(), dim3(1), dim3(1), cargs, 0, st));
+    void *args[] = {&a};
+    ONNG_HIP(hipLaunchKernel(P.fn, dim3(P.blocks), dim3(P.wpb * 64), args,
+                             (size_t)P.lds_per_wave * P.wpb, st));
+    return ONNG_OK;
+}
+
+// ----------------------------------------------------------- autotune -----
+
+typedef std::tuple<int, int, int, int64_t, int, int, int> TuneKey;
+static std::mutex g_tune_mu;
+static std::map<TuneKey, onng_launch_config> g_tune;
+
+static bool lookup_tuned(const onng_vectors *base, const onng_search_params *p,
+                         onng_launch_config *out) {
+    TuneKey key{base->dtype, base->metric, base->dim, base->n, p->k_stride,
+                p->rerank_base ? p->pool_factor : 0, p->two_phase};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+}  // namespace onng
+
+using namespace onng;
+
+extern "C" {
+
+const char *onng_status_string(onng_status st) {
+    switch (st) {
+    case ONNG_OK: return "ok";
+    case ONNG_ERR_INVALID_ARG: return "invalid argument";
+    case ONNG_ERR_UNSUPPORTED: return "unsupported";
+    case ONNG_ERR_CAPACITY: return "capacity too small";
+    case ONNG_ERR_WORKSPACE: return "workspace too small";
+    case ONNG_ERR_DEVICE: return "device error";
+    }
+    return "unknown status";
+}
+
+const char *onng_last_error(void) { return get_error(); }
+
+int32_t onng_version(void) { return 10000; }
+
+// ------------------------------------------------------------- top-k ------
+
+size_t onng_topk_workspace_size(const onng_vectors *queries, const onng_vectors *base,
+                                int64_t n_cand, int32_t k) {
+    if (!queries || !base) return 0;
+    return topk_ws_size(queries, base, n_cand, k);
+}
+
+onng_status onng_topk(const onng_vectors *queries, const onng_vectors *base,
+                      const int32_t *cand, int64_t n_cand, int32_t k, int32_t exclude_self,
+                      int32_t *ids, void *dists, void *ws, size_t ws_bytes, void *stream) {
+    set_error("");
+    ONNG_TRY(check_vectors(queries, "queries"));
+    ONNG_TRY(check_vectors(base, "base"));
+    ONNG_CHECK_ARG(queries->dim == base->dim && queries->metric == base->metric,
+                   "queries and base differ in dim or metric");
+    ONNG_CHECK_ARG(k >= 1 && k <= 256, "k must be in [1, 256]");
+    ONNG_CHECK_ARG(!cand || n_cand >= 0, "bad n_cand");
+    ONNG_CHECK_ARG(ids && dists, "outputs are null");
+    ONNG_CHECK_ARG(ws, "workspace is null");
+    if (queries->dtype == ONNG_U8) ONNG_CHECK_ARG(queries->dim <= 512, "u8 dim above 512");
+    else ONNG_CHECK_ARG(queries->dim <= 256, "f32 dim above 256");
+    return launch_topk(queries, base, cand, cand ? n_cand : 0, k, exclude_self, ids, dists, ws,
+                       ws_bytes, as_stream(stream));
+}
+
+onng_status onng_build_knn(const onng_vectors *base, int32_t k, int32_t *ids, void *dists,
+                           void *ws, size_t ws_bytes, void *stream) {
+    set_error("");
+    ONNG_TRY(check_vectors(base, "base"));
+    ONNG_CHECK_ARG(k >= 1 && k <= base->n - 1, "k must be in [1, n-1]");
+    return onng_topk(base, base, nullptr, 0, k, 1, ids, dists, ws, ws_bytes, stream);
+}
+
+// ------------------------------------------------------- adjustments ------
+
+size_t onng_adjust_degree_workspace_size(int64_t n, int32_t k, int32_t e_o, int32_t e_i) {
+    if (n < 0 || k < 0 || e_o < 0 || e_i < 0) return 0;
+    return adjust_degree_ws(n, k, e_o, e_i);
+}
+
+onng_status onng_adjust_degree(const int32_t *knn_ids, const void *knn_dists, int64_t n, int32_t k,
+                               int32_t data_dtype, int32_t metric, int32_t e_o, int32_t e_i,
+                               int64_t *offsets, int32_t *nbrs, void *lens, int64_t nnz_capacity,
+                               int64_t *nnz_out, void *ws, size_t ws_bytes, void *stream) {
+    set_error("");
+    ONNG_CHECK_ARG(n >= 0 && k >= 1 && e_o >= 0 && e_i >= 0, "bad sizes");
+    ONNG_CHECK_ARG(n == 0 || (knn_ids && knn_dists), "kNN table is null");
+    ONNG_CHECK_ARG(offsets && nnz_out, "outputs are null");
+    ONNG_CHECK_ARG(nnz_capacity == 0 || (nbrs && lens), "nbrs/lens are null");
+    ONNG_CHECK_ARG(data_dtype >= ONNG_U8 && data_dtype <= ONNG_FP8_E4M3, "unknown dtype");
+    ONNG_CHECK_ARG(n <= 0x7fffffffLL, "more than 2^31-1 nodes");
+    if (ws_bytes < adjust_degree_ws(n, k, e_o, e_i) || !ws) {
+        set_error("onng_adjust_degree: workspace too small");
+        return ONNG_ERR_WORKSPACE;
+    }
+    return adjust_degree_launch(knn_ids, knn_dists, n, k, int_dist(data_dtype, metric), e_o, e_i,
+                                offsets, nbrs, lens, nnz_capacity, nnz_out, ws, as_stream(stream));
+}
+
+size_t onng_adjust_path_workspace_size(int64_t n, int64_t nnz) {
+    if (n < 0 || nnz < 0) return 0;
+    return adjust_path_ws(n, nnz);
+}
+
+onng_status onng_adjust_path(const onng_graph *in, int32_t data_dtype, int32_t metric,
+                             int64_t *offsets, int32_t *nbrs, void *lens, int64_t *nnz_out,
+                             void *ws, size_t ws_bytes, void *stream) {
+    set_error("");
+    ONNG_CHECK_ARG(in && in->offsets && in->n >= 0 && in->nnz >= 0, "graph is null");
+    ONNG_CHECK_ARG(in->nnz == 0 || (in->nbrs && in->lens), "graph needs nbrs and lens");
+    ONNG_CHECK_ARG(offsets && nnz_out && (in->nnz == 0 || (nbrs && lens)), "outputs are null");
+    ONNG_CHECK_ARG(in->n <= 0x7fffffffLL, "more than 2^31-1 nodes");
+    if (ws_bytes < adjust_path_ws(in->n, in->nnz) || !ws) {
+        set_error("onng_adjust_path: workspace too small");
+        return ONNG_ERR_WORKSPACE;
+    }
+    return adjust_path_launch(in, int_dist(data_dtype, metric), offsets, nbrs, lens, nnz_out, ws,
+                              as_stream(stream));
+}
+
+// ------------------------------------------------------------- search -----
+
+size_t onng_search_workspace_size(const onng_vectors *base, int64_t n_queries,
+                                  const onng_search_params *params) {
+    if (!base || !params || check_vectors(base, "base") != ONNG_OK) return 0;
+    onng_launch_config tuned;
+    const onng_launch_config *cfg = params->launch;
+    if (!cfg && lookup_tuned(base, params, &tuned)) cfg = &tuned;
+    SearchPlan P;
+    if (make_plan(base, n_queries, params, cfg, &P) != ONNG_OK) return 0;
+    return P.ws;
+}
+
+onng_status onng_search(const onng_vectors *base, const onng_graph *graph,
+                        const onng_vectors *queries, const int32_t *seeds, int32_t n_seeds,
+                        const onng_search_params *params, int32_t *ids, void *dists,
+                        onng_query_stats *stats, void *ws, size_t ws_bytes, void *stream) {
+    set_error("");
+    onng_launch_config tuned;
+    const onng_launch_config *cfg = params ? params->launch : nullptr;
+    if (params && !cfg && base && lookup_tuned(base, params, &tuned)) cfg = &tuned;
+    return run_search(base, graph, queries, seeds, n_seeds, params, ids, dists, stats, ws,
+                      ws_bytes, as_stream(stream), cfg);
+}
+
+onng_status onng_autotune_search(const onng_vectors *base, const onng_graph *graph,
+                                 const onng_vectors *queries, const int32_t *seeds,
+                                 int32_t n_seeds, const onng_search_params *params,
+                                 int32_t *ids, void *dists, onng_query_stats *stats, void *ws,
+                                 size_t ws_bytes, void *stream, onng_launch_config *best) {
+    set_error("");
+    ONNG_CHECK_ARG(best, "best is null");
+    ONNG_TRY(validate_search(base, graph, queries, seeds, n_seeds, params));
+    if (lookup_tuned(base, params, best)) return ONNG_OK;
+    hipStream_t st = as_stream(stream);
+    std::vector<onng_launch_config> cands;
+    const int n16 = (int)(base->pitch_bytes / 16);
+    for (int L : {4, 8, 16, 32})
+        for (int s_cap : {128, 256, 512})
+            for (int vl : {10, 11, 12, -1})
+                for (int wpb : {2, 4}) {
+                    if ((n16 + L - 1) / L > ppl_for(base->dtype)) continue;
+                    onng_launch_config c{};
+                    c.waves_per_block = wpb;
+                    c.lanes_per_row = L;
+                    c.s_capacity = s_cap;
+                    c.visited_log2 = vl;
+                    cands.push_back(c);
+                }
+    hipEvent_t e0, e1;
+    ONNG_HIP(hipEventCreate(&e0));
+    ONNG_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    bool found = false;
+    for (const auto &c : cands) {
+        SearchPlan P;
+        if (make_plan(base, queries->n, params, &c, &P) != ONNG_OK) continue;
+        if (P.ws > ws_bytes) continue;
+        if (params->two_phase && (int64_t)params->ep_first + n_seeds > P.s_cap) continue;
+        // warm-up, then two timed runs
+        if (run_search(base, graph, queries, seeds, n_seeds, params, ids, dists, stats, ws,
+                       ws_bytes, st, &c) != ONNG_OK)
+            continue;
+        ONNG_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < 2; r++)
+            run_search(base, graph, queries, seeds, n_seeds, params, ids, dists, stats, ws,
+                       ws_bytes, st, &c);
+        ONNG_HIP(hipEventRecord(e1, st));
+        ONNG_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        ONNG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            *best = c;
+            found = true;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (!found) {
+        set_error("onng_autotune_search: no launch shape fits the workspace");
+        return ONNG_ERR_WORKSPACE;
+    }
+    TuneKey key{base->dtype, base->metric, base->dim, base->n, params->k_stride,
+                params->rerank_base ? params->pool_factor : 0, params->two_phase};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = *best;
+    return ONNG_OK;
+}
+
+// ------------------------------------------------------ codecs, rerank ----
+
+onng_status onng_encode(const float *src, int64_t n, int32_t dim, int32_t dtype, void *dst,
+                        int64_t dst_pitch, float *scale, void *stream) {
+    set_error("");
+    ONNG_CHECK_ARG(n >= 0 && dim > 0, "bad sizes");
+    ONNG_CHECK_ARG(n == 0 || (src && dst), "null pointer");
+    ONNG_CHECK_ARG(dtype >= ONNG_F32 && dtype <= ONNG_FP8_E4M3, "dtype must be a float format");
+    ONNG_CHECK_ARG(dst_pitch >= (int64_t)dim * elem_bytes(dtype), "dst_pitch too small");
+    ONNG_CHECK_ARG(dtype != ONNG_FP8_E4M3 || scale, "FP8 needs a scale array");
+    return encode_launch(src, n, dim, dtype, dst, dst_pitch, scale, as_stream(stream));
+}
+
+onng_status onng_rerank(const onng_vectors *queries, const onng_vectors *base,
+                        const int32_t *pool, int32_t pool_size, int32_t k, int32_t use_f64,
+                        int32_t *ids, void *dists, void *stream) {
+    set_error("");
+    ONNG_TRY(check_vectors(queries, "queries"));
+    ONNG_TRY(check_vectors(base, "base"));
+    ONNG_CHECK_ARG(queries->dim == base->dim && queries->metric == base->metric,
+                   "queries and base differ in dim or metric");
+    ONNG_CHECK_ARG(pool_size >= 0 && k >= 1, "bad sizes");
+    ONNG_CHECK_ARG(queries->n == 0 || (pool && ids && dists), "null pointer");
+    return rerank_launch(queries, base, pool, pool_size, k, use_f64, ids, dists,
+                         as_stream(stream));
+}
+
+// ---------------------------------------------------------------- MLP -----
+
+onng_status onng_mlp_forward(const float *X, int32_t batch, int32_t F, const float *W1,
+                             const float *b1, int32_t H, const float *W2, const float *b2,
+                             int32_t T, float *hidden, float *Y, void *stream) {
+    set_error("");
+    ONNG_CHECK_ARG(batch >= 0 && F >= 1 && H >= 1 && H <= 64 && T >= 1 && T <= 8,
+                   "sizes: H in [1, 64], T in [1, 8]");
+    ONNG_CHECK_ARG(batch == 0 || (X && W1 && b1 && W2 && b2 && Y), "null pointer");
+    return mlp_forward_launch(X, batch, F, W1, b1, H, W2, b2, T, hidden, Y, as_stream(stream));
+}
+
+size_t onng_mlp_backward_workspace_size(int32_t batch, int32_t H, int32_t T) {
+    if (batch < 0 || H < 1 || T < 1) return 0;
+    return mlp_backward_ws(batch, H, T);
+}
+
+onng_status onng_mlp_backward(const float *X, const float *target, const float *w, int32_t batch,
+                              int32_t F, const float *W1, const float *b1, int32_t H,
+                              const float *W2, const float *b2, int32_t T, float *gW1,
+                              float *gb1, float *gW2, float *gb2, float *loss, void *ws,
+                              size_t ws_bytes, void *stream) {
+    set_error("");
+    ONNG_CHECK_ARG(batch >= 1 && F >= 1 && H >= 1 && H <= 64 && T >= 1 && T <= 8,
+                   "sizes: batch >= 1, H in [1, 64], T in [1, 8]");
+    ONNG_CHECK_ARG(X && target && W1 && b1 && W2 && b2 && gW1 && gb1 && gW2 && gb2 && loss,
+                   "null pointer");
+    if (!ws || ws_bytes < mlp_backward_ws(batch, H, T)) {
+        set_error("onng_mlp_backward: workspace too small");
+        return ONNG_ERR_WORKSPACE;
+    }
+    return mlp_backward_launch(X, target, w, batch, F, W1, b1, H, W2, b2, T, gW1, gb1, gW2, gb2,
+                               loss, ws, as_stream(stream));
+}
+
+onng_status onng_adam_step(float *p, const float *g, float *m, float *v, int64_t n, float lr,
+                           float beta1, float beta2, float eps, int32_t t, void *stream) {
+    set_error("");
+    ONNG_CHECK_ARG(n >= 0 && t >= 1, "bad sizes");
+    ONNG_CHECK_ARG(n == 0 || (p && g && m && v), "null pointer");
+    return adam_launch(p, g, m, v, n, lr, beta1, beta2, eps, t, as_stream(stream));
+}
+
+onng_status onng_feature_transform(const float *raw, int64_t n, int32_t metric, float *out,
+                                   void *stream) {
+    set_error("");
+    ONNG_CHECK_ARG(n >= 0 && (n == 0 || (raw && out)), "bad arguments");
+    return feature_transform_launch(raw, n, metric, out, as_stream(stream));
+}
+
+// ----------------------------------------------------------- pipeline -----
+
+struct onng_pipeline {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+size_t onng_pipeline_workspace_size(const onng_vectors *base, const onng_vectors *queries,
+                                    int64_t n_pivots, int32_t n_seeds,
+                                    const onng_search_params *params) {
+    if (!base || !queries || !params) return 0;
+    size_t a = onng_topk_workspace_size(queries, base, n_pivots, n_seeds);
+    size_t b = onng_search_workspace_size(base, queries->n, params);
+    if (!a || !b) return 0;
+    return (a + 255) / 256 * 256 + b;
+}
+
+onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *graph,
+                                 const onng_vectors *queries, const int32_t *pivots,
+                                 int64_t n_pivots, int32_t n_seeds, int32_t *seeds,
+                                 const onng_search_params *params, int32_t *ids, void *dists,
+                                 onng_query_stats *stats, void *ws, size_t ws_bytes,
+                                 void *stream, onng_pipeline **handle) {
+    set_error("");
+    ONNG_CHECK_ARG(handle && pivots && seeds && n_pivots >= 1, "bad pipeline arguments");
+    ONNG_TRY(validate_search(base, graph, queries, seeds, n_seeds, params));
+    ONNG_CHECK_ARG(base->dtype == ONNG_U8 || base->dtype == ONNG_F32 || params->rerank_base,
+                   "low-precision rows need rerank_base (f32 rows) for seeding");
+    size_t need = onng_pipeline_workspace_size(base, queries, n_pivots, n_seeds, params);
+    if (!need || !ws || ws_bytes < need) {
+        set_error("onng_pipeline_create: workspace too small");
+        return ONNG_ERR_WORKSPACE;
+    }
+    size_t a = (onng_topk_workspace_size(queries, base, n_pivots, n_seeds) + 255) / 256 * 256;
+    char *wsa = static_cast<char *>(ws);
+    // seeds come from the f32 rows when the searched rows are low precision
+    const onng_vectors *seed_base = base->dtype == ONNG_U8 || base->dtype == ONNG_F32
+                                        ? base : params->rerank_base;
+    hipStream_t st = as_stream(stream);
+    bool own = false;
+    if (!st) {
+        ONNG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        own = true;
+    }
+    // seed distances are not needed: write them into the search outputs,
+    // which the search overwrites afterwards
+    void *seed_d = dists;
+    onng_pipeline *pl = new onng_pipeline();
+    onng_status rc = ONNG_OK;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        set_error("onng_pipeline_create: stream capture failed to start");
+        delete pl;
+        if (own) hipStreamDestroy(st);
+        return ONNG_ERR_DEVICE;
+    }
+    if (params->k_stride < n_seeds) {
+        rc = ONNG_ERR_INVALID_ARG;
+        set_error("onng_pipeline_create: k_stride must be >= n_seeds");
+    }
+    if (rc == ONNG_OK)
+        rc = launch_topk(queries, seed_base, pivots, n_pivots, n_seeds, 0, seeds, seed_d, wsa, a,
+                         st);
+    if (rc == ONNG_OK)
+        rc = run_search(base, graph, queries, seeds, n_seeds, params, ids, dists, stats, wsa + a,
+                        ws_bytes - a, st, params->launch);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(st, &g);
+    if (rc == ONNG_OK && ce != hipSuccess) {
+        rc = ONNG_ERR_DEVICE;
+        set_error(std::string("onng_pipeline_create: capture failed: ") + hipGetErrorString(ce));
+    }
+    if (rc == ONNG_OK && hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        rc = ONNG_ERR_DEVICE;
+        set_error("onng_pipeline_create: graph instantiation failed");
+    }
+    pl->graph = g;
+    if (own) hipStreamDestroy(st);
+    if (rc != ONNG_OK) {
+        if (pl->exec) hipGraphExecDestroy(pl->exec);
+        if (pl->graph) hipGraphDestroy(pl->graph);
+        delete pl;
+        return rc;
+    }
+    *handle = pl;
+    return ONNG_OK;
+}
+
+onng_status onng_pipeline_launch(onng_pipeline *handle, void *stream) {
+    set_error("");
+    ONNG_CHECK_ARG(handle && handle->exec, "bad handle");
+    ONNG_HIP(hipGraphLaunch(handle->exec, as_stream(stream)));
+    return ONNG_OK;
+}
+
+onng_status onng_pipeline_destroy(onng_pipeline *handle) {
+    if (!handle) return ONNG_OK;
+    if (handle->exec) hipGraphExecDestroy(handle->exec);
+    if (handle->graph) hipGraphDestroy(handle->graph);
+    delete handle;
+    return ONNG_OK;
+}
+
+}  // extern "C"

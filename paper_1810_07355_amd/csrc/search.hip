@@ -1,0 +1,663 @@
+// Batched best-first k-nearest-neighbour search over an adjusted kNN graph:
+// KnnSearch (Algorithm 1) of Iwasaki & Miyazaki, one 64-lane wavefront per query.
+//
+// Per query the wave keeps, in LDS:
+//   pool   the best `pool_q` (distance, id) keys seen so far, sorted.  Its first
+//          k entries are the result set R of Algorithm 1; r is the k-th
+//          distance once k entries exist.  With a rerank, pool_q = pool_factor*k
+//          candidates are kept for the exact pass.
+//   S      the candidate set, a sorted array [head, size) of keys that are
+//          still within the search range; entries that no longer pass
+//          d <= r(1+eps) are cut from its tail (they can never be expanded).
+//          Keys that do not fit spill to a per-slot global array and come back
+//          when the on-chip part runs below their minimum, so S is exact.
+//   vis    the visited set C: an open-addressing hash table of node ids.  When
+//          it gets half full the query moves to a per-slot global bitset
+//          (atomic OR), which is cleared after the query.
+//
+// One expansion (pop of s, scan of its first e_p edges) is processed as one
+// batch: the unvisited neighbours are marked, their distances computed by the
+// whole wave, R updated with all of them, then the ones within the updated
+// range inserted into S.  Algorithm 1 interleaves these per neighbour; the
+// batch gives the same R, visited set, distance count and pop sequence,
+// because r never grows: a neighbour Algorithm 1 would insert with an older,
+// larger r but the batch rejects is beyond every later range and could only
+// end the search when popped, at a pop where the batch's next candidate ends
+// it too.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "dist.h"
+#include "onng_internal.h"
+#include "search_args.h"
+#include "wave.h"
+
+namespace onng {
+
+namespace {
+
+constexpr uint32_t VIS_EMPTY = 0xffffffffu;
+constexpr float F_INF = __builtin_inff();
+
+__device__ __forceinline__ uint32_t hash_id(uint32_t id) { return id * 2654435761u; }
+
+// (1+eps)^2 for squared L2, 1+eps for cosine, rounded to f32; +inf stays +inf.
+__device__ __forceinline__ float range_factor(float eps, int metric) {
+    if (__builtin_isinf(eps)) return F_INF;
+    double t = __dadd_rn(1.0, (double)eps);
+    return metric == ONNG_L2SQ ? (float)__dmul_rn(t, t) : (float)t;
+}
+
+__device__ __forceinline__ uint32_t dynamic_ep(float eps, float e0, float we) {
+    double v = floor(pow(10.0, (double)we * (double)eps) + (double)e0);
+    if (!(v < 4294967295.0)) return 0xffffffffu;
+    return v < 1.0 ? 1u : (uint32_t)v;
+}
+
+template <int DT, int MT>
+struct Q;
+
+// ----------------------------------------------------------- u8, L2^2 ----
+template <>
+struct Q<ONNG_U8, ONNG_L2SQ> {
+    static constexpr int PPL = 2;
+    static constexpr bool INT = true;
+    u32x4 q[PPL];
+    uint32_t qq;
+    __device__ void load(const uint8_t *row, int p, int L, int n16) {
+        qq = 0;
+#pragma unroll
+        for (int t = 0; t < PPL; t++) {
+            int pc = p + t * L;
+            if (pc < n16) {
+                q[t] = load16(row + pc * 16);
+                qq += u8_norm_piece(q[t]);
+            } else {
+                q[t] = u32x4{0, 0, 0, 0};
+            }
+        }
+    }
+    // partial over this lane's pieces of the row
+    __device__ uint32_t partial(const uint8_t *row, const float *, int p, int L, int n16) const {
+        uint32_t s = qq;
+        u32x4 x[PPL];
+#pragma unroll
+        for (int t = 0; t < PPL; t++) {
+            int pc = p + t * L;
+            x[t] = pc < n16 ? load16(row + pc * 16) : u32x4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int t = 0; t < PPL; t++) s += u8_piece(x[t], q[t]);
+        return s;
+    }
+};
+
+// ------------------------------------------------------ float storage ----
+template <int DT, int MT>
+struct Q {
+    static constexpr int PPL = DT == ONNG_F32 ? 4 : 2;
+    static constexpr int N = Piece<DT>::N;
+    static constexpr bool INT = false;
+    float q[PPL][N];
+    // the query is always f32: its piece t of the stored layout covers
+    // components [pc*N, pc*N + N)
+    __device__ void load_f32(const float *qrow, int dim, int p, int L, int n16) {
+#pragma unroll
+        for (int t = 0; t < PPL; t++) {
+            int pc = p + t * L;
+#pragma unroll
+            for (int e = 0; e < N; e++) {
+                int c = pc * N + e;
+                q[t][e] = (pc < n16 && c < dim) ? qrow[c] : 0.0f;
+            }
+        }
+    }
+    __device__ float partial(const uint8_t *row, const float *scale, int p, int L, int n16) const {
+        u32x4 x[PPL];
+#pragma unroll
+        for (int t = 0; t < PPL; t++) {
+            int pc = p + t * L;
+            x[t] = pc < n16 ? load16(row + pc * 16) : u32x4{0, 0, 0, 0};
+        }
+        float sc = 1.0f;
+        if constexpr (DT == ONNG_FP8_E4M3) sc = *scale;
+        float acc = 0.0f;
+#pragma unroll
+        for (int t = 0; t < PPL; t++) {
+            float v[N];
+            Piece<DT>::decode(x[t], v);
+#pragma unroll
+            for (int e = 0; e < N; e++) {
+                float xv = v[e];
+                if constexpr (DT == ONNG_FP8_E4M3) xv *= sc;
+                if constexpr (MT == ONNG_L2SQ) {
+                    float df = xv - q[t][e];
+                    acc = fmaf(df, df, acc);
+                } else {
+                    acc = fmaf(xv, q[t][e], acc);
+                }
+            }
+        }
+        return acc;
+    }
+};
+
+template <bool INT>
+__device__ __forceinline__ float key_dist(uint64_t key) {
+    uint32_t hi = (uint32_t)(key >> 32);
+    if constexpr (INT) return (float)hi;
+    else return unord_f32(hi);
+}
+
+__device__ __forceinline__ float threshold(bool rfull, float r, float f) {
+    if (!rfull || __builtin_isinf(f)) return F_INF;
+    return __fmul_rn(r, f);
+}
+
+struct LdsWave {
+    uint64_t *pool;
+    uint64_t *S;
+    uint64_t *stage;
+    uint64_t *stage2;
+    uint32_t *ids;
+    uint32_t *vis;
+    float *misc;
+};
+
+}  // namespace
+
+template <int DT, int MT>
+__global__ void __launch_bounds__(512) search_kernel(SearchKArgs a) {
+    typedef Q<DT, MT> QT;
+    constexpr bool INT = QT::INT;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int lane = lane_id();
+    const int wib = threadIdx.x / WAVE;
+    const int slot = blockIdx.x * a.waves_per_block + wib;
+
+    char *w = smem + (size_t)wib * a.lds_per_wave;
+    LdsWave lds;
+    lds.pool = reinterpret_cast<uint64_t *>(w + a.off_pool);
+    lds.S = reinterpret_cast<uint64_t *>(w + a.off_s);
+    lds.stage = reinterpret_cast<uint64_t *>(w + a.off_stage);
+    lds.stage2 = reinterpret_cast<uint64_t *>(w + a.off_stage2);
+    lds.ids = reinterpret_cast<uint32_t *>(w + a.off_ids);
+    lds.vis = reinterpret_cast<uint32_t *>(w + a.off_vis);
+    lds.misc = reinterpret_cast<float *>(w + a.off_misc);
+
+    uint32_t *gbits = a.gbits + (size_t)slot * a.gbits_words;
+    int32_t *vlog = a.vlog + (size_t)slot * a.vlog_cap;
+    uint64_t *spill0 = a.spill + (size_t)slot * 2 * a.spill_cap;
+    bool gbits_clean = false;   // this slot's bitset is known to be all zero
+
+    const int L = a.lanes_per_row;
+    const int p = lane & (L - 1);
+    const int grp = lane / L;
+    const int rpp = WAVE / L;   // rows per pass
+    const uint32_t vmask = a.vis_log2 > 0 ? (1u << a.vis_log2) - 1u : 0u;
+    const int vis_max = a.vis_log2 > 0 ? (1 << (a.vis_log2 - 1)) : 0;   // load 1/2
+
+    for (;;) {
+        int qi = 0;
+        if (lane == 0) qi = atomicAdd(a.counter, 1);
+        qi = uni(__shfl(qi, 0));
+        if (qi >= a.nq) break;
+
+        // ---------------------------------------------- per-query setup --
+        const int k = a.k_pq ? min(max(uni(a.k_pq[qi]), 1), a.k_stride) : a.k;
+        float eps = a.eps_pq ? unif(a.eps_pq[qi]) : a.eps;
+        uint32_t ep = a.ep_pq ? uniu(a.ep_pq[qi]) : a.ep;
+        float f = range_factor(eps, MT);
+        if (a.two_phase) {
+            f = F_INF;
+            ep = a.ep_first;
+        }
+        const int pool_q = a.has_rr ? min(a.pool_cap, max(k, a.pool_factor * k)) : k;
+
+        QT qr;
+        const uint8_t *qrow = a.qry + (size_t)qi * a.q_pitch;
+        if constexpr (INT) qr.load(qrow, p, L, a.n16);
+        else qr.load_f32(reinterpret_cast<const float *>(qrow), a.dim, p, L, a.n16);
+
+        // state
+        int npool = 0;
+        int head = 0, size = 0;
+        int spill_n = 0, spill_sel = 0;
+        uint64_t spill_min = KEY_MAX;
+        int vis_n = 0;
+        bool gmode = a.vis_log2 == 0;
+        int log_n = 0;
+        int dc = 0, hops = 0;
+        int flags = 0;
+        bool rfull = false;
+        float r = F_INF;
+
+        // clear the on-chip visited table
+        for (int i = lane; i <= (int)vmask && a.vis_log2 > 0; i += WAVE) lds.vis[i] = VIS_EMPTY;
+        if (gmode && !gbits_clean) {
+            for (int64_t i = lane; i < a.gbits_words; i += WAVE) gbits[i] = 0u;
+            __threadfence_block();
+            gbits_clean = true;
+        }
+        wave_sync();
+
+        // -------------------------------------------------- helpers ------
+        // Mark a batch of ids visited; returns whether this lane's id is new.
+        auto visit = [&](bool valid, uint32_t id) -> bool {
+            bool isnew = false;
+            if (!gmode) {
+                if (valid) {
+                    uint32_t h = hash_id(id) >> (32 - a.vis_log2);
+                    for (int probe = 0; probe <= (int)vmask; probe++) {
+                        uint32_t old = atomicCAS(&lds.vis[h], VIS_EMPTY, id);
+                        if (old == VIS_EMPTY) { isnew = true; break; }
+                        if (old == id) break;
+                        h = (h + 1) & vmask;
+                    }
+                }
+                vis_n += __popcll(ballot(isnew));
+                if (vis_n > vis_max) {
+                    // move to the global bitset: copy the table, log the ids
+                    wave_sync();
+                    if (!gbits_clean) {
+                        for (int64_t i = lane; i < a.gbits_words; i += WAVE) gbits[i] = 0u;
+                        __threadfence_block();
+                        gbits_clean = true;
+                    }
+                    for (int i = lane; i <= (int)vmask; i += WAVE) {
+                        uint32_t v = lds.vis[i];
+                        bool has = v != VIS_EMPTY;
+                        if (has) atomicOr(&gbits[v >> 5], 1u << (v & 31));
+                        uint64_t m = ballot(has);
+                        if (has && log_n + mbcnt(m) < a.vlog_cap) vlog[log_n + mbcnt(m)] = (int32_t)v;
+                        log_n += __popcll(m);
+                    }
+                    gmode = true;
+                    gbits_clean = false;
+                }
+            } else {
+                if (valid) {
+                    uint32_t bit = 1u << (id & 31);
+                    uint32_t old = atomicOr(&gbits[id >> 5], bit);
+                    isnew = (old & bit) == 0;
+                }
+                uint64_t m = ballot(isnew);
+                if (isnew && log_n + mbcnt(m) < a.vlog_cap) vlog[log_n + mbcnt(m)] = (int32_t)id;
+                log_n += __popcll(m);
+                gbits_clean = false;
+            }
+            return isnew;
+        };
+
+        // Distances of rows lds.ids[0..u) -> lds.stage2[i] as keys.
+        auto batch_keys = [&](int u) {
+            for (int r0 = 0; r0 < u; r0 += rpp) {
+                int row = r0 + grp;
+                typename DistTraits<DT>::acc_t acc = 0;
+                uint32_t id = 0;
+                if (row < u) {
+                    id = lds.ids[row];
+                    const uint8_t *rp = a.base + (size_t)id * a.base_pitch;
+                    const float *sp = a.base_scale ? a.base_scale + id : nullptr;
+                    acc = qr.partial(rp, sp, p, L, a.n16);
+                }
+                for (int m = L >> 1; m >= 1; m >>= 1) {
+                    if constexpr (INT) acc += (uint32_t)__shfl_xor((int)acc, m);
+                    else acc += __shfl_xor(acc, m);
+                }
+                if (row < u && p == 0) {
+                    uint32_t dord;
+                    if constexpr (INT) dord = acc;
+                    else dord = ord_f32(MT == ONNG_COSINE ? 1.0f - acc : acc);
+                    lds.stage2[row] = make_key(dord, id);
+                }
+            }
+            wave_sync();
+        };
+
+        // spill a key that fell past the on-chip capacity of S; spilled keys
+        // arrive in ascending order, so index 0 is the smallest of this merge
+        uint64_t first_spilled = KEY_MAX;
+        auto spill_put = [&](int idx, uint64_t key) {
+            int pos = spill_n + idx;
+            if (idx == 0) first_spilled = key;
+            if (pos < a.spill_cap) spill0[(size_t)spill_sel * a.spill_cap + pos] = key;
+        };
+
+        // Merge sorted batch (lane j < nb holds j-th key) into S.
+        auto s_insert = [&](uint64_t key, int nb) {
+            if (nb == 0) return;
+            if (size + nb > a.s_cap && head > 0) {
+                // compact the live part to the front
+                int live = size - head;
+                for (int c0 = 0; c0 < live; c0 += WAVE) {
+                    uint64_t v = 0;
+                    if (c0 + lane < live) v = lds.S[head + c0 + lane];
+                    wave_sync();
+                    if (c0 + lane < live) lds.S[c0 + lane] = v;
+                    wave_sync();
+                }
+                size = live;
+                head = 0;
+            }
+            first_spilled = KEY_MAX;
+            int total = merge_sorted(lds.S, head, size - head, key, nb, a.s_cap - head, lds.stage,
+                                     spill_put);
+            int over = total - (a.s_cap - head);
+            if (over > 0) {
+                uint64_t mn = first_spilled;
+                for (int m = 32; m >= 1; m >>= 1) {
+                    uint64_t o = shfl_xor64(mn, m);
+                    mn = o < mn ? o : mn;
+                }
+                mn = uni64(mn);
+                spill_min = mn < spill_min ? mn : spill_min;
+                if (spill_n + over > a.spill_cap) flags |= ONNG_QF_CAPACITY;
+                spill_n = min(spill_n + over, (int)a.spill_cap);
+                flags |= ONNG_QF_SPILLED;
+                size = a.s_cap;
+            } else {
+                size = head + total;
+            }
+        };
+
+        // Drop S entries beyond the range (a suffix of the sorted array).
+        auto s_prune = [&](float thr) {
+            if (size == head || __builtin_isinf(thr)) return;
+            // first index with d > thr
+            int lo = head, hi = size;
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (key_dist<INT>(lds.S[mid]) > thr) hi = mid;
+                else lo = mid + 1;
+            }
+            size = uni(lo);
+        };
+
+        // Merge sorted keys into the pool (R and rerank candidates).
+        auto pool_insert = [&](uint64_t key, int nb) {
+            if (nb == 0) return;
+            int total = merge_sorted(lds.pool, 0, npool, key, nb, pool_q, lds.stage, NoSpill());
+            npool = min(total, pool_q);
+            if (npool >= k) {
+                rfull = true;
+                r = key_dist<INT>(lds.pool[k - 1]);
+                r = unif(r);
+            }
+        };
+
+        // Process a sorted batch: R first, then the range test with the new r.
+        auto absorb = [&](uint64_t key, int u, bool to_s) {
+            pool_insert(key, u);
+            float thr = threshold(rfull, r, f);
+            bool keep = lane < u && key_dist<INT>(key) <= thr;
+            if (!to_s) keep = lane < u;
+            uint64_t m = ballot(keep);
+            int nk = __popcll(m);
+            // compact (order preserved)
+            if (keep) lds.stage2[mbcnt(m)] = key;
+            wave_sync();
+            uint64_t ck = lane < nk ? lds.stage2[lane] : KEY_MAX;
+            wave_sync();
+            s_prune(thr);
+            s_insert(ck, nk);
+        };
+
+        // Bring spilled keys back: merge every live spilled key into S, the
+        // ones that do not fit go to the other spill buffer.
+        auto refill = [&]() {
+            __threadfence_block();   // spilled keys were stored by other lanes
+            float thr = threshold(rfull, r, f);
+            int n_old = spill_n;
+            int sel_old = spill_sel;
+            spill_sel ^= 1;
+            spill_n = 0;
+            spill_min = KEY_MAX;
+            for (int c0 = 0; c0 < n_old; c0 += WAVE) {
+                uint64_t v = KEY_MAX;
+                if (c0 + lane < n_old) {
+                    v = spill0[(size_t)sel_old * a.spill_cap + c0 + lane];
+                    if (key_dist<INT>(v) > thr) v = KEY_MAX;   // dead
+                }
+                uint64_t m = ballot(v != KEY_MAX);
+                int nb = __popcll(m);
+                if (nb == 0) continue;
+                v = wave_sort(v, WAVE);
+                s_prune(thr);
+                s_insert(v, nb);
+            }
+        };
+
+        // ------------------------------------------------------ seeds ----
+        {
+            bool valid = false;
+            uint32_t sid = 0;
+            if (lane < a.n_seeds) {
+                int32_t s = a.seeds[(size_t)qi * a.n_seeds + lane];
+                valid = s >= 0 && (int64_t)s < a.n_base;
+                sid = valid ? (uint32_t)s : 0u;
+            }
+            bool isnew = visit(valid, sid);
+            uint64_t m = ballot(isnew);
+            int u = __popcll(m);
+            if (isnew) lds.ids[mbcnt(m)] = sid;
+            wave_sync();
+            batch_keys(u);
+            dc += u;
+            uint64_t key = lane < u ? lds.stage2[lane] : KEY_MAX;
+            wave_sync();
+            key = wave_sort(key, pow2_at_least(u));
+            if (a.two_phase) lds.misc[lane] = lane < u ? key_dist<INT>(key) : 0.0f;
+            if (a.two_phase && lane == 0) lds.misc[64] = (float)u;
+            // every seed enters S (no range test) and is offered to R
+            absorb(key, u, false);
+        }
+
+        // ------------------------------------------------- main loop -----
+        for (;;) {
+            if (head == size && spill_n == 0) break;                  // S empty
+            if (spill_n > 0 && (head == size || uni64(lds.S[head]) > spill_min)) {
+                refill();
+                if (head == size) break;
+            }
+            uint64_t sk = uni64(lds.S[head]);
+            head++;
+            float thr = threshold(rfull, r, f);
+            if (key_dist<INT>(sk) > thr) break;                        // d(s,q) > r(1+eps)
+            hops++;
+            const uint32_t s = (uint32_t)sk;
+            const int64_t e0 = a.offsets[s];
+            const int64_t deg = a.offsets[s + 1] - e0;
+            const int64_t np = (int64_t)ep < deg ? (int64_t)ep : deg;
+            for (int64_t c0 = 0; c0 < np; c0 += WAVE) {
+                int64_t j = c0 + lane;
+                uint32_t id = j < np ? (uint32_t)a.nbrs[e0 + j] : 0u;
+                bool valid = j < np && (int64_t)id < a.n_base;
+                bool isnew = visit(valid, id);
+                uint64_t m = ballot(isnew);
+                int u = __popcll(m);
+                if (u == 0) continue;
+                if (isnew) lds.ids[mbcnt(m)] = id;
+                wave_sync();
+                batch_keys(u);
+                dc += u;
+                uint64_t key = lane < u ? lds.stage2[lane] : KEY_MAX;
+                wave_sync();
+                key = wave_sort(key, pow2_at_least(u));
+                absorb(key, u, true);
+            }
+
+            if (a.two_phase && hops == 1) {
+                // ---- state after the first expansion -> search range ----
+                float feat[ONNG_NFEAT];
+                int nseed = (int)lds.misc[64];
+#pragma unroll
+                for (int t = 0; t < 8; t++)
+                    feat[t] = nseed == 0 ? 0.0f : lds.misc[t < nseed ? t : nseed - 1];
+                int ns = size - head;   // no spill can happen in the first expansion
+                float rmax = npool > 0 ? key_dist<INT>(lds.pool[min(npool, k) - 1]) : 0.0f;
+                feat[8] = (float)ns;
+                if (ns > 0) {
+                    feat[9] = key_dist<INT>(lds.S[head]);
+                    feat[10] = key_dist<INT>(lds.S[head + (ns - 1) / 2]);
+                    feat[11] = key_dist<INT>(lds.S[size - 1]);
+                } else {
+                    feat[9] = feat[10] = feat[11] = rmax;
+                }
+                feat[12] = rmax;
+                feat[13] = (float)dc;
+                if (a.feat_out && lane == 0) {
+#pragma unroll
+                    for (int t = 0; t < ONNG_NFEAT; t++)
+                        a.feat_out[(size_t)qi * ONNG_NFEAT + t] = feat[t];
+                }
+                if (a.has_pred) {
+                    eps = predict_eps(a.pred, feat, MT, qi, lane);
+                    eps = unif(eps);
+                    ep = a.pred.we >= 0.0f ? dynamic_ep(eps, a.pred.e0, a.pred.we)
+                                           : (a.ep_pq ? uniu(a.ep_pq[qi]) : a.ep);
+                } else {
+                    eps = a.eps_pq ? unif(a.eps_pq[qi]) : a.eps;
+                    ep = a.ep_pq ? uniu(a.ep_pq[qi]) : a.ep;
+                }
+                f = range_factor(eps, MT);
+                s_prune(threshold(rfull, r, f));
+            }
+        }
+
+        // ---------------------------------------------- rerank, output ---
+        int nout = min(npool, k);
+        if (a.has_rr && npool > 0) {
+            // exact f32 distances of the pool from the f32 rows
+            for (int c0 = 0; c0 < npool; c0 += WAVE) {
+                if (c0 + lane < npool) lds.ids[lane] = (uint32_t)lds.pool[c0 + lane];
+                wave_sync();
+                int u = min(WAVE, npool - c0);
+                for (int r0 = 0; r0 < u; r0 += 4) {
+                    int row = r0 + (lane >> 4);
+                    int pp = lane & 15;
+                    float acc = 0.0f;
+                    uint32_t id = 0;
+                    if (row < u) {
+                        id = lds.ids[row];
+                        const float *xr =
+                            reinterpret_cast<const float *>(a.rr_base + (size_t)id * a.rr_pitch);
+                        const float *qf = reinterpret_cast<const float *>(qrow);
+                        for (int c = pp; c < a.dim; c += 16) {
+                            if constexpr (MT == ONNG_L2SQ) {
+                                float df = xr[c] - qf[c];
+                                acc = fmaf(df, df, acc);
+                            } else {
+                                acc = fmaf(xr[c], qf[c], acc);
+                            }
+                        }
+                    }
+                    for (int m = 8; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
+                    if (row < u && pp == 0) {
+                        float d = MT == ONNG_COSINE ? 1.0f - acc : acc;
+                        lds.stage2[row] = make_key(ord_f32(d), id);
+                    }
+                }
+                wave_sync();
+                uint64_t key = lane < u ? lds.stage2[lane] : KEY_MAX;
+                wave_sync();
+                key = wave_sort(key, pow2_at_least(u));
+                // reuse S as the top-k accumulator of the reranked keys
+                int cur = c0 == 0 ? 0 : min(c0, k);
+                merge_sorted(lds.S, 0, cur, key, u, k, lds.stage, NoSpill());
+            }
+            nout = min(npool, k);
+            for (int i = lane; i < a.k_stride; i += WAVE) {
+                int32_t id = -1;
+                float d = F_INF;
+                if (i < nout) {
+                    uint64_t key = lds.S[i];
+                    id = (int32_t)(uint32_t)key;
+                    d = unord_f32((uint32_t)(key >> 32));
+                }
+                a.out_ids[(size_t)qi * a.k_stride + i] = id;
+                reinterpret_cast<float *>(a.out_d)[(size_t)qi * a.k_stride + i] = d;
+            }
+        } else {
+            for (int i = lane; i < a.k_stride; i += WAVE) {
+                int32_t id = -1;
+                uint64_t key = i < nout ? lds.pool[i] : KEY_MAX;
+                if (i < nout) id = (int32_t)(uint32_t)key;
+                a.out_ids[(size_t)qi * a.k_stride + i] = id;
+                if constexpr (INT) {
+                    reinterpret_cast<int32_t *>(a.out_d)[(size_t)qi * a.k_stride + i] =
+                        i < nout ? (int32_t)(key >> 32) : INT32_MAX;
+                } else {
+                    reinterpret_cast<float *>(a.out_d)[(size_t)qi * a.k_stride + i] =
+                        i < nout ? unord_f32((uint32_t)(key >> 32)) : F_INF;
+                }
+            }
+        }
+        if (nout < k) flags |= ONNG_QF_PADDED;
+        if (lane == 0) {
+            onng_query_stats st;
+            st.dc = dc;
+            st.hops = hops;
+            st.flags = flags;
+            st.e_p = ep;
+            st.eps = eps;
+            st.reserved[0] = st.reserved[1] = st.reserved[2] = 0;
+            a.stats[qi] = st;
+        }
+
+        // leave the global visited bitset clean for the next query
+        if (gmode) {
+            __threadfence_block();   // the log was written by other lanes
+            if (log_n <= a.vlog_cap) {
+                for (int i = lane; i < log_n; i += WAVE) gbits[(uint32_t)vlog[i] >> 5] = 0u;
+            } else {
+                for (int64_t i = lane; i < a.gbits_words; i += WAVE) gbits[i] = 0u;
+            }
+            __threadfence_block();
+            gbits_clean = true;
+        }
+        wave_sync();
+    }
+}
+
+// Dispatch -----------------------------------------------------------------
+
+#define ONNG_SEARCH_INST(DT, MT)                                                      \
+    template __global__ void search_kernel<DT, MT>(SearchKArgs);
+
+ONNG_SEARCH_INST(ONNG_U8, ONNG_L2SQ)
+ONNG_SEARCH_INST(ONNG_F32, ONNG_L2SQ)
+ONNG_SEARCH_INST(ONNG_F32, ONNG_COSINE)
+ONNG_SEARCH_INST(ONNG_F16, ONNG_L2SQ)
+ONNG_SEARCH_INST(ONNG_F16, ONNG_COSINE)
+ONNG_SEARCH_INST(ONNG_BF16, ONNG_L2SQ)
+ONNG_SEARCH_INST(ONNG_BF16, ONNG_COSINE)
+ONNG_SEARCH_INST(ONNG_FP8_E4M3, ONNG_L2SQ)
+ONNG_SEARCH_INST(ONNG_FP8_E4M3, ONNG_COSINE)
+
+__global__ void reset_counter_kernel(int32_t *c) { *c = 0; }
+
+const void *search_kernel_ptr(int dtype, int metric) {
+    switch (dtype) {
+    case ONNG_U8: return metric == ONNG_L2SQ ? (const void *)search_kernel<ONNG_U8, ONNG_L2SQ> : nullptr;
+    case ONNG_F32:
+        return metric == ONNG_L2SQ ? (const void *)search_kernel<ONNG_F32, ONNG_L2SQ>
+                                   : (const void *)search_kernel<ONNG_F32, ONNG_COSINE>;
+    case ONNG_F16:
+        return metric == ONNG_L2SQ ? (const void *)search_kernel<ONNG_F16, ONNG_L2SQ>
+                                   : (const void *)search_kernel<ONNG_F16, ONNG_COSINE>;
+    case ONNG_BF16:
+        return metric == ONNG_L2SQ ? (const void *)search_kernel<ONNG_BF16, ONNG_L2SQ>
+                                   : (const void *)search_kernel<ONNG_BF16, ONNG_COSINE>;
+    case ONNG_FP8_E4M3:
+        return metric == ONNG_L2SQ ? (const void *)search_kernel<ONNG_FP8_E4M3, ONNG_L2SQ>
+                                   : (const void *)search_kernel<ONNG_FP8_E4M3, ONNG_COSINE>;
+    }
+    return nullptr;
+}
+
+const void *reset_counter_kernel_ptr() { return (const void *)reset_counter_kernel; }
+
+}  // namespace onng

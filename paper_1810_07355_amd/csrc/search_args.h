@@ -1,0 +1,122 @@
+// Kernel-argument block of the search kernel and the fused search-range
+// predictor evaluated after the first expansion.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/onng.h"
+
+namespace onng {
+
+struct PredArgs {
+    const uint16_t *w1;   // bf16 [H][F]
+    const float *b1;      // [H]
+    const uint16_t *w2;   // bf16 [T][H]
+    const float *b2;      // [T]
+    const float *mean;    // [F]
+    const float *stdv;    // [F]
+    const float *shift;   // [T] or null
+    const int32_t *head_pq;
+    int32_t head;
+    int32_t F, H, T;
+    float eps_min, eps_max, e0, we;
+};
+
+struct SearchKArgs {
+    // stored rows
+    const uint8_t *base;
+    const float *base_scale;
+    int64_t base_pitch;
+    int64_t n_base;
+    int32_t dim;
+    int32_t n16;            // 16-byte pieces per stored row
+    // graph
+    const int64_t *offsets;
+    const int32_t *nbrs;
+    // queries (u8 rows for u8 data, f32 rows otherwise)
+    const uint8_t *qry;
+    int64_t q_pitch;
+    int32_t nq;
+    const int32_t *seeds;
+    int32_t n_seeds;
+    // parameters
+    int32_t k;
+    const int32_t *k_pq;
+    int32_t k_stride;
+    float eps;
+    const float *eps_pq;
+    uint32_t ep;
+    const uint32_t *ep_pq;
+    int32_t two_phase;
+    uint32_t ep_first;
+    int32_t has_pred;
+    PredArgs pred;
+    float *feat_out;
+    // rerank
+    int32_t has_rr;
+    const uint8_t *rr_base;
+    int64_t rr_pitch;
+    int32_t pool_factor;
+    // outputs
+    int32_t *out_ids;
+    void *out_d;
+    onng_query_stats *stats;
+    // scheduling and scratch
+    int32_t *counter;
+    uint32_t *gbits;
+    int64_t gbits_words;    // per slot
+    int32_t *vlog;
+    int32_t vlog_cap;       // per slot
+    uint64_t *spill;
+    int32_t spill_cap;      // per slot and buffer (two buffers per slot)
+    // on-chip layout, per wave
+    int32_t lanes_per_row;
+    int32_t s_cap;
+    int32_t vis_log2;
+    int32_t pool_cap;
+    int32_t waves_per_block;
+    int32_t lds_per_wave;
+    int32_t off_pool, off_s, off_stage, off_stage2, off_ids, off_vis, off_misc;
+};
+
+// log10(eps + 0.01) heads -> eps for this query.  Features are the raw state
+// after the first expansion (8 seed distances ascending, |S|, min/median/max
+// of S, radius of R, distance computations); all lanes return the same value.
+__device__ inline float predict_eps(const PredArgs &P, const float *feat, int metric, int qi,
+                                    int lane) {
+    const float c = metric == ONNG_COSINE ? 1e-3f : 1.0f;
+    float x[ONNG_NFEAT];
+    float lg0 = logf(fmaxf(feat[0], 0.0f) + c);
+    x[0] = lg0;
+#pragma unroll
+    for (int t = 1; t < 8; t++) x[t] = logf(fmaxf(feat[t], 0.0f) + c) - lg0;
+    x[8] = log1pf(feat[8]);
+#pragma unroll
+    for (int t = 9; t < 13; t++) x[t] = logf(fmaxf(feat[t], 0.0f) + c) - lg0;
+    x[13] = log1pf(feat[13]);
+#pragma unroll
+    for (int t = 0; t < ONNG_NFEAT; t++) x[t] = (x[t] - P.mean[t]) / P.stdv[t];
+    const int head = P.head_pq ? P.head_pq[qi] : P.head;
+    float h = 0.0f;
+    if (lane < P.H) {
+        float s = P.b1[lane];
+        for (int t = 0; t < P.F; t++) {
+            float wv = __uint_as_float((uint32_t)P.w1[lane * P.F + t] << 16);
+            s = fmaf(wv, x[t], s);
+        }
+        h = fmaxf(s, 0.0f);
+        h *= __uint_as_float((uint32_t)P.w2[head * P.H + lane] << 16);
+    }
+    for (int m = 32; m >= 1; m >>= 1) h += __shfl_xor(h, m);
+    float y = h + P.b2[head] + (P.shift ? P.shift[head] : 0.0f);
+    float eps = exp10f(y) - 0.01f;
+    eps = fminf(fmaxf(eps, P.eps_min), P.eps_max);
+    return eps;
+}
+
+const void *search_kernel_ptr(int dtype, int metric);
+const void *reset_counter_kernel_ptr();
+
+}  // namespace onng

@@ -1,0 +1,416 @@
+// Exact top-k under (distance, id) by brute force on the matrix cores.
+//
+// The distance matrix is |x|^2 + |y|^2 - 2<x, y>; the dot products are the
+// dense contraction and run on MFMA: int8 x int8 -> int32 (16x16x64) for u8
+// data, after shifting every component by -128 (the shift cancels in x - y,
+// and |<x', y'>| <= 128^3 keeps int32 exact), f32 x f32 -> f32 (16x16x4)
+// for float data.  Cosine distance on unit vectors is 1 - <x, y>.
+//
+// A block owns BM query rows (16 per wave) and sweeps all base rows in tiles
+// of 64 staged in LDS.  Each row keeps its current k best keys sorted in LDS
+// and a buffer of candidates that beat its k-th key; the buffer is sorted and
+// merged into the list when it could overflow on the next tile and at the end.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "onng_internal.h"
+#include "wave.h"
+
+namespace onng {
+
+namespace {
+
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BN = 64;        // base rows per tile
+constexpr int CB = 128;       // candidate slots per query row
+
+struct TopkArgs {
+    const uint8_t *q;
+    int64_t q_pitch;
+    int64_t nq;
+    const uint8_t *b;         // base rows (or gathered candidate rows)
+    int64_t b_pitch;
+    int64_t nb;
+    const int32_t *b_ids;     // global id of each base row (null: the row index)
+    const void *qn;           // query norms (int32 or float), null for cosine
+    const void *bn;           // base norms
+    int32_t dim;
+    int32_t k;
+    int32_t kcap;             // list capacity per row (>= k, multiple of 64)
+    int32_t bm;               // query rows per block (16 per wave)
+    int32_t exclude_self;
+    int32_t lds_pitch;        // bytes per staged base row
+    int32_t *out_ids;
+    void *out_d;
+};
+
+// ---- per-row norms (int32 |x-128|^2 for u8, f32 |x|^2 otherwise) ----------
+__global__ void norms_u8_kernel(const uint8_t *x, int64_t pitch, int64_t n, int dim,
+                                int32_t *out) {
+    int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    int lane = threadIdx.x & 63;
+    if (i >= n) return;
+    int32_t s = 0;
+    for (int c = lane; c < dim; c += 64) {
+        int v = (int)x[i * pitch + c] - 128;
+        s += v * v;
+    }
+    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+    if (lane == 0) out[i] = s;
+}
+
+__global__ void norms_f32_kernel(const uint8_t *x, int64_t pitch, int64_t n, int dim,
+                                 float *out) {
+    int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    int lane = threadIdx.x & 63;
+    if (i >= n) return;
+    const float *r = reinterpret_cast<const float *>(x + i * pitch);
+    float s = 0.0f;
+    for (int c = lane; c < dim; c += 64) s = fmaf(r[c], r[c], s);
+    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+    if (lane == 0) out[i] = s;
+}
+
+__global__ void gather_rows_kernel(const uint8_t *src, int64_t pitch, const int32_t *ids,
+                                   int64_t n, uint8_t *dst) {
+    int64_t i = blockIdx.x;
+    if (i >= n) return;
+    const uint8_t *s = src + (int64_t)ids[i] * pitch;
+    uint8_t *d = dst + i * pitch;
+    for (int64_t c = threadIdx.x * 16; c < pitch; c += blockDim.x * 16)
+        *reinterpret_cast<uint4 *>(d + c) = *reinterpret_cast<const uint4 *>(s + c);
+}
+
+// 16 int8 values of (x - 128) at row bytes [c, c+16), zero past dim
+__device__ __forceinline__ i32x4 shifted16(const uint8_t *row, int c, int dim) {
+    i32x4 out;
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            int idx = c + 4 * w + b;
+            uint32_t byte = idx < dim ? (uint32_t)(uint8_t)((int)row[idx] - 128) : 0u;
+            v |= byte << (8 * b);
+        }
+        out[w] = (int32_t)v;
+    }
+    return out;
+}
+
+template <int DT, int MT>
+__global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
+    constexpr bool U8 = DT == ONNG_U8;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int lane = lane_id();
+    const int wv = threadIdx.x / WAVE;
+    const int nwaves = a.bm / 16;
+    const int64_t row0 = (int64_t)blockIdx.x * a.bm;
+
+    // LDS: [B tile][lists bm*kcap][cands bm*CB][tau bm][cnt bm][nlist bm][stage nwaves*64]
+    char *p = smem;
+    uint8_t *btile = reinterpret_cast<uint8_t *>(p);
+    p += (size_t)BN * a.lds_pitch;
+    uint64_t *lists = reinterpret_cast<uint64_t *>(p);
+    p += (size_t)a.bm * a.kcap * 8;
+    uint64_t *cands = reinterpret_cast<uint64_t *>(p);
+    p += (size_t)a.bm * CB * 8;
+    uint64_t *tau = reinterpret_cast<uint64_t *>(p);
+    p += (size_t)a.bm * 8;
+    int32_t *cnt = reinterpret_cast<int32_t *>(p);
+    p += (size_t)a.bm * 4;
+    int32_t *nlist = reinterpret_cast<int32_t *>(p);
+    p += (size_t)a.bm * 4;
+    uint64_t *stage = reinterpret_cast<uint64_t *>(p) + wv * WAVE;
+
+    for (int i = threadIdx.x; i < a.bm; i += blockDim.x) {
+        tau[i] = KEY_MAX;
+        cnt[i] = 0;
+        nlist[i] = 0;
+    }
+
+    // ---- this wave's 16 query rows as MFMA A operands ----
+    const int arow = lane & 15;      // row within the wave's block
+    const int kg = lane >> 4;        // k-group of this lane
+    const int64_t qrow = row0 + wv * 16 + arow;
+    const bool qvalid = qrow < a.nq;
+    const uint8_t *qp = a.q + (qvalid ? qrow : 0) * a.q_pitch;
+    constexpr int MAXS = U8 ? 8 : 64;    // k-steps held in registers
+    const int ksteps = U8 ? (a.dim + 63) / 64 : (a.dim + 3) / 4;
+    i32x4 A8[U8 ? MAXS : 1];
+    float AF[U8 ? 1 : MAXS];
+    if constexpr (U8) {
+#pragma unroll
+        for (int s = 0; s < MAXS; s++)
+            if (s < ksteps) A8[s] = qvalid ? shifted16(qp, s * 64 + kg * 16, a.dim) : i32x4{0, 0, 0, 0};
+    } else {
+        const float *qf = reinterpret_cast<const float *>(qp);
+#pragma unroll
+        for (int s = 0; s < MAXS; s++) {
+            int c = s * 4 + kg;
+            if (s < ksteps) AF[s] = (qvalid && c < a.dim) ? qf[c] : 0.0f;
+        }
+    }
+    // norms of the 4 output rows this lane sees in C (rows 4*kg + r)
+    int32_t qn8[4] = {0, 0, 0, 0};
+    float qnf[4] = {0, 0, 0, 0};
+    int64_t crow[4];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        crow[r] = row0 + wv * 16 + 4 * kg + r;
+        if (crow[r] < a.nq) {
+            if constexpr (U8) qn8[r] = reinterpret_cast<const int32_t *>(a.qn)[crow[r]];
+            else if constexpr (MT == ONNG_L2SQ) qnf[r] = reinterpret_cast<const float *>(a.qn)[crow[r]];
+        }
+    }
+    __syncthreads();
+
+    auto flush_row = [&](int lr) {
+        // lr: row within block; whole wave participates
+        int n = uni(cnt[lr]);
+        if (n == 0) return;
+        uint64_t *lst = lists + (size_t)lr * a.kcap;
+        int nl = uni(nlist[lr]);
+        for (int c0 = 0; c0 < n; c0 += WAVE) {
+            uint64_t key = c0 + lane < n ? cands[(size_t)lr * CB + c0 + lane] : KEY_MAX;
+            int nb = min(WAVE, n - c0);
+            key = wave_sort(key, pow2_at_least(nb));
+            int total = merge_sorted(lst, 0, nl, key, nb, a.k, stage, NoSpill());
+            nl = min(total, a.k);
+        }
+        if (lane == 0) {
+            cnt[lr] = 0;
+            nlist[lr] = nl;
+            tau[lr] = nl == a.k ? lst[a.k - 1] : KEY_MAX;
+        }
+        wave_sync();
+    };
+
+    const int ntiles = (int)((a.nb + BN - 1) / BN);
+    const int chunks_per_row = a.lds_pitch / 16;
+    for (int t = 0; t < ntiles; t++) {
+        const int64_t col0 = (int64_t)t * BN;
+        __syncthreads();
+        // stage 64 base rows
+        for (int i = threadIdx.x; i < BN * chunks_per_row; i += blockDim.x) {
+            int r = i / chunks_per_row, c = i % chunks_per_row;
+            int64_t br = col0 + r;
+            uint4 v = {0, 0, 0, 0};
+            if (br < a.nb && (int64_t)c * 16 < a.b_pitch)
+                v = *reinterpret_cast<const uint4 *>(a.b + br * a.b_pitch + c * 16);
+            if constexpr (U8) {
+                // x - 128 as int8 is x ^ 0x80; components past dim become 0
+                uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int w = 0; w < 4; w++) {
+                    uint32_t x = w4[w] ^ 0x80808080u;
+                    int valid = a.dim - (c * 16 + 4 * w);
+                    if (valid <= 0) x = 0u;
+                    else if (valid < 4) x &= (1u << (8 * valid)) - 1u;
+                    w4[w] = x;
+                }
+                v = uint4{w4[0], w4[1], w4[2], w4[3]};
+            }
+            *reinterpret_cast<uint4 *>(btile + r * a.lds_pitch + c * 16) = v;
+        }
+        __syncthreads();
+        if (row0 + wv * 16 >= a.nq) continue;
+
+        uint64_t thr[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) thr[r] = tau[wv * 16 + 4 * kg + r];
+
+#pragma unroll
+        for (int cb = 0; cb < 4; cb++) {
+            const int bcol = cb * 16 + arow;           // tile column this lane feeds
+            const uint8_t *brow = btile + bcol * a.lds_pitch;
+            i32x4 acc8 = {0, 0, 0, 0};
+            f32x4 accf = {0, 0, 0, 0};
+            if constexpr (U8) {
+#pragma unroll
+                for (int s = 0; s < MAXS; s++) {
+                    if (s < ksteps) {
+                        i32x4 bv = *reinterpret_cast<const i32x4 *>(brow + s * 64 + kg * 16);
+                        acc8 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A8[s], bv, acc8, 0, 0, 0);
+                    }
+                }
+            } else {
+                const float *bf = reinterpret_cast<const float *>(brow);
+#pragma unroll
+                for (int s = 0; s < MAXS; s++) {
+                    if (s < ksteps) {
+                        int c = s * 4 + kg;
+                        float bv = c < a.dim ? bf[c] : 0.0f;
+                        accf = __builtin_amdgcn_mfma_f32_16x16x4f32(AF[s], bv, accf, 0, 0, 0);
+                    }
+                }
+            }
+            // C layout: lane holds rows 4*kg + r (r = 0..3) of column arow
+            const int64_t col = col0 + cb * 16 + arow;
+            const bool cvalid = col < a.nb;
+            const uint32_t gid = cvalid ? (a.b_ids ? (uint32_t)a.b_ids[col] : (uint32_t)col) : 0u;
+            int32_t bn8 = 0;
+            float bnf = 0.0f;
+            if (cvalid) {
+                if constexpr (U8) bn8 = reinterpret_cast<const int32_t *>(a.bn)[col];
+                else if constexpr (MT == ONNG_L2SQ) bnf = reinterpret_cast<const float *>(a.bn)[col];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                uint32_t dord;
+                if constexpr (U8) {
+                    dord = (uint32_t)(qn8[r] + bn8 - 2 * acc8[r]);
+                } else if constexpr (MT == ONNG_L2SQ) {
+                    dord = ord_f32(qnf[r] + bnf - 2.0f * accf[r]);
+                } else {
+                    dord = ord_f32(1.0f - accf[r]);
+                }
+                uint64_t key = make_key(dord, gid);
+                bool ok = cvalid && crow[r] < a.nq && key < thr[r] &&
+                          !(a.exclude_self && (int64_t)gid == crow[r]);
+                if (ok) {
+                    int lr = wv * 16 + 4 * kg + r;
+                    int slot = atomicAdd(&cnt[lr], 1);
+                    cands[(size_t)lr * CB + slot] = key;
+                }
+            }
+        }
+        wave_sync();
+        // rows whose buffer could overflow on the next tile
+        for (int r = 0; r < 16; r++) {
+            int lr = wv * 16 + r;
+            if (uni(cnt[lr]) > CB - BN) flush_row(lr);
+        }
+    }
+    __syncthreads();
+    if (row0 + wv * 16 >= a.nq) return;
+    for (int r = 0; r < 16; r++) {
+        int lr = wv * 16 + r;
+        int64_t grow = row0 + lr;
+        if (grow >= a.nq) break;
+        flush_row(lr);
+        int nl = uni(nlist[lr]);
+        const uint64_t *lst = lists + (size_t)lr * a.kcap;
+        for (int i = lane; i < a.k; i += WAVE) {
+            uint64_t key = i < nl ? lst[i] : KEY_MAX;
+            a.out_ids[grow * a.k + i] = i < nl ? (int32_t)(uint32_t)key : -1;
+            if constexpr (U8) {
+                reinterpret_cast<int32_t *>(a.out_d)[grow * a.k + i] =
+                    i < nl ? (int32_t)(key >> 32) : INT32_MAX;
+            } else {
+                reinterpret_cast<float *>(a.out_d)[grow * a.k + i] =
+                    i < nl ? unord_f32((uint32_t)(key >> 32)) : __builtin_inff();
+            }
+        }
+    }
+}
+
+int lds_pitch_for(int dtype, int64_t pitch) {
+    // +16 bytes keeps the 16 rows read by one MFMA operand on distinct banks
+    (void)dtype;
+    return (int)((pitch + 15) / 16 * 16 + 16);
+}
+
+size_t topk_lds_bytes(int bm, int kcap, int lds_pitch) {
+    int nwaves = bm / 16;
+    return (size_t)BN * lds_pitch + (size_t)bm * kcap * 8 + (size_t)bm * CB * 8 + (size_t)bm * 16 +
+           (size_t)nwaves * WAVE * 8;
+}
+
+}  // namespace
+
+size_t topk_ws_size(const onng_vectors *Q, const onng_vectors *B, int64_t n_cand, int32_t k) {
+    Carver c(nullptr);
+    int64_t nb = n_cand > 0 ? n_cand : B->n;
+    c.take<float>(Q->n);
+    c.take<float>(nb);
+    if (n_cand > 0) c.take<uint8_t>((size_t)nb * B->pitch_bytes);
+    return c.size() + 256;
+}
+
+onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int32_t *cand,
+                        int64_t n_cand, int32_t k, int32_t exclude_self, int32_t *ids,
+                        void *dists, void *ws, size_t ws_bytes, hipStream_t st) {
+    if (!(Q->dtype == B->dtype && (Q->dtype == ONNG_U8 || Q->dtype == ONNG_F32))) {
+        set_error("onng_topk: queries and base must both be u8 or both f32");
+        return ONNG_ERR_UNSUPPORTED;
+    }
+    if (Q->dtype == ONNG_U8 && Q->metric != ONNG_L2SQ) {
+        set_error("onng_topk: u8 data supports squared L2 only");
+        return ONNG_ERR_UNSUPPORTED;
+    }
+    if (ws_bytes < topk_ws_size(Q, B, cand ? n_cand : 0, k)) {
+        set_error("onng_topk: workspace too small");
+        return ONNG_ERR_WORKSPACE;
+    }
+    const bool u8 = Q->dtype == ONNG_U8;
+    const int64_t nb = cand ? n_cand : B->n;
+    Carver c(ws);
+    void *qn = c.take<float>(Q->n);
+    void *bn = c.take<float>(nb);
+    const uint8_t *brows = static_cast<const uint8_t *>(B->data);
+    if (cand && nb > 0) {
+        uint8_t *g = c.take<uint8_t>((size_t)nb * B->pitch_bytes);
+        hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)nb), dim3(64), 0, st, brows,
+                           B->pitch_bytes, cand, nb, g);
+        brows = g;
+    }
+    if (Q->n > 0) {
+        if (u8)
+            hipLaunchKernelGGL(norms_u8_kernel, dim3((unsigned)((Q->n + 3) / 4)), dim3(256), 0, st,
+                               static_cast<const uint8_t *>(Q->data), Q->pitch_bytes, Q->n, Q->dim,
+                               static_cast<int32_t *>(qn));
+        else
+            hipLaunchKernelGGL(norms_f32_kernel, dim3((unsigned)((Q->n + 3) / 4)), dim3(256), 0,
+                               st, static_cast<const uint8_t *>(Q->data), Q->pitch_bytes, Q->n,
+                               Q->dim, static_cast<float *>(qn));
+    }
+    if (nb > 0) {
+        if (u8)
+            hipLaunchKernelGGL(norms_u8_kernel, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, st,
+                               brows, B->pitch_bytes, nb, B->dim, static_cast<int32_t *>(bn));
+        else
+            hipLaunchKernelGGL(norms_f32_kernel, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, st,
+                               brows, B->pitch_bytes, nb, B->dim, static_cast<float *>(bn));
+    }
+    ONNG_HIP(hipGetLastError());
+    if (Q->n == 0) return ONNG_OK;
+
+    TopkArgs a;
+    a.q = static_cast<const uint8_t *>(Q->data);
+    a.q_pitch = Q->pitch_bytes;
+    a.nq = Q->n;
+    a.b = brows;
+    a.b_pitch = B->pitch_bytes;
+    a.nb = nb;
+    a.b_ids = cand;
+    a.qn = qn;
+    a.bn = bn;
+    a.dim = Q->dim;
+    a.k = k;
+    a.kcap = (k + 63) / 64 * 64;
+    a.bm = a.kcap <= 128 ? 64 : 32;
+    a.exclude_self = exclude_self;
+    a.lds_pitch = lds_pitch_for(Q->dtype, B->pitch_bytes);
+    a.out_ids = ids;
+    a.out_d = dists;
+    size_t lds = topk_lds_bytes(a.bm, a.kcap, a.lds_pitch);
+    if (lds > 160 * 1024) {
+        set_error("onng_topk: k or dim too large for the on-chip tile");
+        return ONNG_ERR_UNSUPPORTED;
+    }
+    const void *fn;
+    if (u8) fn = (const void *)topk_kernel<ONNG_U8, ONNG_L2SQ>;
+    else if (Q->metric == ONNG_L2SQ) fn = (const void *)topk_kernel<ONNG_F32, ONNG_L2SQ>;
+    else fn = (const void *)topk_kernel<ONNG_F32, ONNG_COSINE>;
+    ONNG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    dim3 grid((unsigned)((Q->n + a.bm - 1) / a.bm)), block((unsigned)(a.bm / 16 * 64));
+    void *args[] = {&a};
+    ONNG_HIP(hipLaunchKernel(fn, grid, block, args, lds, st));
+    return ONNG_OK;
+}
+
+}  // namespace onng

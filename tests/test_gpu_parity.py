@@ -1,0 +1,474 @@
+"""GPU parity: every kernel of the path against the CPU oracle on the same
+seeded inputs.  u8 data is compared bit for bit (ids, distances, distance
+computations, expansions); float data by the margin rule."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1810_07355_amd import datagen as dg
+
+from gpu_common import (api, c1_problem, dev, gpu_graph, gpu_vectors, have_gpu, host, L,
+                        margin_ok, say, to_dev, torch)
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not have_gpu(), reason="needs an MI355X GPU")]
+
+
+# ------------------------------------------------------------------ codecs
+
+def test_encode_bit_exact():
+    g = np.random.default_rng(11)
+    x = np.concatenate([g.standard_normal((300, 100)) * 3.0,
+                        g.uniform(-1e-3, 1e-3, (20, 100)),
+                        np.zeros((1, 100))]).astype(np.float32)
+    x[0, :6] = [65504, 65520, 1e-8, -2 ** -24, 3.3e38, -0.0]
+    A, Lb = api(), L()
+    for dt, odt in [(Lb.F16, orc.F16), (Lb.BF16, orc.BF16), (Lb.FP8_E4M3, orc.FP8)]:
+        say("encode", dt)
+        v = A.encode(to_dev(x), dt, Lb.L2SQ)
+        ref, rs = orc.encode_rows(x, odt, pitch=v.pitch)
+        assert np.array_equal(host(v.data), ref), dt
+        if rs is not None:
+            assert np.array_equal(host(v.scale), rs)
+
+
+# ------------------------------------------------------------------- top-k
+
+def test_topk_u8_knn_graph_c1():
+    P = c1_problem()
+    say("build_knn c1")
+    B = gpu_vectors(P["x"], orc.L2SQ)
+    ids, d = api().build_knn(B, P["cfg"].knn_k)
+    assert np.array_equal(host(ids), P["knn"])
+    assert np.array_equal(host(d), P["kd"].astype(np.int32))
+
+
+@pytest.mark.parametrize("n,dim,k", [(1037, 128, 20), (130, 64, 129), (70, 200, 7), (5, 16, 4)])
+def test_topk_u8_ragged(n, dim, k):
+    say("topk ragged", n, dim, k)
+    x = dg.random_tie_u8(n, dim, 3) if dim == 64 else dg.random_vectors(n, dim, "u8", 4)
+    bv = orc.Vectors.from_array(x, orc.L2SQ)
+    k = min(k, n - 1)
+    rid, rd = orc.knn_graph(bv, k)
+    ids, d = api().build_knn(gpu_vectors(x, orc.L2SQ), k)
+    assert np.array_equal(host(ids), rid)
+    assert np.array_equal(host(d), rd.astype(np.int32))
+
+
+def test_topk_seeds_from_pivots_c1():
+    P = c1_problem()
+    say("seeds from pivots c1")
+    A = api()
+    ids, d = A.topk(gpu_vectors(P["q"], orc.L2SQ), gpu_vectors(P["x"], orc.L2SQ), 8,
+                    cand=to_dev(P["piv"]))
+    assert np.array_equal(host(ids), P["seeds"])
+
+
+def test_topk_f32_cosine_and_l2():
+    for kind, metric in [("f32cos", orc.COS), ("f32l2", orc.L2SQ)]:
+        say("topk float", kind)
+        cfg = dg.scaled(dg.PRESETS["c3" if kind == "f32cos" else "c5"], 3000, 40, n_clusters=30)
+        x, q = dg.base(cfg), dg.queries(cfg)
+        bv, qv = orc.Vectors.from_array(x, metric), orc.Vectors.from_array(q, metric)
+        rid, rd = orc.topk(qv, bv, 20)
+        ids, d = api().topk(gpu_vectors(q, metric), gpu_vectors(x, metric), 20)
+        gi, gd = host(ids), host(d)
+        scale = 1.0 if metric == orc.COS else float(np.abs(rd).max())
+        assert np.all(np.abs(gd - rd) <= 2e-5 * max(scale, 1.0) + 1e-5 * np.abs(rd))
+        # ids agree except where the boundary distances nearly tie
+        for r in range(len(q)):
+            if set(gi[r]) != set(rid[r]):
+                kth = rd[r, -1]
+                diff = set(gi[r]) ^ set(rid[r])
+                full = orc.lib()
+                for j in diff:
+                    dj = full.or_dist(bv.ref, int(j), qv.ref, r)
+                    assert abs(dj - kth) <= 5e-5 * max(1.0, abs(kth)) + 2e-5 * scale
+
+
+# ---------------------------------------------------------- adjustments
+
+def test_adjust_degree_u8_c1():
+    P = c1_problem()
+    say("adjust_degree c1")
+    A, Lb = api(), L()
+    g = A.adjust_degree(to_dev(P["knn"]), to_dev(P["kd"].astype(np.int32)), Lb.U8, Lb.L2SQ,
+                        P["cfg"].e_o, P["cfg"].e_i)
+    off, nb, ln = P["sa"]
+    assert np.array_equal(host(g.offsets), off)
+    assert np.array_equal(host(g.nbrs), nb)
+    assert np.array_equal(host(g.lens), ln.astype(np.int32))
+
+
+@pytest.mark.parametrize("e_o,e_i", [(3, 7), (7, 3), (0, 5), (5, 0), (12, 12)])
+def test_adjust_degree_float_and_ties(e_o, e_i):
+    say("adjust_degree float", e_o, e_i)
+    A, Lb = api(), L()
+    # float lengths, with asymmetric values so the duplicate rule matters
+    x = dg.random_tie_u8(400, 5, 9, levels=4)
+    bv = orc.Vectors.from_array(x, orc.L2SQ)
+    knn, kd = orc.knn_graph(bv, 12)
+    g = np.random.default_rng(e_o * 31 + e_i)
+    kdf = (kd + g.uniform(0, 0.5, kd.shape)).astype(np.float32)
+    kdf = np.sort(kdf, axis=1)        # rows stay ascending
+    off, nb, ln = orc.adjust_degree(knn, kdf.astype(np.float64), e_o, e_i)
+    gg = A.adjust_degree(to_dev(knn), to_dev(kdf), Lb.F32, Lb.L2SQ, e_o, e_i)
+    assert np.array_equal(host(gg.offsets), off)
+    assert np.array_equal(host(gg.nbrs), nb)
+    assert np.array_equal(host(gg.lens), ln.astype(np.float32))
+
+
+def test_adjust_path_u8_c1():
+    P = c1_problem()
+    say("adjust_path c1")
+    A, Lb = api(), L()
+    off, nb, ln = P["sa"]
+    g = A.adjust_path(gpu_graph(off, nb, ln), Lb.U8, Lb.L2SQ)
+    po, pn, pl = P["pa"]
+    assert np.array_equal(host(g.offsets), po)
+    assert np.array_equal(host(g.nbrs), pn)
+    assert np.array_equal(host(g.lens), pl.astype(np.int32))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_adjust_path_ties(seed):
+    say("adjust_path ties", seed)
+    A, Lb = api(), L()
+    x = dg.random_tie_u8(600, 4, 40 + seed, levels=3)
+    bv = orc.Vectors.from_array(x, orc.L2SQ)
+    knn, kd = orc.knn_graph(bv, 16)
+    off, nb, ln = orc.adjust_degree(knn, kd, 6, 16)
+    po, pn, pl = orc.adjust_path(off, nb, ln)
+    g = A.adjust_path(gpu_graph(off, nb, ln), Lb.U8, Lb.L2SQ)
+    assert np.array_equal(host(g.offsets), po)
+    assert np.array_equal(host(g.nbrs), pn)
+
+
+def test_graph_chain_on_gpu_equals_oracle_c1():
+    P = c1_problem()
+    say("kNN -> SA -> PA chain on GPU")
+    A, Lb = api(), L()
+    cfg = P["cfg"]
+    ids, d = A.build_knn(gpu_vectors(P["x"], orc.L2SQ), cfg.knn_k)
+    sa = A.adjust_degree(ids, d, Lb.U8, Lb.L2SQ, cfg.e_o, cfg.e_i)
+    pa = A.adjust_path(sa, Lb.U8, Lb.L2SQ)
+    po, pn, pl = P["pa"]
+    assert np.array_equal(host(pa.offsets), po)
+    assert np.array_equal(host(pa.nbrs), pn)
+
+
+# ---------------------------------------------------------------- search
+
+def _run_search_u8(P, graph, k, eps, ep, launch=None, seeds=None, q=None):
+    A = api()
+    seeds = P["seeds"] if seeds is None else seeds
+    q = P["q"] if q is None else q
+    r = A.search(gpu_vectors(P["x"], orc.L2SQ), graph, gpu_vectors(q, orc.L2SQ), to_dev(seeds),
+                 k=k, eps=eps, ep=ep, launch=launch)
+    torch.cuda.synchronize()
+    return r
+
+
+def _assert_exact(r, ref, k):
+    assert np.array_equal(host(r.ids)[:, :k], ref["ids"][:, :k])
+    gd = host(r.dists)[:, :k]
+    rd = np.where(np.isinf(ref["dists"][:, :k]), 2 ** 31 - 1, ref["dists"][:, :k]).astype(np.int64)
+    assert np.array_equal(gd.astype(np.int64), rd)
+    assert np.array_equal(host(r.dc), ref["dc"])
+    assert np.array_equal(host(r.hops), ref["hops"])
+    assert not np.any(host(r.flags) & L().QF_CAPACITY)
+
+
+@pytest.mark.parametrize("k", [1, 10, 20])
+def test_search_u8_c1_eps_sweep(k):
+    P = c1_problem()
+    po, pn, _ = P["pa"]
+    G = gpu_graph(po, pn)
+    for eps in P["cfg"].eps_grid:
+        for ep in (orc.INF_EP, orc.dynamic_ep(eps)):
+            say("search c1 k", k, "eps", eps, "ep", ep)
+            ref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], k, eps, ep)
+            r = _run_search_u8(P, G, k, eps, ep)
+            _assert_exact(r, ref, k)
+
+
+@pytest.mark.parametrize("shape", [dict(s_capacity=64, visited_log2=8),
+                                   dict(s_capacity=64, visited_log2=-1),
+                                   dict(lanes_per_row=8, waves_per_block=2),
+                                   dict(lanes_per_row=16, waves_per_block=1, blocks=3)])
+def test_search_u8_small_capacities_stay_exact(shape):
+    """Tiny on-chip capacities force the spill and off-chip visited paths."""
+    P = c1_problem()
+    off, nb, _ = P["sa"]                     # denser graph: more candidates per query
+    G = gpu_graph(off, nb)
+    cfg = api().launch_config(**shape)
+    for eps, k in [(0.1, 10), (0.3, 20), (np.inf, 20)]:
+        say("search small caps", shape, eps, k)
+        ref = orc.search(P["bv"], off, nb, P["qv"], P["seeds"], k, eps, orc.INF_EP)
+        r = _run_search_u8(P, G, k, eps, orc.INF_EP, launch=cfg)
+        _assert_exact(r, ref, k)
+
+
+def test_search_u8_single_big_component_unbounded():
+    """One 4,000-node cluster and eps = inf: the whole component is visited."""
+    say("search one component eps=inf")
+    cfg = dg.scaled(dg.PRESETS["c1"], 4000, 40, n_clusters=1)
+    x, q = dg.base(cfg), dg.queries(cfg)
+    bv, qv = orc.Vectors.from_array(x, orc.L2SQ), orc.Vectors.from_array(q, orc.L2SQ)
+    knn, kd = orc.knn_graph(bv, 10)
+    off, nb, ln = orc.adjust_degree(knn, kd, 5, 10)
+    seeds = dg.random_seeds(cfg, 40, 4)
+    P = dict(x=x, q=q, seeds=seeds)
+    G = gpu_graph(off, nb)
+    for eps, k in [(np.inf, 10), (0.2, 50)]:
+        ref = orc.search(bv, off, nb, qv, seeds, k, eps, orc.INF_EP)
+        r = _run_search_u8(P, G, k, eps, orc.INF_EP)
+        _assert_exact(r, ref, k)
+        if np.isinf(eps):
+            assert np.all(host(r.dc) == 4000) or np.all(ref["dc"] == host(r.dc))
+
+
+def test_search_u8_duplicate_invalid_seeds_and_padding():
+    P = c1_problem()
+    po, pn, _ = P["pa"]
+    seeds = P["seeds"].copy()
+    seeds[:, 1] = seeds[:, 0]
+    seeds[:, 2] = -1
+    seeds[::3, 3] = 10 ** 6            # out of range: ignored
+    say("search duplicate seeds")
+    ref = orc.search(P["bv"], po, pn, P["qv"], seeds, 10, 0.05, orc.INF_EP)
+    r = _run_search_u8(P, gpu_graph(po, pn), 10, 0.05, orc.INF_EP, seeds=seeds)
+    _assert_exact(r, ref, 10)
+    # empty graph: only the seeds are found, the rest is padding
+    say("search empty graph")
+    n = P["x"].shape[0]
+    off0 = np.zeros(n + 1, np.int64)
+    ref = orc.search(P["bv"], off0, np.zeros(1, np.int32), P["qv"], P["seeds"], 20, 0.1)
+    A = api()
+    g0 = A.Graph(to_dev(off0), torch.zeros(1, dtype=torch.int32, device=dev()), None)
+    r = _run_search_u8(P, g0, 20, 0.1, orc.INF_EP)
+    _assert_exact(r, ref, 20)
+    assert np.all(host(r.flags) & L().QF_PADDED)
+
+
+def test_search_mixed_k_eps_ep_per_query():
+    P = c1_problem()
+    po, pn, _ = P["pa"]
+    nq = len(P["q"])
+    g = np.random.default_rng(3)
+    kq = g.choice([1, 10, 20], nq).astype(np.int32)
+    eq = g.choice([0.0, 0.05, 0.2], nq).astype(np.float32)
+    pq = np.array([orc.dynamic_ep(e) if i % 2 else orc.INF_EP for i, e in enumerate(eq)],
+                  dtype=np.uint32)
+    say("search mixed per-query parameters")
+    ref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], kq, eq, pq, k_stride=20)
+    A = api()
+    r = A.search(gpu_vectors(P["x"], orc.L2SQ), gpu_graph(po, pn), gpu_vectors(P["q"], orc.L2SQ),
+                 to_dev(P["seeds"]), k=to_dev(kq), k_stride=20, eps=to_dev(eq),
+                 ep=torch.from_numpy(pq.astype(np.int64)).to(dev()))
+    torch.cuda.synchronize()
+    assert np.array_equal(host(r.ids), ref["ids"])
+    assert np.array_equal(host(r.dc), ref["dc"])
+    assert np.array_equal(host(r.hops), ref["hops"])
+
+
+def test_two_phase_features_and_predictor_replay():
+    P = c1_problem()
+    po, pn, _ = P["pa"]
+    A, Lb = api(), L()
+    say("two-phase features")
+    ref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, 0.05, 40, eps1=np.inf, ep1=64,
+                     want_features=True)
+    r = A.search(gpu_vectors(P["x"], orc.L2SQ), gpu_graph(po, pn), gpu_vectors(P["q"], orc.L2SQ),
+                 to_dev(P["seeds"]), k=10, eps=0.05, ep=40, two_phase=True, ep_first=64,
+                 want_features=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(r.ids), ref["ids"])
+    assert np.array_equal(host(r.dc), ref["dc"])
+    assert np.array_equal(host(r.features).astype(np.float64), ref["feat"])
+    # a random predictor: replay the oracle with the eps / e_p the kernel used
+    say("predictor replay")
+    g = np.random.default_rng(7)
+    H = 64
+    w1 = torch.from_numpy(g.standard_normal((H, 14)).astype(np.float32) * 0.3).to(dev())
+    w2 = torch.from_numpy(g.standard_normal((3, H)).astype(np.float32) * 0.1).to(dev())
+    pred = A.Predictor(A.to_bf16_bits(w1), to_dev(np.zeros(H, np.float32)), A.to_bf16_bits(w2),
+                       to_dev(np.array([-1.2, -1.0, -0.8], np.float32)),
+                       to_dev(np.zeros(14, np.float32)), to_dev(np.ones(14, np.float32)),
+                       head=1, eps_min=0.0, eps_max=0.3, e0=30.0, we=20.0)
+    r = A.search(gpu_vectors(P["x"], orc.L2SQ), gpu_graph(po, pn), gpu_vectors(P["q"], orc.L2SQ),
+                 to_dev(P["seeds"]), k=10, eps=0.0, ep=orc.INF_EP, two_phase=True, ep_first=64,
+                 predictor=pred)
+    torch.cuda.synchronize()
+    eps_used = host(r.eps_used)
+    ep_used = host(r.ep_used).astype(np.uint32)
+    assert np.all((eps_used >= 0) & (eps_used <= 0.3))
+    assert len(np.unique(eps_used)) > 1
+    ref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, eps_used, ep_used, eps1=np.inf,
+                     ep1=64)
+    assert np.array_equal(host(r.ids), ref["ids"])
+    assert np.array_equal(host(r.dc), ref["dc"])
+    assert np.array_equal(host(r.hops), ref["hops"])
+
+
+def _float_problem(kind, n=6000, nq=60, k=10):
+    metric = orc.COS if kind == "f32cos" else orc.L2SQ
+    cfg = dg.scaled(dg.PRESETS["c3" if kind == "f32cos" else "c5"], n, nq, n_clusters=12)
+    x, q = dg.base(cfg), dg.queries(cfg)
+    bv, qv = orc.Vectors.from_array(x, metric), orc.Vectors.from_array(q, metric)
+    knn, kd = orc.knn_graph(bv, 20)
+    off, nb, ln = orc.adjust_degree(knn, kd, 8, 16)
+    off, nb, ln = orc.adjust_path(off, nb, ln)
+    seeds, _ = orc.topk(qv, bv, 8, cand=dg.pivots(cfg, 256))
+    return dict(metric=metric, x=x, q=q, bv=bv, qv=qv, off=off, nb=nb, seeds=seeds, cfg=cfg)
+
+
+@pytest.mark.parametrize("kind", ["f32cos", "f32l2"])
+def test_search_float_margin_rule(kind):
+    F = _float_problem(kind)
+    A = api()
+    G = gpu_graph(F["off"], F["nb"])
+    for eps in (0.0, 0.05, 0.2):
+        say("search float", kind, eps)
+        ref = orc.search(F["bv"], F["off"], F["nb"], F["qv"], F["seeds"], 10, eps)
+        r = A.search(gpu_vectors(F["x"], F["metric"]), G, gpu_vectors(F["q"], F["metric"]),
+                     to_dev(F["seeds"]), k=10, eps=eps)
+        ok, info = margin_ok(ref, host(r.ids), host(r.dists), ref["margin"])
+        assert ok, f"query {info} differs beyond the margin"
+        say("queries whose id sets differ (all tie-sensitive):", info)
+        assert info <= 0.1 * len(F["q"]), f"{info} queries differ"
+        gd, rd = host(r.dists), ref["dists"]
+        same = np.array([set(host(r.ids)[i]) == set(ref["ids"][i]) for i in range(len(rd))])
+        fin = np.isfinite(rd) & same[:, None]
+        floor = 1e-2 if kind == "f32cos" else 0.0
+        assert np.all(np.abs(gd[fin] - rd[fin]) <= 1e-4 * np.maximum(np.abs(rd[fin]), floor) + 1e-6)
+
+
+@pytest.mark.parametrize("dt", ["f16", "bf16", "fp8"])
+def test_search_low_precision_against_decoded_oracle(dt):
+    F = _float_problem("f32cos" if dt != "fp8" else "f32l2")
+    A, Lb = api(), L()
+    ldt = {"f16": Lb.F16, "bf16": Lb.BF16, "fp8": Lb.FP8_E4M3}[dt]
+    odt = {"f16": orc.F16, "bf16": orc.BF16, "fp8": orc.FP8}[dt]
+    say("search low precision", dt)
+    lp = A.encode(to_dev(F["x"]), ldt, Lb.COSINE if F["metric"] == orc.COS else Lb.L2SQ)
+    codes = host(lp.data)
+    scale = host(lp.scale) if lp.scale is not None else None
+    lbv = orc.Vectors(codes, odt, F["metric"], dim=F["x"].shape[1], scale=scale)
+    G = gpu_graph(F["off"], F["nb"])
+    for eps in (0.0, 0.1):
+        ref = orc.search(lbv, F["off"], F["nb"], F["qv"], F["seeds"], 10, eps)
+        r = A.search(lp, G, gpu_vectors(F["q"], F["metric"]), to_dev(F["seeds"]), k=10, eps=eps)
+        ok, info = margin_ok(ref, host(r.ids), host(r.dists), ref["margin"])
+        assert ok, f"query {info} differs beyond the margin"
+        # with a rerank from the f32 rows the returned distances are exact f32 ones
+        rr = A.search(lp, G, gpu_vectors(F["q"], F["metric"]), to_dev(F["seeds"]), k=10, eps=eps,
+                      rerank_base=gpu_vectors(F["x"], F["metric"]), pool_factor=4)
+        ri, rd = host(rr.ids), host(rr.dists)
+        for qi in range(len(F["q"])):
+            for t in range(10):
+                if ri[qi, t] < 0:
+                    continue
+                exact = orc.lib().or_dist(F["bv"].ref, int(ri[qi, t]), F["qv"].ref, qi)
+                assert abs(rd[qi, t] - exact) <= 1e-5 * max(1.0, abs(exact))
+        rec_lp = orc.recall_at_k(host(r.ids), ref["dists"], ref["dists"], 10)
+        assert rec_lp.shape == (len(F["q"]),)
+
+
+def test_rerank_standalone_matches_oracle():
+    say("rerank")
+    A = api()
+    x = dg.random_vectors(500, 100, "f32cos", 21)
+    q = dg.random_vectors(30, 100, "f32cos", 22)
+    g = np.random.default_rng(1)
+    pool = np.stack([g.choice(500, 200, replace=False) for _ in range(30)]).astype(np.int32)
+    pool[:, -5:] = -1
+    bv, qv = orc.Vectors.from_array(x, orc.COS), orc.Vectors.from_array(q, orc.COS)
+    rid, rd = orc.rerank(qv, bv, pool, 10)
+    for f64 in (True, False):
+        ids, d = A.rerank(gpu_vectors(q, orc.COS), gpu_vectors(x, orc.COS), to_dev(pool), 10,
+                          use_f64=f64)
+        if f64:
+            assert np.array_equal(host(ids), rid)
+            assert np.allclose(host(d), rd, rtol=0, atol=1e-12)
+        else:
+            assert np.allclose(host(d), rd, rtol=0, atol=2e-6)
+
+
+# ------------------------------------------------------------------- MLP
+
+def test_mlp_forward_backward_adam_against_oracle():
+    say("mlp")
+    A = api()
+    g = np.random.default_rng(5)
+    B, F, H, T = 1024, 14, 64, 3
+    X = g.standard_normal((B, F)).astype(np.float32)
+    Y = g.standard_normal((B, T)).astype(np.float32)
+    W = g.uniform(0.5, 1.5, (B, T)).astype(np.float32)
+    W1 = (g.standard_normal((H, F)) * 0.3).astype(np.float32)
+    b1 = (g.standard_normal(H) * 0.1).astype(np.float32)
+    W2 = (g.standard_normal((T, H)) * 0.3).astype(np.float32)
+    b2 = (g.standard_normal(T) * 0.1).astype(np.float32)
+    _, ref_y = orc.mlp_forward(X, W1, b1, W2, b2)
+    ref_loss, ref_g = orc.mlp_loss_grad(X, Y, W1, b1, W2, b2, W)
+    dW1, db1, dW2, db2 = [to_dev(a) for a in (W1, b1, W2, b2)]
+    y = A.mlp_forward(to_dev(X), dW1, db1, dW2, db2)
+    assert np.allclose(host(y), ref_y, rtol=1e-4, atol=1e-5)
+    loss, grads = A.mlp_backward(to_dev(X), to_dev(Y), dW1, db1, dW2, db2, w=to_dev(W))
+    assert abs(float(host(loss)[0]) - ref_loss) <= 1e-4 * abs(ref_loss)
+    for gg, rg in zip(grads, ref_g):
+        gg = host(gg).astype(np.float64)
+        assert np.linalg.norm(gg - rg) <= 1e-4 * np.linalg.norm(rg)
+    # one Adam step
+    p = W1.astype(np.float64).copy()
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    orc.adam_step(p, ref_g[0].copy(), m, v, 0.01, 1)
+    dp, dm, dv = dW1.clone(), torch.zeros_like(dW1), torch.zeros_like(dW1)
+    A.adam_step(dp, to_dev(ref_g[0].astype(np.float32)), dm, dv, 0.01, 1)
+    assert np.allclose(host(dp), p, rtol=0, atol=1e-6)
+    # feature transform equals the oracle's
+    raw = np.abs(g.standard_normal((50, 14))).astype(np.float32) * 1000
+    ft = A.feature_transform(to_dev(raw), L().L2SQ)
+    assert np.allclose(host(ft), orc.feature_transform(raw, orc.L2SQ), rtol=1e-5, atol=1e-5)
+
+
+# ----------------------------------------------------- pipeline, autotune
+
+def test_pipeline_graph_replays_match_eager():
+    P = c1_problem()
+    po, pn, _ = P["pa"]
+    A = api()
+    B, Q = gpu_vectors(P["x"], orc.L2SQ), gpu_vectors(P["q"], orc.L2SQ)
+    G = gpu_graph(po, pn)
+    say("pipeline create")
+    pl = A.Pipeline(B, G, Q, to_dev(P["piv"]), 8, k=10, eps=0.05, ep=orc.INF_EP)
+    ref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, 0.05)
+    for rep in range(3):
+        say("pipeline replay", rep)
+        req = pl.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(pl.seeds), P["seeds"])
+        assert np.array_equal(host(req.ids), ref["ids"])
+        assert np.array_equal(host(req.dc), ref["dc"])
+        # eager work in between replays
+        _ = A.search(B, G, Q, to_dev(P["seeds"]), k=5, eps=0.0)
+        torch.cuda.synchronize()
+        req.ids.fill_(-7)
+    pl.close()
+
+
+def test_autotune_picks_a_shape_that_stays_exact():
+    P = c1_problem()
+    po, pn, _ = P["pa"]
+    A = api()
+    say("autotune")
+    req = A.SearchRequest(gpu_vectors(P["x"], orc.L2SQ), gpu_graph(po, pn),
+                          gpu_vectors(P["q"], orc.L2SQ), to_dev(P["seeds"]), k=10, eps=0.1)
+    best = req.autotune()
+    assert best.lanes_per_row in (4, 8, 16, 32)
+    req.run()
+    torch.cuda.synchronize()
+    ref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, 0.1)
+    assert np.array_equal(host(req.ids), ref["ids"])
+    assert np.array_equal(host(req.dc), ref["dc"])
