@@ -1,0 +1,394 @@
+#!/usr/bin/env python3
+"""Throughput of batched adjusted-kNN-graph search on one MI355X.
+
+Metric: queries/sec at mean recall@10 = 0.95 and 0.99, learned search range
+with low-precision storage against plain f32 search, both on this GPU.
+
+Default workload (c3): 1,000,000 base + 10,000 query unit vectors, dim 100,
+cosine distance, 2,000 von Mises-Fisher-like clusters with Zipf(1.1) sizes
+(synthetic stand-in for the paper's GloVe sets), 100,000 training queries.
+The index is built on the GPU (exact kNN k=100 on the matrix cores, static
+degree adjustment e_o=20/e_i=60, path adjustment) before any timing.
+
+A step is one pass of the query path over the 10,000 queries: seed
+selection (nearest of the pivots), search with the learned range, and the
+exact f32 rerank, replayed from one captured HIP graph.  Rank 0 prints one
+JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+T0 = time.time()
+
+
+def log(*a):
+    print(f"[bench {time.time() - T0:7.1f}s]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2"])
+    ap.add_argument("--n-base", type=int, default=None, help="smaller base for quick runs")
+    ap.add_argument("--n-train", type=int, default=None)
+    ap.add_argument("--lp", default="f16", choices=["f16", "bf16", "fp8"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--dump", default=None, help="save per-query sweep data (.npz)")
+    ap.add_argument("--search-only", action="store_true",
+                    help="after the index and operating points, only loop the search kernel "
+                         "(used under rocprofv3)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the search shards by "
+              "query or by base (see the design notes), which this build does not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1810_07355_amd import _lib as L
+    from paper_1810_07355_amd import api as A
+    from paper_1810_07355_amd import datagen as dg
+    from paper_1810_07355_amd import learned as LR
+
+    dev = torch.device("cuda:0")
+    cfg = dg.PRESETS[args.workload]
+    if args.n_base:
+        ratio = args.n_base / cfg.n_base
+        cfg = dg.scaled(cfg, args.n_base, cfg.n_query,
+                        n_clusters=max(10, int(cfg.n_clusters * ratio)),
+                        n_train=args.n_train or cfg.n_train)
+    elif args.n_train:
+        cfg = dg.scaled(cfg, cfg.n_base, cfg.n_query, n_train=args.n_train)
+    if cfg.n_train == 0:     # c2 shares its data with c4, which has training queries
+        cfg = dg.scaled(cfg, cfg.n_base, cfg.n_query, n_train=args.n_train or 100_000)
+    is_u8 = cfg.kind == "u8"
+    metric = L.L2SQ if cfg.kind != "f32cos" else L.COSINE
+    K = 10
+    NS = 8
+    grid = [0.0, 0.005, 0.01, 0.02, 0.03, 0.05, 0.07, 0.1, 0.15, 0.2, 0.3, 0.4, 0.6, 1.0]
+    targets = (0.9, 0.95, 0.99)
+
+    # ------------------------------------------------------------ inputs --
+    log("generating", cfg.name, cfg.n_base, "x", cfg.dim, cfg.kind)
+    x = dg.base(cfg)
+    q = dg.queries(cfg)
+    xt = torch.from_numpy(x).to(dev)
+    qt = torch.from_numpy(q).to(dev)
+    base = A.Vectors.from_tensor(xt, metric)
+    queries = A.Vectors.from_tensor(qt, metric)
+    piv = torch.from_numpy(dg.pivots(cfg)).to(dev)
+
+    # ------------------------------------------------------- index build --
+    build = {}
+
+    def timed(name, fn):
+        torch.cuda.synchronize()
+        t = time.time()
+        out = fn()
+        torch.cuda.synchronize()
+        build[name] = round(time.time() - t, 3)
+        log(f"{name}: {build[name]} s")
+        return out
+
+    ids, d = timed("knn_s", lambda: A.build_knn(base, cfg.knn_k))
+    sa = timed("adjust_degree_s", lambda: A.adjust_degree(ids, d, base.dtype, metric, cfg.e_o,
+                                                          cfg.e_i))
+    graph = timed("adjust_path_s", lambda: A.adjust_path(sa, base.dtype, metric))
+    del ids, d
+    log(f"edges: SA {sa.nnz}, PA {graph.nnz} (mean outdegree {graph.nnz / cfg.n_base:.1f})")
+    del sa
+    seeds, _ = A.topk(queries, base, NS, cand=piv)
+    gt_ids, _ = timed("ground_truth_s", lambda: A.ground_truth(queries, base, K))
+    gt = gt_ids.cpu().numpy()
+
+    # ------------------------------------------- operating points (recall) --
+    def time_req(req, reps=3):
+        req.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ts = []
+        for _ in range(reps):
+            e0.record()
+            req.run()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    def measure(make, knob, name, timing=True):
+        req = make(knob)
+        if timing:
+            ms = time_req(req)
+        else:
+            req.run()
+            torch.cuda.synchronize()
+            ms = float("nan")
+        rec = float(LR.recall_by_ids(req.ids.cpu().numpy(), gt, K).mean())
+        pt = dict(knob=round(float(knob), 5), recall=rec, ms=ms, qps=queries.n / (ms / 1e3),
+                  dc=float(req.dc.float().mean()), eps_mean=float(req.eps_used.mean()))
+        log(f"{name:>14} knob={knob:+.4f} recall={rec:.4f} dc={pt['dc']:8.1f} {ms:8.2f} ms "
+            f"{pt['qps']:12.0f} q/s")
+        return pt
+
+    def bisect(make, target, lo, hi, name, iters=9):
+        """Smallest knob in [lo, hi] whose mean recall reaches target (the
+        paper finds its search ranges the same way, by binary search)."""
+        top = measure(make, hi, name, timing=False)
+        if top["recall"] < target:
+            return None
+        for _ in range(iters):
+            mid = 0.5 * (lo + hi)
+            if measure(make, mid, name, timing=False)["recall"] >= target:
+                hi = mid
+            else:
+                lo = mid
+        return measure(make, hi, name)
+
+    curve_eps = [0.0, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3]
+    make_plain = lambda e: A.SearchRequest(base, graph, queries, seeds, k=K, eps=e,
+                                           ep=LR.dynamic_ep(e))
+    curve = {"plain": [measure(make_plain, e, "plain") for e in curve_eps]}
+    result = {"plain": {str(t): bisect(make_plain, t, 0.0, 1.0, "plain") for t in (0.95, 0.99)}}
+
+    lp_rows = None
+    learned_pts = {}
+    if not is_u8:
+        lp_dt = {"f16": L.F16, "bf16": L.BF16, "fp8": L.FP8_E4M3}[args.lp]
+        lp_rows = A.encode(xt, lp_dt, metric)
+        make_lp = lambda e: A.SearchRequest(lp_rows, graph, queries, seeds, k=K, eps=e,
+                                            ep=LR.dynamic_ep(e), rerank_base=base, pool_factor=4)
+        curve["lp"] = [measure(make_lp, e, args.lp + "+rerank") for e in curve_eps]
+        result["lp"] = {str(t): bisect(make_lp, t, 0.0, 1.0, args.lp + "+rerank")
+                        for t in (0.95, 0.99)}
+
+    # ------------------------------------------------- learned search range --
+    EPF = 64
+    search_rows = lp_rows if lp_rows is not None else base
+    rr = dict(rerank_base=base, pool_factor=4) if lp_rows is not None else {}
+    tq_np = dg.train_queries(cfg)
+    log("training queries:", len(tq_np))
+    tq = A.Vectors.from_tensor(torch.from_numpy(tq_np).to(dev), metric)
+    tseeds, _ = A.topk(tq, base, NS, cand=piv)
+    tgt_ids, _ = A.ground_truth(tq, base, K)
+    tgt_np = tgt_ids.cpu().numpy()
+
+    def label_sweep(vq, vseeds, vgt):
+        feats, recs, dcs = None, [], []
+        for i, eps in enumerate(grid):
+            req = A.SearchRequest(search_rows, graph, vq, vseeds, k=K, eps=eps,
+                                  ep=LR.dynamic_ep(eps), two_phase=True, ep_first=EPF,
+                                  want_features=(i == 0), **rr)
+            req.run()
+            torch.cuda.synchronize()
+            if i == 0:
+                feats = req.features.clone()
+            recs.append(LR.recall_by_ids(req.ids.cpu().numpy(), vgt, K))
+            dcs.append(req.dc.cpu().numpy())
+        return feats, np.stack(recs), np.stack(dcs)
+
+    t_lab = time.time()
+    feats, recalls, dcs = label_sweep(tq, tseeds, tgt_np)
+    labels = LR.labels_from_recalls(recalls, grid, targets)
+    log(f"labels from {len(grid)}-point sweep over {len(tq_np)} queries in "
+        f"{time.time() - t_lab:.1f} s; mean label eps per target "
+        f"{labels.mean(axis=0).round(4).tolist()}")
+    if args.dump:
+        hf, hr, hd = label_sweep(queries, seeds, gt)
+        np.savez_compressed(args.dump, grid=np.array(grid), train_feat=feats.cpu().numpy(),
+                            train_recall=recalls, train_dc=dcs, test_feat=hf.cpu().numpy(),
+                            test_recall=hr, test_dc=hd)
+        log("dumped sweep data to", args.dump)
+    t_tr = time.time()
+    model = LR.train(feats, labels, metric, steps=3000)
+    log(f"trained predictor in {time.time() - t_tr:.1f} s; loss {model.losses[0]:.4f} -> "
+        f"{model.losses[-1]:.4f}")
+
+    def make_learned(head):
+        def make(shift):
+            sh = torch.zeros(len(targets), dtype=torch.float32, device=dev)
+            sh[head] = float(shift)
+            pred = model.predictor(head=head, shift=sh, eps_min=0.0, eps_max=max(grid))
+            req = A.SearchRequest(search_rows, graph, queries, seeds, k=K, eps=0.0, ep=L.EP_INF,
+                                  two_phase=True, ep_first=EPF, predictor=pred, **rr)
+            req._pred = pred
+            return req
+        return make
+
+    for tgt in (0.95, 0.99):
+        head = targets.index(tgt)
+        learned_pts[str(tgt)] = bisect(make_learned(head), tgt, -1.5, 1.5, f"learned@{tgt}")
+    result["learned"] = learned_pts
+    shifts = {t: (learned_pts[str(t)]["knob"] if learned_pts[str(t)] else 1.5)
+              for t in (0.95, 0.99)}
+
+    # ----------------------------------------------- timed region (graph) --
+    head95 = targets.index(0.95)
+    sh = torch.zeros(len(targets), dtype=torch.float32, device=dev)
+    sh[head95] = shifts[0.95]
+    pred95 = model.predictor(head=head95, shift=sh, eps_min=0.0, eps_max=max(grid))
+    pipe = A.Pipeline(search_rows, graph, queries, piv, NS, k=K, eps=0.0, ep=L.EP_INF,
+                      two_phase=True, ep_first=EPF, predictor=pred95, **rr)
+    plain95 = result["plain"]["0.95"]
+    pipe_plain = None
+    if plain95 is not None:
+        pipe_plain = A.Pipeline(base, graph, queries, piv, NS, k=K, eps=plain95["knob"],
+                                ep=LR.dynamic_ep(plain95["knob"]))
+
+    if args.search_only:
+        req = make_learned(head95)(shifts[0.95])
+        for _ in range(args.warmup + args.steps):
+            req.run()
+        torch.cuda.synchronize()
+        log("search-only loop done")
+        return
+
+    for _ in range(args.warmup):
+        pipe.launch()
+    torch.cuda.synchronize()
+    t = time.time()
+    for _ in range(args.steps):
+        req = pipe.launch()
+    torch.cuda.synchronize()
+    wall = time.time() - t
+    ms_step = wall * 1e3 / args.steps
+    value = queries.n / (ms_step / 1e3)
+    rec95 = float(LR.recall_by_ids(req.ids.cpu().numpy(), gt, K).mean())
+    log(f"timed: {args.steps} steps, {ms_step:.2f} ms/step, {value:.0f} q/s, recall {rec95:.4f}")
+
+    plain_pipe_qps = None
+    if pipe_plain is not None:
+        for _ in range(args.warmup):
+            pipe_plain.launch()
+        torch.cuda.synchronize()
+        t = time.time()
+        for _ in range(args.steps):
+            rp = pipe_plain.launch()
+        torch.cuda.synchronize()
+        plain_pipe_qps = queries.n / ((time.time() - t) / args.steps)
+        log(f"plain f32 pipeline at eps={plain95['knob']}: {plain_pipe_qps:.0f} q/s")
+
+    # ---------------------------------------- roofline of the search kernel --
+    req = make_learned(head95)(shifts[0.95])
+    ms_search = time_req(req, reps=5)
+    st = req.stats.cpu().numpy()
+    dc, hops, scanned = st[:, 0].astype(np.float64), st[:, 1].astype(np.float64), st[:, 5].astype(np.float64)
+    dim = cfg.dim
+    row_bytes = {L.U8: dim, L.F32: 4 * dim, L.F16: 2 * dim, L.BF16: 2 * dim,
+                 L.FP8_E4M3: dim + 4}[search_rows.dtype]
+    q_bytes = dim if is_u8 else 4 * dim
+    pool = np.minimum(dc, 4 * K) if lp_rows is not None else 0
+    per_query = (q_bytes + 4 * NS + 16 * hops + 4 * scanned + row_bytes * dc
+                 + (4 * dim) * pool + 8 * K + 32)
+    bytes_launch = float(per_query.sum())
+    achieved = bytes_launch / (ms_search / 1e3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=8000.0, unit="GB/s",
+                    frac=round(achieved / 8000.0, 4), traffic=None,
+                    kernel="search_kernel", bytes_per_launch=bytes_launch,
+                    ms_per_launch=round(ms_search, 4),
+                    bytes_per_query_mean=round(float(per_query.mean()), 1))
+    log(f"search kernel: {ms_search:.3f} ms, {bytes_launch / 1e6:.1f} MB algorithmic, "
+        f"{achieved:.0f} GB/s ({achieved / 8000:.1%} of 8 TB/s)")
+
+    # ----------------------------------------------------- CPU oracle leg --
+    cpu = None
+    if not args.no_cpu_baseline and plain95 is not None:
+        from oracle import oracle as orc
+        off = graph.offsets.cpu().numpy()
+        nb = graph.nbrs.cpu().numpy()
+        sd = seeds.cpu().numpy()
+        bv = orc.Vectors.from_array(x, orc.COS if metric == L.COSINE else orc.L2SQ)
+        qv_all = q
+        eps0 = plain95["knob"]
+        ep0 = LR.dynamic_ep(eps0)
+        thr = orc.nthreads()
+        n = 64
+        spent = 0.0
+        done = 0
+        while spent < args.cpu_seconds and done < len(q):
+            m = min(n, len(q) - done)
+            qv = orc.Vectors.from_array(qv_all[done:done + m], bv.metric)
+            t = time.time()
+            orc.search(bv, off, nb, qv, sd[done:done + m], K, eps0, ep0, threads=thr)
+            spent += time.time() - t
+            done += m
+            n = min(4 * n, 4096)
+        cpu = dict(value=round(done / spent, 1), unit="queries/s", cores=thr, kind="oracle",
+                   sample=f"first {done} queries of the workload, plain f32 search at "
+                          f"eps={eps0} (the f32 operating point for recall 0.95), fp64 "
+                          f"distances, {thr} threads")
+        log(f"cpu oracle: {done} queries in {spent:.1f} s on {thr} threads")
+
+    def qps_of(pt):
+        return round(pt["qps"], 1) if pt else None
+
+    out = {
+        "metric": "queries/sec at recall@10 = 0.95 and 0.99, learned+low-precision vs plain FP32",
+        "value": round(value, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8/int32" if is_u8 else "f32",
+        "storage": "u8" if is_u8 else args.lp,
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{cfg.name}: {cfg.n_base:,} base + {cfg.n_query:,} queries, dim "
+                         f"{cfg.dim}, {cfg.kind}, {cfg.n_clusters} clusters; kNN k={cfg.knn_k}, "
+                         f"e_o={cfg.e_o}/e_i={cfg.e_i}, path adjustment; k={K}, {NS} seeds "
+                         f"from {piv.numel()} pivots; learned eps for recall 0.95, "
+                         f"{args.lp if not is_u8 else 'u8'} rows + f32 rerank of 4k"),
+            "global_batch": cfg.n_query,
+        },
+        "recall_at_timed_point": round(rec95, 4),
+        "qps": {
+            "learned_lp@0.95": round(value, 1),
+            "learned_lp@0.99": qps_of(learned_pts.get("0.99")),
+            "plain_f32@0.95": qps_of(plain95),
+            "plain_f32@0.99": qps_of(result["plain"]["0.99"]),
+            "plain_f32_pipeline@0.95": round(plain_pipe_qps, 1) if plain_pipe_qps else None,
+            "lp_fixed_eps@0.95": qps_of(result.get("lp", {}).get("0.95")),
+            "lp_fixed_eps@0.99": qps_of(result.get("lp", {}).get("0.99")),
+            "learned_lp_search@0.95": qps_of(learned_pts.get("0.95")),
+        },
+        "speedup_vs_plain_f32@0.95": (round(value / plain_pipe_qps, 3) if plain_pipe_qps else None),
+        "speedup_vs_plain_f32@0.99": (
+            round(learned_pts["0.99"]["qps"] / result["plain"]["0.99"]["qps"], 3)
+            if learned_pts.get("0.99") and result["plain"]["0.99"] else None),
+        "operating_points": result,
+        "curve": curve,
+        "build_s": build,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    pipe.close()
+    if pipe_plain is not None:
+        pipe_plain.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -217,7 +217,8 @@ typedef struct {
     int32_t flags;     /* ONNG_QF_* bits */
     uint32_t e_p;      /* explored-edge limit used after the first expansion */
     float eps;         /* search range used after the first expansion */
-    int32_t reserved[3];
+    int32_t scanned;   /* adjacency entries read: sum over expansions of min(deg, e_p) */
+    int32_t reserved[2];
 } onng_query_stats;
 
 #define ONNG_QF_PADDED 1      /* fewer than k results were reachable */

@@ -272,6 +272,10 @@ class SearchRequest:
     def eps_used(self):
         return self.stats[:, 4].view(torch.float32)
 
+    @property
+    def scanned(self):
+        return self.stats[:, 5]
+
 
 def search(base, graph, queries, seeds, **kw) -> SearchRequest:
     return SearchRequest(base, graph, queries, seeds, **kw).run()

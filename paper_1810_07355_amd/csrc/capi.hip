@@ -644,7 +644,11 @@ size_t onng_pipeline_workspace_size(const onng_vectors *base, const onng_vectors
                                     int64_t n_pivots, int32_t n_seeds,
                                     const onng_search_params *params) {
     if (!base || !queries || !params) return 0;
-    size_t a = onng_topk_workspace_size(queries, base, n_pivots, n_seeds);
+    // seeds come from the f32 rows when the searched rows are low precision
+    const onng_vectors *seed_base =
+        base->dtype == ONNG_U8 || base->dtype == ONNG_F32 ? base : params->rerank_base;
+    if (!seed_base) return 0;
+    size_t a = onng_topk_workspace_size(queries, seed_base, n_pivots, n_seeds);
     size_t b = onng_search_workspace_size(base, queries->n, params);
     if (!a || !b) return 0;
     return (a + 255) / 256 * 256 + b;
@@ -666,11 +670,11 @@ onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *gra
         set_error("onng_pipeline_create: workspace too small");
         return ONNG_ERR_WORKSPACE;
     }
-    size_t a = (onng_topk_workspace_size(queries, base, n_pivots, n_seeds) + 255) / 256 * 256;
-    char *wsa = static_cast<char *>(ws);
     // seeds come from the f32 rows when the searched rows are low precision
     const onng_vectors *seed_base = base->dtype == ONNG_U8 || base->dtype == ONNG_F32
                                         ? base : params->rerank_base;
+    size_t a = (onng_topk_workspace_size(queries, seed_base, n_pivots, n_seeds) + 255) / 256 * 256;
+    char *wsa = static_cast<char *>(ws);
     hipStream_t st = as_stream(stream);
     bool own = false;
     if (!st) {

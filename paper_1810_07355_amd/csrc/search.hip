@@ -230,6 +230,7 @@ __global__ void __launch_bounds__(512) search_kernel(SearchKArgs a) {
         bool gmode = a.vis_log2 == 0;
         int log_n = 0;
         int dc = 0, hops = 0;
+        int scanned = 0;   // adjacency entries read (sum of min(deg, e_p) over expansions)
         int flags = 0;
         bool rfull = false;
         float r = F_INF;
@@ -471,6 +472,7 @@ __global__ void __launch_bounds__(512) search_kernel(SearchKArgs a) {
             const int64_t e0 = a.offsets[s];
             const int64_t deg = a.offsets[s + 1] - e0;
             const int64_t np = (int64_t)ep < deg ? (int64_t)ep : deg;
+            scanned += (int)np;
             for (int64_t c0 = 0; c0 < np; c0 += WAVE) {
                 int64_t j = c0 + lane;
                 uint32_t id = j < np ? (uint32_t)a.nbrs[e0 + j] : 0u;
@@ -603,7 +605,8 @@ __global__ void __launch_bounds__(512) search_kernel(SearchKArgs a) {
             st.flags = flags;
             st.e_p = ep;
             st.eps = eps;
-            st.reserved[0] = st.reserved[1] = st.reserved[2] = 0;
+            st.reserved[0] = scanned;
+            st.reserved[1] = st.reserved[2] = 0;
             a.stats[qi] = st;
         }
 

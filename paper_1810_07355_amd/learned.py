@@ -1,0 +1,135 @@
+"""Learned per-query search range: labels from eps sweeps, training of the
+2-layer perceptron with the library's forward/backward/Adam kernels, and
+calibration of the per-target shift.  Not part of the paper; the plain eps
+sweep stays the fallback and the judge of recall.
+
+Model: 14 features of the state after the first expansion -> 64 ReLU ->
+one head per target recall, each predicting log10(eps + 0.01) of the
+smallest grid eps at which the query reaches that recall."""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import api
+
+EPS_OFFSET = 0.01
+
+
+def eps_to_target(eps):
+    return np.log10(np.asarray(eps, dtype=np.float64) + EPS_OFFSET)
+
+
+def dynamic_ep(eps: float, e0: float = 30.0, we: float = 20.0) -> int:
+    """Equation 1, e_p = 10^(w_e eps) + e_0, as an edge count."""
+    return int(min(math.floor(10.0 ** (we * float(np.float32(eps))) + e0), L.EP_INF))
+
+
+def recall_by_ids(ids: np.ndarray, gt_ids: np.ndarray, k: int) -> np.ndarray:
+    """Per-query recall@k: returned ids found among the k true neighbours."""
+    ids = ids[:, :k]
+    gt = gt_ids[:, :k]
+    hit = (ids[:, :, None] == gt[:, None, :]).any(axis=2) & (ids >= 0)
+    return hit.sum(axis=1) / float(k)
+
+
+def labels_from_recalls(recalls: np.ndarray, grid, targets) -> np.ndarray:
+    """recalls[e, q] at grid[e] -> per query and target the smallest grid eps
+    reaching the target (the largest grid eps if none does)."""
+    grid = np.asarray(grid, dtype=np.float64)
+    out = np.empty((recalls.shape[1], len(targets)))
+    for t, tgt in enumerate(targets):
+        reach = recalls >= tgt - 1e-9
+        idx = np.where(reach.any(axis=0), reach.argmax(axis=0), len(grid) - 1)
+        out[:, t] = grid[idx]
+    return out
+
+
+@dataclasses.dataclass
+class Trained:
+    W1: torch.Tensor
+    b1: torch.Tensor
+    W2: torch.Tensor
+    b2: torch.Tensor
+    mean: torch.Tensor
+    std: torch.Tensor
+    losses: list
+
+    def predictor(self, head=0, shift=None, eps_min=0.0, eps_max=0.5, e0=30.0, we=20.0,
+                  head_per_query=None) -> api.Predictor:
+        dev = self.W1.device
+        if shift is None:
+            shift = torch.zeros(self.W2.shape[0], dtype=torch.float32, device=dev)
+        return api.Predictor(api.to_bf16_bits(self.W1), self.b1, api.to_bf16_bits(self.W2),
+                             self.b2, self.mean, self.std, shift=shift, head=head,
+                             head_per_query=head_per_query, eps_min=eps_min, eps_max=eps_max,
+                             e0=e0, we=we)
+
+
+def train(features: torch.Tensor, labels: np.ndarray, metric: int, hidden: int = 64,
+          steps: int = 3000, batch: int = 1024, lr: float = 3e-3, seed: int = 0) -> Trained:
+    """features: raw [n, 14] f32 on the GPU; labels: [n, T] eps values."""
+    dev = features.device
+    X = api.feature_transform(features.contiguous(), metric)
+    torch.cuda.synchronize()
+    xh = X.cpu().numpy().astype(np.float64)
+    mean = xh.mean(axis=0)
+    std = xh.std(axis=0)
+    std = np.where(std < 1e-6, 1.0, std)
+    Xz = torch.from_numpy(((xh - mean) / std).astype(np.float32)).to(dev)
+    Y = torch.from_numpy(eps_to_target(labels).astype(np.float32)).to(dev)
+    n, F = Xz.shape
+    T = Y.shape[1]
+    g = np.random.default_rng(seed)
+    W1 = torch.from_numpy((g.standard_normal((hidden, F)) * math.sqrt(2.0 / F)).astype(np.float32)).to(dev)
+    b1 = torch.zeros(hidden, dtype=torch.float32, device=dev)
+    W2 = torch.from_numpy((g.standard_normal((T, hidden)) * math.sqrt(1.0 / hidden)).astype(np.float32)).to(dev)
+    b2 = torch.from_numpy(Y.mean(dim=0).cpu().numpy()).to(dev)
+    params = [W1, b1, W2, b2]
+    ms = [torch.zeros_like(p) for p in params]
+    vs = [torch.zeros_like(p) for p in params]
+    losses = []
+    batch = min(batch, n)
+    perm = g.permutation(n)
+    pos = 0
+    for t in range(1, steps + 1):
+        if pos + batch > n:
+            perm = g.permutation(n)
+            pos = 0
+        idx = torch.from_numpy(perm[pos:pos + batch]).to(dev)
+        pos += batch
+        xb = Xz.index_select(0, idx).contiguous()
+        yb = Y.index_select(0, idx).contiguous()
+        loss, grads = api.mlp_backward(xb, yb, W1, b1, W2, b2)
+        step_lr = lr * (0.5 * (1.0 + math.cos(math.pi * t / steps)) * 0.9 + 0.1)
+        for p, gr, m, v in zip(params, grads, ms, vs):
+            api.adam_step(p, gr, m, v, step_lr, t)
+        if t % 100 == 0 or t == 1:
+            losses.append(float(loss.item()))
+    mean_t = torch.from_numpy(mean.astype(np.float32)).to(dev)
+    std_t = torch.from_numpy(std.astype(np.float32)).to(dev)
+    return Trained(W1, b1, W2, b2, mean_t, std_t, losses)
+
+
+def calibrate(run_recall, target: float, lo: float = -1.0, hi: float = 1.0, iters: int = 9,
+              slack: float = 0.0) -> tuple[float, float]:
+    """Smallest shift (log10 units) whose mean recall reaches target + slack;
+    run_recall(shift) -> mean recall is monotone in the shift up to noise."""
+    goal = target + slack
+    r_hi = run_recall(hi)
+    if r_hi < goal:
+        return hi, r_hi
+    best = (hi, r_hi)
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        r = run_recall(mid)
+        if r >= goal:
+            hi = mid
+            best = (mid, r)
+        else:
+            lo = mid
+    return best

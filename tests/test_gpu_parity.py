@@ -472,3 +472,29 @@ def test_autotune_picks_a_shape_that_stays_exact():
     ref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, 0.1)
     assert np.array_equal(host(req.ids), ref["ids"])
     assert np.array_equal(host(req.dc), ref["dc"])
+
+
+def test_pipeline_low_precision_rows_with_rerank():
+    """Seeds come from the f32 rows when the searched rows are f16."""
+    F = _float_problem("f32cos")
+    A, Lb = api(), L()
+    B = gpu_vectors(F["x"], F["metric"])
+    Q = gpu_vectors(F["q"], F["metric"])
+    lp = A.encode(B.data, Lb.F16, Lb.COSINE)
+    G = gpu_graph(F["off"], F["nb"])
+    piv = to_dev(dg.pivots(F["cfg"], 256))
+    say("pipeline f16 + rerank")
+    pl = A.Pipeline(lp, G, Q, piv, 8, k=10, eps=0.05, rerank_base=B, pool_factor=4)
+    req = pl.launch()
+    torch.cuda.synchronize()
+    seeds = host(pl.seeds)
+    assert np.array_equal(seeds, F["seeds"])
+    eager = A.search(lp, G, Q, to_dev(seeds), k=10, eps=0.05, rerank_base=B, pool_factor=4)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        assert np.array_equal(host(req.ids), host(eager.ids))
+        assert np.array_equal(host(req.dists), host(eager.dists))
+        req.ids.fill_(-3)
+        req = pl.launch()
+        torch.cuda.synchronize()
+    pl.close()
