@@ -85,7 +85,8 @@ def main():
     metric = L.L2SQ if cfg.kind != "f32cos" else L.COSINE
     K = 10
     NS = 8
-    grid = [0.0, 0.005, 0.01, 0.02, 0.03, 0.05, 0.07, 0.1, 0.15, 0.2, 0.3, 0.4, 0.6, 1.0]
+    # label grid of the learned range: fine where recall climbs, coarse above
+    grid = ([round(0.01 * i, 2) for i in range(0, 21)] + [0.225, 0.25, 0.3, 0.4, 0.6, 1.0])
     targets = (0.9, 0.95, 0.99)
 
     # ------------------------------------------------------------ inputs --

@@ -110,7 +110,8 @@ struct SearchPlan {
     size_t ws = 0;
 };
 
-static int ppl_for(int dtype) { return dtype == ONNG_U8 ? 2 : dtype == ONNG_F32 ? 4 : 2; }
+// 16-byte pieces of a row per lane (matches the search kernel's query registers)
+static int ppl_for(int dtype) { return dtype == ONNG_FP8_E4M3 ? 1 : 2; }
 
 static int align16(int x) { return (x + 15) / 16 * 16; }
 
@@ -171,7 +172,7 @@ static onng_status make_plan(const onng_vectors *base, int64_t nq, const onng_se
     P.off_stage2 = o; o = align16(o + 64 * 8);
     P.off_ids = o; o = align16(o + 64 * 4);
     P.off_vis = o; o = align16(o + (P.vis_log2 ? (4 << P.vis_log2) : 0));
-    P.off_misc = o; o = align16(o + 72 * 4);
+    P.off_misc = o; o = align16(o + 96 * 4);
     P.lds_per_wave = o;
     size_t lds = (size_t)o * P.wpb;
     if (lds > 160 * 1024) {

@@ -50,10 +50,12 @@ __device__ __forceinline__ float range_factor(float eps, int metric) {
     return metric == ONNG_L2SQ ? (float)__dmul_rn(t, t) : (float)t;
 }
 
+// Equation 1 for a predicted eps, in f32 (the value used is reported per
+// query, so a replay uses the same integer).
 __device__ __forceinline__ uint32_t dynamic_ep(float eps, float e0, float we) {
-    double v = floor(pow(10.0, (double)we * (double)eps) + (double)e0);
-    if (!(v < 4294967295.0)) return 0xffffffffu;
-    return v < 1.0 ? 1u : (uint32_t)v;
+    float v = floorf(exp10f(we * eps) + e0);
+    if (!(v < 4294967040.0f)) return 0xffffffffu;
+    return v < 1.0f ? 1u : (uint32_t)v;
 }
 
 template <int DT, int MT>
@@ -79,15 +81,17 @@ struct Q<ONNG_U8, ONNG_L2SQ> {
             }
         }
     }
-    // partial over this lane's pieces of the row
-    __device__ uint32_t partial(const uint8_t *row, const float *, int p, int L, int n16) const {
-        uint32_t s = qq;
-        u32x4 x[PPL];
+    // this lane's pieces of a row (zero where the lane has none)
+    __device__ void fetch(const uint8_t *row, int p, int L, int n16, u32x4 *x) const {
 #pragma unroll
         for (int t = 0; t < PPL; t++) {
             int pc = p + t * L;
             x[t] = pc < n16 ? load16(row + pc * 16) : u32x4{0, 0, 0, 0};
         }
+    }
+    // sum over this lane's pieces of (x - q)^2
+    __device__ uint32_t fold(const u32x4 *x, float) const {
+        uint32_t s = qq;
 #pragma unroll
         for (int t = 0; t < PPL; t++) s += u8_piece(x[t], q[t]);
         return s;
@@ -97,7 +101,7 @@ struct Q<ONNG_U8, ONNG_L2SQ> {
 // ------------------------------------------------------ float storage ----
 template <int DT, int MT>
 struct Q {
-    static constexpr int PPL = DT == ONNG_F32 ? 4 : 2;
+    static constexpr int PPL = DT == ONNG_FP8_E4M3 ? 1 : 2;
     static constexpr int N = Piece<DT>::N;
     static constexpr bool INT = false;
     float q[PPL][N];
@@ -114,15 +118,15 @@ struct Q {
             }
         }
     }
-    __device__ float partial(const uint8_t *row, const float *scale, int p, int L, int n16) const {
-        u32x4 x[PPL];
+    __device__ void fetch(const uint8_t *row, int p, int L, int n16, u32x4 *x) const {
 #pragma unroll
         for (int t = 0; t < PPL; t++) {
             int pc = p + t * L;
             x[t] = pc < n16 ? load16(row + pc * 16) : u32x4{0, 0, 0, 0};
         }
-        float sc = 1.0f;
-        if constexpr (DT == ONNG_FP8_E4M3) sc = *scale;
+    }
+    // this lane's part of sum (x - q)^2, or of <x, q> for cosine
+    __device__ float fold(const u32x4 *x, float sc) const {
         float acc = 0.0f;
 #pragma unroll
         for (int t = 0; t < PPL; t++) {
@@ -169,7 +173,8 @@ struct LdsWave {
 }  // namespace
 
 template <int DT, int MT>
-__global__ void __launch_bounds__(512) search_kernel(SearchKArgs a) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8)))
+search_kernel(SearchKArgs a) {
     typedef Q<DT, MT> QT;
     constexpr bool INT = QT::INT;
     extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -292,27 +297,42 @@ __global__ void __launch_bounds__(512) search_kernel(SearchKArgs a) {
             return isnew;
         };
 
-        // Distances of rows lds.ids[0..u) -> lds.stage2[i] as keys.
+        // Distances of rows lds.ids[0..u) -> lds.stage2[i] as keys.  A lane
+        // group of L lanes takes one row; the loads of UP row passes are
+        // issued together so that several rows per lane are in flight.
         auto batch_keys = [&](int u) {
-            for (int r0 = 0; r0 < u; r0 += rpp) {
-                int row = r0 + grp;
-                typename DistTraits<DT>::acc_t acc = 0;
-                uint32_t id = 0;
-                if (row < u) {
-                    id = lds.ids[row];
-                    const uint8_t *rp = a.base + (size_t)id * a.base_pitch;
-                    const float *sp = a.base_scale ? a.base_scale + id : nullptr;
-                    acc = qr.partial(rp, sp, p, L, a.n16);
+            constexpr int UP = DT == ONNG_FP8_E4M3 ? 2 : 4;
+            for (int r0 = 0; r0 < u; r0 += rpp * UP) {
+                u32x4 x[UP][QT::PPL];
+                uint32_t rid[UP];
+                float sc[UP];
+#pragma unroll
+                for (int up = 0; up < UP; up++) {
+                    int row = r0 + up * rpp + grp;
+                    rid[up] = row < u ? lds.ids[row] : 0u;
                 }
-                for (int m = L >> 1; m >= 1; m >>= 1) {
-                    if constexpr (INT) acc += (uint32_t)__shfl_xor((int)acc, m);
-                    else acc += __shfl_xor(acc, m);
+#pragma unroll
+                for (int up = 0; up < UP; up++) {
+                    int row = r0 + up * rpp + grp;
+                    const uint8_t *rp = a.base + (size_t)rid[up] * a.base_pitch;
+                    qr.fetch(rp, p, L, row < u ? a.n16 : 0, x[up]);
+                    sc[up] = 1.0f;
+                    if constexpr (DT == ONNG_FP8_E4M3) sc[up] = row < u ? a.base_scale[rid[up]] : 1.0f;
                 }
-                if (row < u && p == 0) {
-                    uint32_t dord;
-                    if constexpr (INT) dord = acc;
-                    else dord = ord_f32(MT == ONNG_COSINE ? 1.0f - acc : acc);
-                    lds.stage2[row] = make_key(dord, id);
+#pragma unroll
+                for (int up = 0; up < UP; up++) {
+                    int row = r0 + up * rpp + grp;
+                    typename DistTraits<DT>::acc_t acc = qr.fold(x[up], sc[up]);
+                    for (int m = L >> 1; m >= 1; m >>= 1) {
+                        if constexpr (INT) acc += (uint32_t)__shfl_xor((int)acc, m);
+                        else acc += __shfl_xor(acc, m);
+                    }
+                    if (row < u && p == 0) {
+                        uint32_t dord;
+                        if constexpr (INT) dord = acc;
+                        else dord = ord_f32(MT == ONNG_COSINE ? 1.0f - acc : acc);
+                        lds.stage2[row] = make_key(dord, rid[up]);
+                    }
                 }
             }
             wave_sync();
@@ -493,30 +513,21 @@ __global__ void __launch_bounds__(512) search_kernel(SearchKArgs a) {
 
             if (a.two_phase && hops == 1) {
                 // ---- state after the first expansion -> search range ----
-                float feat[ONNG_NFEAT];
+                // lane t < 14 computes feature t (see predict_eps for the list)
                 int nseed = (int)lds.misc[64];
-#pragma unroll
-                for (int t = 0; t < 8; t++)
-                    feat[t] = nseed == 0 ? 0.0f : lds.misc[t < nseed ? t : nseed - 1];
                 int ns = size - head;   // no spill can happen in the first expansion
                 float rmax = npool > 0 ? key_dist<INT>(lds.pool[min(npool, k) - 1]) : 0.0f;
-                feat[8] = (float)ns;
-                if (ns > 0) {
-                    feat[9] = key_dist<INT>(lds.S[head]);
-                    feat[10] = key_dist<INT>(lds.S[head + (ns - 1) / 2]);
-                    feat[11] = key_dist<INT>(lds.S[size - 1]);
-                } else {
-                    feat[9] = feat[10] = feat[11] = rmax;
-                }
-                feat[12] = rmax;
-                feat[13] = (float)dc;
-                if (a.feat_out && lane == 0) {
-#pragma unroll
-                    for (int t = 0; t < ONNG_NFEAT; t++)
-                        a.feat_out[(size_t)qi * ONNG_NFEAT + t] = feat[t];
-                }
+                float fv = 0.0f;
+                if (lane < 8) fv = nseed == 0 ? 0.0f : lds.misc[lane < nseed ? lane : nseed - 1];
+                else if (lane == 8) fv = (float)ns;
+                else if (lane == 9) fv = ns > 0 ? key_dist<INT>(lds.S[head]) : rmax;
+                else if (lane == 10) fv = ns > 0 ? key_dist<INT>(lds.S[head + (ns - 1) / 2]) : rmax;
+                else if (lane == 11) fv = ns > 0 ? key_dist<INT>(lds.S[size - 1]) : rmax;
+                else if (lane == 12) fv = rmax;
+                else if (lane == 13) fv = (float)dc;
+                if (a.feat_out && lane < ONNG_NFEAT) a.feat_out[(size_t)qi * ONNG_NFEAT + lane] = fv;
                 if (a.has_pred) {
-                    eps = predict_eps(a.pred, feat, MT, qi, lane);
+                    eps = predict_eps(a.pred, fv, MT, qi, lane, lds.misc + 80);
                     eps = unif(eps);
                     ep = a.pred.we >= 0.0f ? dynamic_ep(eps, a.pred.e0, a.pred.we)
                                            : (a.ep_pq ? uniu(a.ep_pq[qi]) : a.ep);

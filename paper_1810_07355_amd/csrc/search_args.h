@@ -81,39 +81,37 @@ struct SearchKArgs {
     int32_t off_pool, off_s, off_stage, off_stage2, off_ids, off_vis, off_misc;
 };
 
-// log10(eps + 0.01) heads -> eps for this query.  Features are the raw state
-// after the first expansion (8 seed distances ascending, |S|, min/median/max
-// of S, radius of R, distance computations); all lanes return the same value.
-__device__ inline float predict_eps(const PredArgs &P, const float *feat, int metric, int qi,
-                                    int lane) {
+// log10(eps + 0.01) heads -> eps for this query.  Lane t < 14 holds raw
+// feature t of the state after the first expansion: 0-7 the 8 seed
+// distances ascending, 8 |S|, 9-11 min/median/max distance in S, 12 the
+// radius of R, 13 distance computations.  `scratch` is 16 floats of LDS.
+// All lanes return the same value.
+__device__ inline float predict_eps(const PredArgs &P, float fv, int metric, int qi, int lane,
+                                    float *scratch) {
     const float c = metric == ONNG_COSINE ? 1e-3f : 1.0f;
-    float x[ONNG_NFEAT];
-    float lg0 = logf(fmaxf(feat[0], 0.0f) + c);
-    x[0] = lg0;
-#pragma unroll
-    for (int t = 1; t < 8; t++) x[t] = logf(fmaxf(feat[t], 0.0f) + c) - lg0;
-    x[8] = log1pf(feat[8]);
-#pragma unroll
-    for (int t = 9; t < 13; t++) x[t] = logf(fmaxf(feat[t], 0.0f) + c) - lg0;
-    x[13] = log1pf(feat[13]);
-#pragma unroll
-    for (int t = 0; t < ONNG_NFEAT; t++) x[t] = (x[t] - P.mean[t]) / P.stdv[t];
+    float lg = logf(fmaxf(fv, 0.0f) + c);
+    float lg0 = __shfl(lg, 0);
+    float x;
+    if (lane == 0) x = lg;
+    else if (lane == 8 || lane == 13) x = log1pf(fv);
+    else x = lg - lg0;
+    if (lane < ONNG_NFEAT) scratch[lane] = (x - P.mean[lane]) / P.stdv[lane];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     const int head = P.head_pq ? P.head_pq[qi] : P.head;
     float h = 0.0f;
     if (lane < P.H) {
         float s = P.b1[lane];
         for (int t = 0; t < P.F; t++) {
             float wv = __uint_as_float((uint32_t)P.w1[lane * P.F + t] << 16);
-            s = fmaf(wv, x[t], s);
+            s = fmaf(wv, scratch[t], s);
         }
-        h = fmaxf(s, 0.0f);
-        h *= __uint_as_float((uint32_t)P.w2[head * P.H + lane] << 16);
+        h = fmaxf(s, 0.0f) * __uint_as_float((uint32_t)P.w2[head * P.H + lane] << 16);
     }
     for (int m = 32; m >= 1; m >>= 1) h += __shfl_xor(h, m);
     float y = h + P.b2[head] + (P.shift ? P.shift[head] : 0.0f);
     float eps = exp10f(y) - 0.01f;
-    eps = fminf(fmaxf(eps, P.eps_min), P.eps_max);
-    return eps;
+    return fminf(fmaxf(eps, P.eps_min), P.eps_max);
 }
 
 const void *search_kernel_ptr(int dtype, int metric);
