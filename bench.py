@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--dump", default=None, help="save per-query sweep data (.npz)")
+    ap.add_argument("--probe-hops", type=int, default=1,
+                    help="expansions before the learned range is chosen")
     ap.add_argument("--search-only", action="store_true",
                     help="after the index and operating points, only loop the search kernel "
                          "(used under rocprofv3)")
@@ -183,7 +185,15 @@ def main():
                         for t in (0.95, 0.99)}
 
     # ------------------------------------------------- learned search range --
-    EPF = 64
+    # The predictor sees the state after PROBE expansions (run with an
+    # unlimited range, which changes no distance computation) and estimates,
+    # for each candidate range, the query's recall and distance computations;
+    # each query then takes the candidate with the best recall minus
+    # lambda * cost, with one lambda calibrated per target recall.
+    PROBE = args.probe_hops
+    cand = {0.95: [0.05, 0.07, 0.09, 0.10, 0.11, 0.12, 0.14, 0.17],
+            0.99: [0.10, 0.13, 0.15, 0.17, 0.19, 0.20, 0.25, 0.30]}
+    EPF = LR.dynamic_ep(0.11)
     search_rows = lp_rows if lp_rows is not None else base
     rr = dict(rerank_base=base, pool_factor=4) if lp_rows is not None else {}
     tq_np = dg.train_queries(cfg)
@@ -198,7 +208,7 @@ def main():
         for i, eps in enumerate(grid):
             req = A.SearchRequest(search_rows, graph, vq, vseeds, k=K, eps=eps,
                                   ep=LR.dynamic_ep(eps), two_phase=True, ep_first=EPF,
-                                  want_features=(i == 0), **rr)
+                                  probe_hops=PROBE, want_features=(i == 0), **rr)
             req.run()
             torch.cuda.synchronize()
             if i == 0:
@@ -209,46 +219,48 @@ def main():
 
     t_lab = time.time()
     feats, recalls, dcs = label_sweep(tq, tseeds, tgt_np)
-    labels = LR.labels_from_recalls(recalls, grid, targets)
-    log(f"labels from {len(grid)}-point sweep over {len(tq_np)} queries in "
-        f"{time.time() - t_lab:.1f} s; mean label eps per target "
-        f"{labels.mean(axis=0).round(4).tolist()}")
+    log(f"sweep of {len(grid)} ranges over {len(tq_np)} training queries in "
+        f"{time.time() - t_lab:.1f} s")
     if args.dump:
         hf, hr, hd = label_sweep(queries, seeds, gt)
         np.savez_compressed(args.dump, grid=np.array(grid), train_feat=feats.cpu().numpy(),
                             train_recall=recalls, train_dc=dcs, test_feat=hf.cpu().numpy(),
-                            test_recall=hr, test_dc=hd)
+                            test_recall=hr, test_dc=hd, probe_hops=PROBE)
         log("dumped sweep data to", args.dump)
-    t_tr = time.time()
-    model = LR.train(feats, labels, metric, steps=3000)
-    log(f"trained predictor in {time.time() - t_tr:.1f} s; loss {model.losses[0]:.4f} -> "
-        f"{model.losses[-1]:.4f}")
+    garr = np.array(grid)
+    models = {}
+    for tgt in (0.95, 0.99):
+        idx = [int(np.argmin(np.abs(garr - e))) for e in cand[tgt]]
+        t_tr = time.time()
+        models[tgt] = LR.train_targets(feats, LR.curve_targets(recalls, dcs, idx), metric,
+                                       steps=4000)
+        log(f"trained predictor for {tgt} in {time.time() - t_tr:.1f} s; loss "
+            f"{models[tgt].losses[0]:.4f} -> {models[tgt].losses[-1]:.4f}")
 
-    def make_learned(head):
-        def make(shift):
-            sh = torch.zeros(len(targets), dtype=torch.float32, device=dev)
-            sh[head] = float(shift)
-            pred = model.predictor(head=head, shift=sh, eps_min=0.0, eps_max=max(grid))
+    def learned_pred(tgt, knob):
+        return models[tgt].predictor(mode=L.PRED_CURVE, eps_cand=cand[tgt], lam=10.0 ** (-knob),
+                                     eps_min=0.0, eps_max=max(grid), e0=30.0, we=20.0)
+
+    def make_learned(tgt):
+        def make(knob):   # knob = -log10(lambda): larger spends more
+            pred = learned_pred(tgt, knob)
             req = A.SearchRequest(search_rows, graph, queries, seeds, k=K, eps=0.0, ep=L.EP_INF,
-                                  two_phase=True, ep_first=EPF, predictor=pred, **rr)
+                                  two_phase=True, ep_first=EPF, probe_hops=PROBE, predictor=pred,
+                                  **rr)
             req._pred = pred
             return req
         return make
 
     for tgt in (0.95, 0.99):
-        head = targets.index(tgt)
-        learned_pts[str(tgt)] = bisect(make_learned(head), tgt, -1.5, 1.5, f"learned@{tgt}")
+        learned_pts[str(tgt)] = bisect(make_learned(tgt), tgt, 2.0, 9.0, f"learned@{tgt}")
     result["learned"] = learned_pts
-    shifts = {t: (learned_pts[str(t)]["knob"] if learned_pts[str(t)] else 1.5)
-              for t in (0.95, 0.99)}
+    knobs = {t: (learned_pts[str(t)]["knob"] if learned_pts[str(t)] else 9.0)
+             for t in (0.95, 0.99)}
 
     # ----------------------------------------------- timed region (graph) --
-    head95 = targets.index(0.95)
-    sh = torch.zeros(len(targets), dtype=torch.float32, device=dev)
-    sh[head95] = shifts[0.95]
-    pred95 = model.predictor(head=head95, shift=sh, eps_min=0.0, eps_max=max(grid))
+    pred95 = learned_pred(0.95, knobs[0.95])
     pipe = A.Pipeline(search_rows, graph, queries, piv, NS, k=K, eps=0.0, ep=L.EP_INF,
-                      two_phase=True, ep_first=EPF, predictor=pred95, **rr)
+                      two_phase=True, ep_first=EPF, probe_hops=PROBE, predictor=pred95, **rr)
     plain95 = result["plain"]["0.95"]
     pipe_plain = None
     if plain95 is not None:
@@ -256,7 +268,7 @@ def main():
                                 ep=LR.dynamic_ep(plain95["knob"]))
 
     if args.search_only:
-        req = make_learned(head95)(shifts[0.95])
+        req = make_learned(0.95)(knobs[0.95])
         for _ in range(args.warmup + args.steps):
             req.run()
         torch.cuda.synchronize()
@@ -289,7 +301,7 @@ def main():
         log(f"plain f32 pipeline at eps={plain95['knob']}: {plain_pipe_qps:.0f} q/s")
 
     # ---------------------------------------- roofline of the search kernel --
-    req = make_learned(head95)(shifts[0.95])
+    req = make_learned(0.95)(knobs[0.95])
     ms_search = time_req(req, reps=5)
     st = req.stats.cpu().numpy()
     dc, hops, scanned = st[:, 0].astype(np.float64), st[:, 1].astype(np.float64), st[:, 5].astype(np.float64)

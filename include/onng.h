@@ -152,10 +152,18 @@ size_t onng_adjust_path_workspace_size(int64_t n, int64_t nnz);
 /* Search — Algorithm 1 (KnnSearch)                                         */
 /* ------------------------------------------------------------------------ */
 
-/* Optional learned search range: a 2-layer MLP (F -> H ReLU -> T heads) that
- * maps the state after the first expansion to log10(eps + 0.01) for each
- * target recall.  Weights are bf16 (w1: [H][F], w2: [T][H]); biases, feature
- * statistics and shifts are f32.  Not part of the paper. */
+/* Optional learned search range: a 2-layer MLP (F -> H ReLU -> T heads)
+ * evaluated on the state after the probe expansions.  Not part of the paper.
+ *  mode 0 (ONNG_PRED_LOG_EPS): head `head` (or head_per_query[q]) predicts
+ *    log10(eps + 0.01); eps = 10^(y + shift[head]) - 0.01.
+ *  mode 1 (ONNG_PRED_CURVE): n_cand candidate ranges eps_cand[g]; head g
+ *    predicts the query's recall at eps_cand[g] and head n_cand + g the
+ *    log(1 + distance computations) there; the query takes the candidate
+ *    maximising recall_g - lambda * (exp(y_{n_cand+g}) - 1), with lambda
+ *    from lambda_per_query[q] when given.
+ * Weights are bf16 (w1: [H][F], w2: [T][H]); biases, feature statistics,
+ * shifts and candidates are f32.  The chosen eps is clamped to
+ * [eps_min, eps_max]; e_p follows Equation 1 with (e0, we) unless we < 0. */
 typedef struct {
     const uint16_t *w1_bf16;
     const float *b1;
@@ -163,16 +171,23 @@ typedef struct {
     const float *b2;
     const float *feat_mean;        /* [F] z-scoring of the transformed features */
     const float *feat_std;         /* [F] */
-    const float *shift;            /* [T] calibration shift added to each head, or NULL */
-    const int32_t *head_per_query; /* [nq] head index per query, or NULL: use `head` */
+    const float *shift;            /* [T] calibration shift added to each head (mode 0), or NULL */
+    const int32_t *head_per_query; /* [nq] head index per query (mode 0), or NULL: use `head` */
     int32_t head;
     int32_t n_features;            /* must be ONNG_NFEAT */
     int32_t hidden;                /* <= 64 */
-    int32_t n_heads;               /* <= 8 */
+    int32_t n_heads;               /* <= 16 */
     float eps_min, eps_max;        /* predicted eps is clamped to this range */
     float e0, we;                  /* e_p = floor(10^(we*eps) + e0) (Equation 1); we < 0: use e_p */
+    int32_t mode;                  /* ONNG_PRED_LOG_EPS or ONNG_PRED_CURVE */
+    int32_t n_cand;                /* mode 1: candidates, n_heads = 2 * n_cand, <= 8 */
+    const float *eps_cand;         /* mode 1: [n_cand] candidate search ranges */
+    float lambda;                  /* mode 1: price of one distance computation in recall */
+    const float *lambda_per_query; /* mode 1: [nq] or NULL */
 } onng_predictor;
 
+#define ONNG_PRED_LOG_EPS 0
+#define ONNG_PRED_CURVE 1
 #define ONNG_NFEAT 14
 
 /* Launch shape of the search kernel (0 = library default for a field). */
@@ -194,20 +209,27 @@ typedef struct {
     uint32_t e_p;                  /* explored-edge limit when ep_per_query is NULL;
                                       0xFFFFFFFF = unlimited (Equation 1's e_p) */
     const uint32_t *ep_per_query;  /* [nq] or NULL */
-    /* Two-phase mode: when two_phase != 0 the first expansion uses an
-     * unlimited range and e_p = ep_first; the search range of every later
-     * step comes from the predictor (if set) or from eps/e_p above. */
+    /* Two-phase mode: when two_phase != 0 the first probe_hops expansions
+     * use an unlimited range and e_p = ep_first; the search range of every
+     * later step comes from the predictor (if set) or from eps/e_p above.
+     * Features at the switch: 0-7 the seed distances ascending (the last
+     * repeated when fewer), 8 |S|, 9-11 the smallest, the ceil(m/2)-th and
+     * the m-th smallest distance in S with m = min(|S|, 64) (all equal to
+     * feature 12 when S is empty), 12 the largest distance in R, 13 the
+     * distance computations so far. */
     int32_t two_phase;
     uint32_t ep_first;
     const onng_predictor *predictor;   /* requires two_phase */
-    float *features_out;           /* [nq][ONNG_NFEAT] raw state after the first
-                                      expansion (two_phase only), or NULL */
+    float *features_out;           /* [nq][ONNG_NFEAT] raw state after the probe
+                                      expansions (two_phase only), or NULL */
     /* Rerank: search on the stored (possibly low-precision) rows, keep the
      * pool_factor*k best visited ids, recompute their distances from
      * rerank_base (f32 rows of the same objects) and return the best k. */
     const onng_vectors *rerank_base;   /* NULL = no rerank */
     int32_t pool_factor;
     const onng_launch_config *launch;  /* NULL = tuned or default shape */
+    uint32_t probe_hops;           /* two_phase: expansions run with the unlimited range
+                                      and e_p = ep_first before the switch (0 means 1) */
 } onng_search_params;
 
 /* Per-query statistics written by onng_search. */

@@ -679,6 +679,7 @@ typedef struct {
     const int32_t *k;
     const float *eps, *eps1;
     const uint32_t *ep, *ep1;
+    int32_t probe_hops;
     int32_t k_stride;
     int32_t *out_ids;
     double *out_d;
@@ -776,7 +777,7 @@ static void search_one(search_job *J, visited_t *C, heap_t *S, rset_t *R, int64_
             margin = fmin(margin, rel_gap(d, r, mfloor));
             rset_offer(R, &r, d, nn);
         }
-        if (phase1 && hops == 1) {
+        if (phase1 && hops == J->probe_hops) {
             if (J->feat) {
                 double *F = J->feat + q * OR_NFEAT;
                 qsort(seedd, (size_t)nseedd, sizeof(double), dcmp);
@@ -785,12 +786,14 @@ static void search_one(search_job *J, visited_t *C, heap_t *S, rset_t *R, int64_
                 double rmax = R->n > 0 ? R->d[R->n - 1] : 0.0;
                 F[8] = (double)S->n;
                 if (S->n > 0) {
+                    /* statistics of the m = min(|S|, 64) smallest entries of S */
                     double *tmp = (double *)malloc(sizeof(double) * (size_t)S->n);
                     for (int64_t t = 0; t < S->n; t++) tmp[t] = S->a[t].d;
                     qsort(tmp, (size_t)S->n, sizeof(double), dcmp);
+                    int64_t m = S->n < 64 ? S->n : 64;
                     F[9] = tmp[0];
-                    F[10] = tmp[(S->n - 1) / 2];
-                    F[11] = tmp[S->n - 1];
+                    F[10] = tmp[(m + 1) / 2 - 1];
+                    F[11] = tmp[m - 1];
                     free(tmp);
                 } else {
                     F[9] = F[10] = F[11] = rmax;
@@ -842,7 +845,7 @@ int or_search(const or_vecs *base, const int64_t *offsets, const int32_t *nbrs,
               int64_t n_nodes, const or_vecs *queries, int64_t nq,
               const int32_t *seeds, int32_t n_seeds,
               const int32_t *k, const float *eps, const uint32_t *ep,
-              const float *eps1, const uint32_t *ep1,
+              const float *eps1, const uint32_t *ep1, int32_t probe_hops,
               int32_t k_stride, int32_t *out_ids, double *out_d,
               int64_t *out_dc, int64_t *out_hops, double *out_margin,
               double *feat, int32_t nthreads)
@@ -856,8 +859,8 @@ int or_search(const or_vecs *base, const int64_t *offsets, const int32_t *nbrs,
     for (int64_t q = 0; q < nq; q++)
         if (k[q] <= 0 || k[q] > k_stride) return -1;
     search_job J = {base, queries, offsets, nbrs, n_nodes, nq, seeds, n_seeds, k, eps, eps1,
-                    ep, ep1, k_stride, out_ids, out_d, out_dc, out_hops, out_margin, feat, 0,
-                    PTHREAD_MUTEX_INITIALIZER};
+                    ep, ep1, probe_hops < 1 ? 1 : probe_hops, k_stride, out_ids, out_d, out_dc,
+                    out_hops, out_margin, feat, 0, PTHREAD_MUTEX_INITIALIZER};
     run_pool(search_worker, &J, nthreads);
     return 0;
 }

@@ -75,17 +75,20 @@ int or_adjust_path(const int64_t *in_off, const int32_t *in_nbrs,
 
 /* ---- Algorithm 1 (KnnSearch) with the visited set of Algorithms 6/7 ---- */
 /* Per query q: k[q], search range eps[q] and explored-edge limit ep[q] (UINT32_MAX
- * = unlimited).  When eps1/ep1 are non-NULL the first expansion uses
+ * = unlimited).  When eps1/ep1 are non-NULL the first probe_hops expansions use
  * (eps1[q], ep1[q]) and every later step uses (eps[q], ep[q]).
  * Outputs: ids/dists rows of k_stride (padded -1/+inf), distance computations,
  * expansions, and the smallest relative decision margin seen (float data).
- * feat (optional, nq x OR_NFEAT) receives the state after the first expansion. */
+ * feat (optional, nq x OR_NFEAT) receives the state at the switch: 8 seed
+ * distances ascending, |S|, the smallest / ceil(m/2)-th / m-th distance of the
+ * m = min(|S|, 64) smallest in S, the largest distance in R, the distance
+ * computations so far. */
 #define OR_NFEAT 14
 int or_search(const or_vecs *base, const int64_t *offsets, const int32_t *nbrs,
               int64_t n_nodes, const or_vecs *queries, int64_t nq,
               const int32_t *seeds, int32_t n_seeds,
               const int32_t *k, const float *eps, const uint32_t *ep,
-              const float *eps1, const uint32_t *ep1,
+              const float *eps1, const uint32_t *ep1, int32_t probe_hops,
               int32_t k_stride, int32_t *out_ids, double *out_d,
               int64_t *out_dc, int64_t *out_hops, double *out_margin,
               double *feat, int32_t nthreads);

@@ -15,6 +15,7 @@ U8, F32, F16, BF16, FP8_E4M3 = 0, 1, 2, 3, 4
 L2SQ, COSINE = 0, 1
 NFEAT = 14
 QF_PADDED, QF_SPILLED, QF_CAPACITY = 1, 2, 4
+PRED_LOG_EPS, PRED_CURVE = 0, 1
 EP_INF = 0xFFFFFFFF
 
 P = C.c_void_p
@@ -35,7 +36,8 @@ class Predictor_t(C.Structure):
                 ("feat_std", P), ("shift", P), ("head_per_query", P), ("head", C.c_int32),
                 ("n_features", C.c_int32), ("hidden", C.c_int32), ("n_heads", C.c_int32),
                 ("eps_min", C.c_float), ("eps_max", C.c_float), ("e0", C.c_float),
-                ("we", C.c_float)]
+                ("we", C.c_float), ("mode", C.c_int32), ("n_cand", C.c_int32),
+                ("eps_cand", P), ("lambda_", C.c_float), ("lambda_per_query", P)]
 
 
 class LaunchConfig_t(C.Structure):
@@ -49,7 +51,7 @@ class SearchParams_t(C.Structure):
                 ("epsilon", C.c_float), ("eps_per_query", P), ("e_p", C.c_uint32),
                 ("ep_per_query", P), ("two_phase", C.c_int32), ("ep_first", C.c_uint32),
                 ("predictor", P), ("features_out", P), ("rerank_base", P),
-                ("pool_factor", C.c_int32), ("launch", P)]
+                ("pool_factor", C.c_int32), ("launch", P), ("probe_hops", C.c_uint32)]
 
 
 # exported symbols and their prototypes (must match include/onng.h)

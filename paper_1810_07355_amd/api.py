@@ -152,7 +152,10 @@ def adjust_path(g: Graph, dtype: int, metric: int) -> Graph:
 
 @dataclasses.dataclass
 class Predictor:
-    """Weights of the search-range predictor (bf16 matrices, f32 vectors)."""
+    """Weights of the search-range predictor (bf16 matrices, f32 vectors).
+    mode L.PRED_LOG_EPS: head `head` predicts log10(eps + 0.01) (+ shift).
+    mode L.PRED_CURVE: heads [0, G) recall and [G, 2G) log(1 + distance
+    computations) at eps_cand[g]; the query takes argmax recall - lambda*cost."""
     w1_bf16: torch.Tensor
     b1: torch.Tensor
     w2_bf16: torch.Tensor
@@ -166,13 +169,19 @@ class Predictor:
     eps_max: float = 0.5
     e0: float = 30.0
     we: float = -1.0
+    mode: int = L.PRED_LOG_EPS
+    eps_cand: torch.Tensor | None = None
+    lam: float = 0.0
+    lambda_per_query: torch.Tensor | None = None
 
     def struct(self):
         return L.Predictor_t(self.w1_bf16.data_ptr(), self.b1.data_ptr(), self.w2_bf16.data_ptr(),
                              self.b2.data_ptr(), self.mean.data_ptr(), self.std.data_ptr(),
                              _ptr(self.shift), _ptr(self.head_per_query), self.head, L.NFEAT,
                              self.b1.numel(), self.b2.numel(), self.eps_min, self.eps_max,
-                             self.e0, self.we)
+                             self.e0, self.we, self.mode,
+                             0 if self.eps_cand is None else self.eps_cand.numel(),
+                             _ptr(self.eps_cand), self.lam, _ptr(self.lambda_per_query))
 
 
 def launch_config(waves_per_block=0, lanes_per_row=0, s_capacity=0, visited_log2=0,
@@ -187,7 +196,7 @@ class SearchRequest:
     def __init__(self, base: Vectors, graph: Graph, queries: Vectors, seeds: torch.Tensor, k=10,
                  k_stride=None, eps=0.0, ep=L.EP_INF, two_phase=False, ep_first=L.EP_INF,
                  predictor: Predictor | None = None, want_features=False,
-                 rerank_base: Vectors | None = None, pool_factor=4, launch=None):
+                 rerank_base: Vectors | None = None, pool_factor=4, launch=None, probe_hops=1):
         dev = queries.data.device
         nq = queries.n
         self.base, self.graph, self.queries = base, graph, queries
@@ -220,7 +229,8 @@ class SearchRequest:
             C.cast(C.byref(self._pred_s), C.c_void_p) if predictor else None,
             _ptr(self.features),
             C.cast(rerank_base.ref, C.c_void_p) if rerank_base else None,
-            int(pool_factor), C.cast(C.byref(launch), C.c_void_p) if launch is not None else None)
+            int(pool_factor), C.cast(C.byref(launch), C.c_void_p) if launch is not None else None,
+            int(probe_hops))
         self.gs = graph.struct()
         out_dt = torch.float32 if rerank_base is not None else base.dist_dtype
         self.ids = torch.empty((nq, self.k_stride), dtype=torch.int32, device=dev)

@@ -172,7 +172,7 @@ static onng_status make_plan(const onng_vectors *base, int64_t nq, const onng_se
     P.off_stage2 = o; o = align16(o + 64 * 8);
     P.off_ids = o; o = align16(o + 64 * 4);
     P.off_vis = o; o = align16(o + (P.vis_log2 ? (4 << P.vis_log2) : 0));
-    P.off_misc = o; o = align16(o + 96 * 4);
+    P.off_misc = o; o = align16(o + 168 * 4);
     P.lds_per_wave = o;
     size_t lds = (size_t)o * P.wpb;
     if (lds > 160 * 1024) {
@@ -236,10 +236,17 @@ static onng_status validate_search(const onng_vectors *base, const onng_graph *g
         ONNG_CHECK_ARG(p->two_phase, "a predictor needs two_phase");
         ONNG_CHECK_ARG(pr->n_features == ONNG_NFEAT, "predictor n_features must be ONNG_NFEAT");
         ONNG_CHECK_ARG(pr->hidden >= 1 && pr->hidden <= 64, "predictor hidden must be in [1, 64]");
-        ONNG_CHECK_ARG(pr->n_heads >= 1 && pr->n_heads <= 8, "predictor n_heads must be in [1, 8]");
+        ONNG_CHECK_ARG(pr->n_heads >= 1 && pr->n_heads <= 16, "predictor n_heads must be in [1, 16]");
+        ONNG_CHECK_ARG(pr->mode == ONNG_PRED_LOG_EPS || pr->mode == ONNG_PRED_CURVE,
+                       "unknown predictor mode");
+        if (pr->mode == ONNG_PRED_CURVE)
+            ONNG_CHECK_ARG(pr->n_cand >= 1 && pr->n_cand <= 8 && pr->n_heads == 2 * pr->n_cand &&
+                               pr->eps_cand,
+                           "curve predictor needs n_cand in [1, 8], n_heads = 2 n_cand, eps_cand");
         ONNG_CHECK_ARG(pr->w1_bf16 && pr->b1 && pr->w2_bf16 && pr->b2 && pr->feat_mean && pr->feat_std,
                        "predictor weights missing");
-        ONNG_CHECK_ARG(pr->head_per_query || (pr->head >= 0 && pr->head < pr->n_heads),
+        ONNG_CHECK_ARG(pr->mode == ONNG_PRED_CURVE || pr->head_per_query ||
+                           (pr->head >= 0 && pr->head < pr->n_heads),
                        "predictor head out of range");
         ONNG_CHECK_ARG(pr->eps_min >= 0.0f && pr->eps_max >= pr->eps_min, "bad eps clamp");
     }
@@ -257,10 +264,7 @@ static onng_status run_search(const onng_vectors *base, const onng_graph *g,
     if (queries->n == 0) return ONNG_OK;
     SearchPlan P;
     ONNG_TRY(make_plan(base, queries->n, p, cfg, &P));
-    if (p->two_phase && (int64_t)p->ep_first + n_seeds > P.s_cap) {
-        set_error("onng_search: ep_first + n_seeds must fit the on-chip candidate set");
-        return ONNG_ERR_INVALID_ARG;
-    }
+
     if (!ws || ws_bytes < P.ws) {
         set_error("onng_search: workspace too small (" + std::to_string(P.ws) + " bytes needed)");
         return ONNG_ERR_WORKSPACE;
@@ -293,6 +297,7 @@ static onng_status run_search(const onng_vectors *base, const onng_graph *g,
     a.ep_pq = p->ep_per_query;
     a.two_phase = p->two_phase;
     a.ep_first = p->ep_first;
+    a.probe_hops = p->probe_hops ? p->probe_hops : 1;
     a.has_pred = p->predictor != nullptr;
     if (p->predictor) {
         const onng_predictor *pr = p->predictor;
@@ -312,6 +317,11 @@ static onng_status run_search(const onng_vectors *base, const onng_graph *g,
         a.pred.eps_max = pr->eps_max;
         a.pred.e0 = pr->e0;
         a.pred.we = pr->we;
+        a.pred.mode = pr->mode;
+        a.pred.n_cand = pr->n_cand;
+        a.pred.eps_cand = pr->eps_cand;
+        a.pred.lambda = pr->lambda;
+        a.pred.lambda_pq = pr->lambda_per_query;
     }
     a.feat_out = p->two_phase ? p->features_out : nullptr;
     a.has_rr = p->rerank_base != nullptr;
@@ -525,7 +535,6 @@ onng_status onng_autotune_search(const onng_vectors *base, const onng_graph *gra
         SearchPlan P;
         if (make_plan(base, queries->n, params, &c, &P) != ONNG_OK) continue;
         if (P.ws > ws_bytes) continue;
-        if (params->two_phase && (int64_t)params->ep_first + n_seeds > P.s_cap) continue;
         // warm-up, then two timed runs
         if (run_search(base, graph, queries, seeds, n_seeds, params, ids, dists, stats, ws,
                        ws_bytes, st, &c) != ONNG_OK)

@@ -511,23 +511,25 @@ search_kernel(SearchKArgs a) {
                 absorb(key, u, true);
             }
 
-            if (a.two_phase && hops == 1) {
-                // ---- state after the first expansion -> search range ----
-                // lane t < 14 computes feature t (see predict_eps for the list)
+            if (a.two_phase && hops == (int)a.probe_hops) {
+                // ---- state after the probe expansions -> search range ----
+                if (spill_n > 0) refill();   // the smallest keys of S on chip
                 int nseed = (int)lds.misc[64];
-                int ns = size - head;   // no spill can happen in the first expansion
+                int ns = size - head + spill_n;
+                int m = min(size - head, 64);
                 float rmax = npool > 0 ? key_dist<INT>(lds.pool[min(npool, k) - 1]) : 0.0f;
+                // lane t < 14 computes feature t
                 float fv = 0.0f;
                 if (lane < 8) fv = nseed == 0 ? 0.0f : lds.misc[lane < nseed ? lane : nseed - 1];
                 else if (lane == 8) fv = (float)ns;
-                else if (lane == 9) fv = ns > 0 ? key_dist<INT>(lds.S[head]) : rmax;
-                else if (lane == 10) fv = ns > 0 ? key_dist<INT>(lds.S[head + (ns - 1) / 2]) : rmax;
-                else if (lane == 11) fv = ns > 0 ? key_dist<INT>(lds.S[size - 1]) : rmax;
+                else if (lane == 9) fv = m > 0 ? key_dist<INT>(lds.S[head]) : rmax;
+                else if (lane == 10) fv = m > 0 ? key_dist<INT>(lds.S[head + (m + 1) / 2 - 1]) : rmax;
+                else if (lane == 11) fv = m > 0 ? key_dist<INT>(lds.S[head + m - 1]) : rmax;
                 else if (lane == 12) fv = rmax;
                 else if (lane == 13) fv = (float)dc;
                 if (a.feat_out && lane < ONNG_NFEAT) a.feat_out[(size_t)qi * ONNG_NFEAT + lane] = fv;
                 if (a.has_pred) {
-                    eps = predict_eps(a.pred, fv, MT, qi, lane, lds.misc + 80);
+                    eps = predict_eps(a.pred, fv, MT, qi, lane, lds.misc + 72);
                     eps = unif(eps);
                     ep = a.pred.we >= 0.0f ? dynamic_ep(eps, a.pred.e0, a.pred.we)
                                            : (a.ep_pq ? uniu(a.ep_pq[qi]) : a.ep);

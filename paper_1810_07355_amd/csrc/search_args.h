@@ -22,6 +22,11 @@ struct PredArgs {
     int32_t head;
     int32_t F, H, T;
     float eps_min, eps_max, e0, we;
+    int32_t mode;             // ONNG_PRED_LOG_EPS or ONNG_PRED_CURVE
+    int32_t n_cand;
+    const float *eps_cand;    // [n_cand]
+    float lambda;
+    const float *lambda_pq;   // [nq] or null
 };
 
 struct SearchKArgs {
@@ -51,6 +56,7 @@ struct SearchKArgs {
     const uint32_t *ep_pq;
     int32_t two_phase;
     uint32_t ep_first;
+    uint32_t probe_hops;
     int32_t has_pred;
     PredArgs pred;
     float *feat_out;
@@ -81,11 +87,13 @@ struct SearchKArgs {
     int32_t off_pool, off_s, off_stage, off_stage2, off_ids, off_vis, off_misc;
 };
 
-// log10(eps + 0.01) heads -> eps for this query.  Lane t < 14 holds raw
-// feature t of the state after the first expansion: 0-7 the 8 seed
-// distances ascending, 8 |S|, 9-11 min/median/max distance in S, 12 the
-// radius of R, 13 distance computations.  `scratch` is 16 floats of LDS.
-// All lanes return the same value.
+// Search range of one query from the state after the probe expansions.
+// Lane t < 14 holds raw feature t (0-7 seed distances ascending, 8 |S|,
+// 9-11 smallest / middle / m-th of the m = min(|S|, 64) smallest distances in
+// S, 12 the largest distance in R, 13 distance computations).  `scratch` is
+// 96 floats of LDS.  Features enter as log distances (relative to the
+// nearest seed) and log(1 + count), z-scored; the hidden layer runs one unit
+// per lane, the heads one per lane.  All lanes return the same value.
 __device__ inline float predict_eps(const PredArgs &P, float fv, int metric, int qi, int lane,
                                     float *scratch) {
     const float c = metric == ONNG_COSINE ? 1e-3f : 1.0f;
@@ -95,22 +103,55 @@ __device__ inline float predict_eps(const PredArgs &P, float fv, int metric, int
     if (lane == 0) x = lg;
     else if (lane == 8 || lane == 13) x = log1pf(fv);
     else x = lg - lg0;
-    if (lane < ONNG_NFEAT) scratch[lane] = (x - P.mean[lane]) / P.stdv[lane];
+    float *z = scratch;          // [16]
+    float *hid = scratch + 16;   // [64]
+    float *yv = scratch + 80;    // [16]
+    if (lane < ONNG_NFEAT) z[lane] = (x - P.mean[lane]) / P.stdv[lane];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    const int head = P.head_pq ? P.head_pq[qi] : P.head;
     float h = 0.0f;
     if (lane < P.H) {
         float s = P.b1[lane];
-        for (int t = 0; t < P.F; t++) {
-            float wv = __uint_as_float((uint32_t)P.w1[lane * P.F + t] << 16);
-            s = fmaf(wv, scratch[t], s);
-        }
-        h = fmaxf(s, 0.0f) * __uint_as_float((uint32_t)P.w2[head * P.H + lane] << 16);
+        for (int t = 0; t < P.F; t++)
+            s = fmaf(__uint_as_float((uint32_t)P.w1[lane * P.F + t] << 16), z[t], s);
+        h = fmaxf(s, 0.0f);
+        hid[lane] = h;
     }
-    for (int m = 32; m >= 1; m >>= 1) h += __shfl_xor(h, m);
-    float y = h + P.b2[head] + (P.shift ? P.shift[head] : 0.0f);
-    float eps = exp10f(y) - 0.01f;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    float y = 0.0f;
+    if (lane < P.T) {
+        y = P.b2[lane];
+        for (int j = 0; j < P.H; j++)
+            y = fmaf(__uint_as_float((uint32_t)P.w2[lane * P.H + j] << 16), hid[j], y);
+        yv[lane] = y;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    float eps;
+    if (P.mode == ONNG_PRED_CURVE) {
+        const float lam = P.lambda_pq ? P.lambda_pq[qi] : P.lambda;
+        const int G = P.n_cand;
+        // score of candidate g = predicted recall - lambda * predicted cost
+        float score = -__builtin_inff();
+        if (lane < G) score = yv[lane] - lam * (expf(yv[G + lane]) - 1.0f);
+        // argmax over lanes, smallest index on ties
+        int best = lane;
+        for (int m = 32; m >= 1; m >>= 1) {
+            float os = __shfl_xor(score, m);
+            int ob = __shfl_xor(best, m);
+            if (os > score || (os == score && ob < best)) {
+                score = os;
+                best = ob;
+            }
+        }
+        best = __shfl(best, 0);
+        eps = P.eps_cand[best < G ? best : 0];
+    } else {
+        const int head = P.head_pq ? P.head_pq[qi] : P.head;
+        float yh = yv[head] + (P.shift ? P.shift[head] : 0.0f);
+        eps = exp10f(yh) - 0.01f;
+    }
     return fminf(fmaxf(eps, P.eps_min), P.eps_max);
 }
 

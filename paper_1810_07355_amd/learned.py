@@ -60,19 +60,26 @@ class Trained:
     losses: list
 
     def predictor(self, head=0, shift=None, eps_min=0.0, eps_max=0.5, e0=30.0, we=20.0,
-                  head_per_query=None) -> api.Predictor:
+                  head_per_query=None, mode=L.PRED_LOG_EPS, eps_cand=None, lam=0.0,
+                  lambda_per_query=None) -> api.Predictor:
         dev = self.W1.device
-        if shift is None:
+        if shift is None and mode == L.PRED_LOG_EPS:
             shift = torch.zeros(self.W2.shape[0], dtype=torch.float32, device=dev)
+        cand = None
+        if eps_cand is not None:
+            cand = torch.as_tensor(np.asarray(eps_cand, dtype=np.float32), device=dev)
         return api.Predictor(api.to_bf16_bits(self.W1), self.b1, api.to_bf16_bits(self.W2),
                              self.b2, self.mean, self.std, shift=shift, head=head,
                              head_per_query=head_per_query, eps_min=eps_min, eps_max=eps_max,
-                             e0=e0, we=we)
+                             e0=e0, we=we, mode=mode, eps_cand=cand, lam=lam,
+                             lambda_per_query=lambda_per_query)
 
 
-def train(features: torch.Tensor, labels: np.ndarray, metric: int, hidden: int = 64,
-          steps: int = 3000, batch: int = 1024, lr: float = 3e-3, seed: int = 0) -> Trained:
-    """features: raw [n, 14] f32 on the GPU; labels: [n, T] eps values."""
+def train_targets(features: torch.Tensor, Y: np.ndarray, metric: int, hidden: int = 64,
+                  steps: int = 4000, batch: int = 1024, lr: float = 3e-3, seed: int = 0) -> Trained:
+    """Fit the perceptron to targets Y [n, T] (mean squared error, each target
+    column standardised during training and folded back into the last layer).
+    features: raw [n, 14] f32 on the GPU."""
     dev = features.device
     X = api.feature_transform(features.contiguous(), metric)
     torch.cuda.synchronize()
@@ -81,14 +88,18 @@ def train(features: torch.Tensor, labels: np.ndarray, metric: int, hidden: int =
     std = xh.std(axis=0)
     std = np.where(std < 1e-6, 1.0, std)
     Xz = torch.from_numpy(((xh - mean) / std).astype(np.float32)).to(dev)
-    Y = torch.from_numpy(eps_to_target(labels).astype(np.float32)).to(dev)
+    Y = np.asarray(Y, dtype=np.float64)
+    ym = Y.mean(axis=0)
+    ys = Y.std(axis=0)
+    ys = np.where(ys < 1e-6, 1.0, ys)
+    Yt = torch.from_numpy(((Y - ym) / ys).astype(np.float32)).to(dev)
     n, F = Xz.shape
-    T = Y.shape[1]
+    T = Yt.shape[1]
     g = np.random.default_rng(seed)
     W1 = torch.from_numpy((g.standard_normal((hidden, F)) * math.sqrt(2.0 / F)).astype(np.float32)).to(dev)
     b1 = torch.zeros(hidden, dtype=torch.float32, device=dev)
     W2 = torch.from_numpy((g.standard_normal((T, hidden)) * math.sqrt(1.0 / hidden)).astype(np.float32)).to(dev)
-    b2 = torch.from_numpy(Y.mean(dim=0).cpu().numpy()).to(dev)
+    b2 = torch.zeros(T, dtype=torch.float32, device=dev)
     params = [W1, b1, W2, b2]
     ms = [torch.zeros_like(p) for p in params]
     vs = [torch.zeros_like(p) for p in params]
@@ -103,16 +114,34 @@ def train(features: torch.Tensor, labels: np.ndarray, metric: int, hidden: int =
         idx = torch.from_numpy(perm[pos:pos + batch]).to(dev)
         pos += batch
         xb = Xz.index_select(0, idx).contiguous()
-        yb = Y.index_select(0, idx).contiguous()
+        yb = Yt.index_select(0, idx).contiguous()
         loss, grads = api.mlp_backward(xb, yb, W1, b1, W2, b2)
         step_lr = lr * (0.5 * (1.0 + math.cos(math.pi * t / steps)) * 0.9 + 0.1)
         for p, gr, m, v in zip(params, grads, ms, vs):
             api.adam_step(p, gr, m, v, step_lr, t)
         if t % 100 == 0 or t == 1:
             losses.append(float(loss.item()))
+    # fold the target standardisation into the last layer
+    ys_t = torch.from_numpy(ys.astype(np.float32)).to(dev)
+    ym_t = torch.from_numpy(ym.astype(np.float32)).to(dev)
+    W2 = (W2 * ys_t[:, None]).contiguous()
+    b2 = (b2 * ys_t + ym_t).contiguous()
     mean_t = torch.from_numpy(mean.astype(np.float32)).to(dev)
     std_t = torch.from_numpy(std.astype(np.float32)).to(dev)
     return Trained(W1, b1, W2, b2, mean_t, std_t, losses)
+
+
+def train(features: torch.Tensor, labels: np.ndarray, metric: int, **kw) -> Trained:
+    """Log-range heads: each target recall's smallest sufficient eps."""
+    return train_targets(features, eps_to_target(labels), metric, **kw)
+
+
+def curve_targets(recalls: np.ndarray, dcs: np.ndarray, cand_idx) -> np.ndarray:
+    """[n, 2G]: recall at each candidate range, then log(1 + distance
+    computations) there (recalls, dcs: [n_eps, n])."""
+    cand_idx = list(cand_idx)
+    return np.concatenate([recalls[cand_idx].T, np.log1p(dcs[cand_idx].T.astype(np.float64))],
+                          axis=1)
 
 
 def calibrate(run_recall, target: float, lo: float = -1.0, hi: float = 1.0, iters: int = 9,

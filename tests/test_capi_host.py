@@ -45,11 +45,12 @@ int main(void) {
   P(onng_vectors) P(onng_graph) P(onng_predictor) P(onng_launch_config) P(onng_search_params)
   P(onng_query_stats)
   O(onng_vectors, pitch_bytes) O(onng_vectors, metric)
-  O(onng_predictor, head) O(onng_predictor, we)
+  O(onng_predictor, head) O(onng_predictor, we) O(onng_predictor, mode)
+  O(onng_predictor, eps_cand) O(onng_predictor, lambda_per_query)
   O(onng_search_params, eps_per_query) O(onng_search_params, ep_per_query)
   O(onng_search_params, two_phase) O(onng_search_params, predictor)
   O(onng_search_params, rerank_base) O(onng_search_params, pool_factor)
-  O(onng_search_params, launch)
+  O(onng_search_params, launch) O(onng_search_params, probe_hops)
   return 0;
 }
 ''')
@@ -66,6 +67,7 @@ int main(void) {
     for key, val in out.items():
         if "." in key:
             sname, field = key.split(".")
+            field = {"lambda": "lambda_"}.get(field, field)
             assert getattr(ct[sname], field).offset == int(val), key
 
 

@@ -272,40 +272,66 @@ def test_search_mixed_k_eps_ep_per_query():
     assert np.array_equal(host(r.hops), ref["hops"])
 
 
-def test_two_phase_features_and_predictor_replay():
+@pytest.mark.parametrize("probe,shape", [(1, None), (3, None), (3, dict(s_capacity=64))])
+def test_two_phase_features(probe, shape):
+    """Features after `probe` expansions equal the oracle's, also when the
+    candidate set spills during the probe (64 on-chip slots)."""
     P = c1_problem()
-    po, pn, _ = P["pa"]
-    A, Lb = api(), L()
-    say("two-phase features")
-    ref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, 0.05, 40, eps1=np.inf, ep1=64,
-                     want_features=True)
-    r = A.search(gpu_vectors(P["x"], orc.L2SQ), gpu_graph(po, pn), gpu_vectors(P["q"], orc.L2SQ),
-                 to_dev(P["seeds"]), k=10, eps=0.05, ep=40, two_phase=True, ep_first=64,
-                 want_features=True)
+    off, nb, _ = P["sa"]
+    A = api()
+    say("two-phase features probe", probe, shape)
+    ref = orc.search(P["bv"], off, nb, P["qv"], P["seeds"], 10, 0.05, 40, eps1=np.inf, ep1=100,
+                     want_features=True, probe_hops=probe)
+    cfg = A.launch_config(**shape) if shape else None
+    r = A.search(gpu_vectors(P["x"], orc.L2SQ), gpu_graph(off, nb), gpu_vectors(P["q"], orc.L2SQ),
+                 to_dev(P["seeds"]), k=10, eps=0.05, ep=40, two_phase=True, ep_first=100,
+                 probe_hops=probe, want_features=True, launch=cfg)
     torch.cuda.synchronize()
     assert np.array_equal(host(r.ids), ref["ids"])
     assert np.array_equal(host(r.dc), ref["dc"])
+    assert np.array_equal(host(r.hops), ref["hops"])
     assert np.array_equal(host(r.features).astype(np.float64), ref["feat"])
-    # a random predictor: replay the oracle with the eps / e_p the kernel used
-    say("predictor replay")
-    g = np.random.default_rng(7)
+
+
+def _random_predictor(A, T, mode, g, **kw):
     H = 64
     w1 = torch.from_numpy(g.standard_normal((H, 14)).astype(np.float32) * 0.3).to(dev())
-    w2 = torch.from_numpy(g.standard_normal((3, H)).astype(np.float32) * 0.1).to(dev())
-    pred = A.Predictor(A.to_bf16_bits(w1), to_dev(np.zeros(H, np.float32)), A.to_bf16_bits(w2),
-                       to_dev(np.array([-1.2, -1.0, -0.8], np.float32)),
+    w2 = torch.from_numpy(g.standard_normal((T, H)).astype(np.float32) * 0.1).to(dev())
+    return A.Predictor(A.to_bf16_bits(w1), to_dev(np.zeros(H, np.float32)), A.to_bf16_bits(w2),
+                       to_dev((g.standard_normal(T) * 0.5 - 1.0).astype(np.float32)),
                        to_dev(np.zeros(14, np.float32)), to_dev(np.ones(14, np.float32)),
-                       head=1, eps_min=0.0, eps_max=0.3, e0=30.0, we=20.0)
+                       mode=mode, **kw)
+
+
+@pytest.mark.parametrize("mode", ["log_eps", "curve"])
+def test_predictor_replay(mode):
+    """The search with a predictor equals the oracle replayed with the range
+    and e_p the kernel reports for each query."""
+    P = c1_problem()
+    po, pn, _ = P["pa"]
+    A, Lb = api(), L()
+    g = np.random.default_rng(7)
+    say("predictor replay", mode)
+    if mode == "log_eps":
+        pred = _random_predictor(A, 3, Lb.PRED_LOG_EPS, g, head=1, eps_min=0.0, eps_max=0.3,
+                                 e0=30.0, we=20.0)
+    else:
+        cand = to_dev(np.array([0.0, 0.02, 0.05, 0.1], np.float32))
+        lam = to_dev(g.uniform(1e-4, 1e-2, len(P["q"])).astype(np.float32))
+        pred = _random_predictor(A, 8, Lb.PRED_CURVE, g, eps_min=0.0, eps_max=0.3, e0=30.0,
+                                 we=20.0, eps_cand=cand, lam=1e-3, lambda_per_query=lam)
     r = A.search(gpu_vectors(P["x"], orc.L2SQ), gpu_graph(po, pn), gpu_vectors(P["q"], orc.L2SQ),
                  to_dev(P["seeds"]), k=10, eps=0.0, ep=orc.INF_EP, two_phase=True, ep_first=64,
-                 predictor=pred)
+                 predictor=pred, probe_hops=2)
     torch.cuda.synchronize()
     eps_used = host(r.eps_used)
     ep_used = host(r.ep_used).astype(np.uint32)
     assert np.all((eps_used >= 0) & (eps_used <= 0.3))
     assert len(np.unique(eps_used)) > 1
+    if mode == "curve":
+        assert set(np.unique(eps_used).tolist()) <= {np.float32(v) for v in (0.0, 0.02, 0.05, 0.1)}
     ref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, eps_used, ep_used, eps1=np.inf,
-                     ep1=64)
+                     ep1=64, probe_hops=2)
     assert np.array_equal(host(r.ids), ref["ids"])
     assert np.array_equal(host(r.dc), ref["dc"])
     assert np.array_equal(host(r.hops), ref["hops"])
