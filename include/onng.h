@@ -286,7 +286,8 @@ onng_status onng_rerank(const onng_vectors *queries, const onng_vectors *base,
 /* Learned search range: training kernels (not part of the paper)           */
 /* ------------------------------------------------------------------------ */
 
-/* Y = W2 relu(W1 X + b1) + b2, all f32 row-major; hidden [batch][H] optional. */
+/* Y = W2 relu(W1 X + b1) + b2, all f32 row-major; hidden [batch][H] optional.
+ * H <= 64, T <= 16. */
 onng_status onng_mlp_forward(const float *X, int32_t batch, int32_t F, const float *W1,
                              const float *b1, int32_t H, const float *W2, const float *b2,
                              int32_t T, float *hidden, float *Y, void *stream);

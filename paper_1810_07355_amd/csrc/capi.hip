@@ -599,8 +599,8 @@ onng_status onng_mlp_forward(const float *X, int32_t batch, int32_t F, const flo
                              const float *b1, int32_t H, const float *W2, const float *b2,
                              int32_t T, float *hidden, float *Y, void *stream) {
     set_error("");
-    ONNG_CHECK_ARG(batch >= 0 && F >= 1 && H >= 1 && H <= 64 && T >= 1 && T <= 8,
-                   "sizes: H in [1, 64], T in [1, 8]");
+    ONNG_CHECK_ARG(batch >= 0 && F >= 1 && H >= 1 && H <= 64 && T >= 1 && T <= 16,
+                   "sizes: H in [1, 64], T in [1, 16]");
     ONNG_CHECK_ARG(batch == 0 || (X && W1 && b1 && W2 && b2 && Y), "null pointer");
     return mlp_forward_launch(X, batch, F, W1, b1, H, W2, b2, T, hidden, Y, as_stream(stream));
 }
@@ -616,8 +616,8 @@ onng_status onng_mlp_backward(const float *X, const float *target, const float *
                               float *gb1, float *gW2, float *gb2, float *loss, void *ws,
                               size_t ws_bytes, void *stream) {
     set_error("");
-    ONNG_CHECK_ARG(batch >= 1 && F >= 1 && H >= 1 && H <= 64 && T >= 1 && T <= 8,
-                   "sizes: batch >= 1, H in [1, 64], T in [1, 8]");
+    ONNG_CHECK_ARG(batch >= 1 && F >= 1 && H >= 1 && H <= 64 && T >= 1 && T <= 16,
+                   "sizes: batch >= 1, H in [1, 64], T in [1, 16]");
     ONNG_CHECK_ARG(X && target && W1 && b1 && W2 && b2 && gW1 && gb1 && gW2 && gb2 && loss,
                    "null pointer");
     if (!ws || ws_bytes < mlp_backward_ws(batch, H, T)) {

@@ -30,7 +30,7 @@ __global__ void mlp_sample_kernel(const float *X, int batch, int F, const float 
         h[j] = fmaxf(s, 0.0f);
         if (hid) hid[(int64_t)n * H + j] = h[j];
     }
-    float g[8];
+    float g[16];
     float l = 0.0f;
     const float scale = 1.0f / ((float)batch * (float)T);
     for (int t = 0; t < T; t++) {

@@ -293,14 +293,16 @@ def test_two_phase_features(probe, shape):
     assert np.array_equal(host(r.features).astype(np.float64), ref["feat"])
 
 
-def _random_predictor(A, T, mode, g, **kw):
+def _random_predictor(A, T, mode, g, feat, b2, **kw):
+    """Random weights; features z-scored with the statistics of `feat`
+    (oracle features of the same queries) so the outputs spread."""
     H = 64
+    x = orc.feature_transform(feat, orc.L2SQ)
     w1 = torch.from_numpy(g.standard_normal((H, 14)).astype(np.float32) * 0.3).to(dev())
     w2 = torch.from_numpy(g.standard_normal((T, H)).astype(np.float32) * 0.1).to(dev())
     return A.Predictor(A.to_bf16_bits(w1), to_dev(np.zeros(H, np.float32)), A.to_bf16_bits(w2),
-                       to_dev((g.standard_normal(T) * 0.5 - 1.0).astype(np.float32)),
-                       to_dev(np.zeros(14, np.float32)), to_dev(np.ones(14, np.float32)),
-                       mode=mode, **kw)
+                       to_dev(np.asarray(b2, np.float32)), to_dev(x.mean(0).astype(np.float32)),
+                       to_dev((x.std(0) + 1e-3).astype(np.float32)), mode=mode, **kw)
 
 
 @pytest.mark.parametrize("mode", ["log_eps", "curve"])
@@ -312,14 +314,18 @@ def test_predictor_replay(mode):
     A, Lb = api(), L()
     g = np.random.default_rng(7)
     say("predictor replay", mode)
+    feat = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, 0.0, orc.INF_EP, eps1=np.inf,
+                      ep1=64, probe_hops=2, want_features=True)["feat"]
     if mode == "log_eps":
-        pred = _random_predictor(A, 3, Lb.PRED_LOG_EPS, g, head=1, eps_min=0.0, eps_max=0.3,
-                                 e0=30.0, we=20.0)
+        pred = _random_predictor(A, 3, Lb.PRED_LOG_EPS, g, feat, [-1.5, -1.2, -1.0], head=1,
+                                 eps_min=0.0, eps_max=0.3, e0=30.0, we=20.0)
     else:
         cand = to_dev(np.array([0.0, 0.02, 0.05, 0.1], np.float32))
-        lam = to_dev(g.uniform(1e-4, 1e-2, len(P["q"])).astype(np.float32))
-        pred = _random_predictor(A, 8, Lb.PRED_CURVE, g, eps_min=0.0, eps_max=0.3, e0=30.0,
-                                 we=20.0, eps_cand=cand, lam=1e-3, lambda_per_query=lam)
+        lam = to_dev(10.0 ** g.uniform(-3, 0, len(P["q"])).astype(np.float32))
+        pred = _random_predictor(A, 8, Lb.PRED_CURVE, g, feat,
+                                 [0.5, 0.6, 0.8, 0.9, 5.0, 5.2, 5.5, 6.0], eps_min=0.0,
+                                 eps_max=0.3, e0=30.0, we=20.0, eps_cand=cand, lam=1e-3,
+                                 lambda_per_query=lam)
     r = A.search(gpu_vectors(P["x"], orc.L2SQ), gpu_graph(po, pn), gpu_vectors(P["q"], orc.L2SQ),
                  to_dev(P["seeds"]), k=10, eps=0.0, ep=orc.INF_EP, two_phase=True, ep_first=64,
                  predictor=pred, probe_hops=2)
