@@ -224,8 +224,11 @@ def main():
     if args.dump:
         hf, hr, hd = label_sweep(queries, seeds, gt)
         np.savez_compressed(args.dump, grid=np.array(grid), train_feat=feats.cpu().numpy(),
-                            train_recall=recalls, train_dc=dcs, test_feat=hf.cpu().numpy(),
-                            test_recall=hr, test_dc=hd, probe_hops=PROBE)
+                            train_recall10=np.rint(recalls * K).astype(np.uint8),
+                            train_dc=np.minimum(dcs, 65535).astype(np.uint16),
+                            test_feat=hf.cpu().numpy(),
+                            test_recall10=np.rint(hr * K).astype(np.uint8),
+                            test_dc=np.minimum(hd, 65535).astype(np.uint16), probe_hops=PROBE)
         log("dumped sweep data to", args.dump)
     garr = np.array(grid)
     models = {}
@@ -244,9 +247,8 @@ def main():
     def make_learned(tgt):
         def make(knob):   # knob = -log10(lambda): larger spends more
             pred = learned_pred(tgt, knob)
-            req = A.SearchRequest(search_rows, graph, queries, seeds, k=K, eps=0.0, ep=L.EP_INF,
-                                  two_phase=True, ep_first=EPF, probe_hops=PROBE, predictor=pred,
-                                  **rr)
+            req = A.LearnedSearch(search_rows, graph, queries, seeds, pred, ep_first=EPF,
+                                  probe_hops=PROBE, k=K, **rr)
             req._pred = pred
             return req
         return make
@@ -301,9 +303,13 @@ def main():
         log(f"plain f32 pipeline at eps={plain95['knob']}: {plain_pipe_qps:.0f} q/s")
 
     # ---------------------------------------- roofline of the search kernel --
-    req = make_learned(0.95)(knobs[0.95])
+    lreq = make_learned(0.95)(knobs[0.95])
+    lreq.run()
+    req = lreq.req                 # the search pass (predict pass and order excluded)
     ms_search = time_req(req, reps=5)
     st = req.stats.cpu().numpy()
+    log(f"queries with candidate-set spill: {(st[:, 2] & L.QF_SPILLED != 0).mean():.3f}; "
+        f"over capacity: {(st[:, 2] & L.QF_CAPACITY != 0).mean():.4f}")
     dc, hops, scanned = st[:, 0].astype(np.float64), st[:, 1].astype(np.float64), st[:, 5].astype(np.float64)
     dim = cfg.dim
     row_bytes = {L.U8: dim, L.F32: 4 * dim, L.F16: 2 * dim, L.BF16: 2 * dim,

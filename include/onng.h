@@ -190,6 +190,8 @@ typedef struct {
 #define ONNG_PRED_CURVE 1
 #define ONNG_NFEAT 14
 
+struct onng_query_stats_s;
+
 /* Launch shape of the search kernel (0 = library default for a field). */
 typedef struct {
     int32_t waves_per_block;   /* 1..8 */
@@ -230,17 +232,29 @@ typedef struct {
     const onng_launch_config *launch;  /* NULL = tuned or default shape */
     uint32_t probe_hops;           /* two_phase: expansions run with the unlimited range
                                       and e_p = ep_first before the switch (0 means 1) */
+    /* Scheduling of a learned search in two passes:
+     * predict_only != 0 (needs two_phase and a predictor): each query stops
+     *   at the switch and only reports its eps, e_p and cost estimate in stats;
+     * range_from: per-query eps and e_p taken from the stats of such a pass
+     *   (overrides epsilon/e_p; two_phase must be 0);
+     * order: [nq] permutation, the order in which the persistent waves take
+     *   the queries (e.g. from onng_order_by_cost), or NULL for 0..nq-1. */
+    int32_t predict_only;
+    const struct onng_query_stats_s *range_from;
+    const int32_t *order;
 } onng_search_params;
 
 /* Per-query statistics written by onng_search. */
-typedef struct {
+typedef struct onng_query_stats_s {
     int32_t dc;        /* distance computations (seeds included) */
     int32_t hops;      /* expansions (pops that passed the range test) */
     int32_t flags;     /* ONNG_QF_* bits */
-    uint32_t e_p;      /* explored-edge limit used after the first expansion */
-    float eps;         /* search range used after the first expansion */
+    uint32_t e_p;      /* explored-edge limit used after the probe expansions */
+    float eps;         /* search range used after the probe expansions */
     int32_t scanned;   /* adjacency entries read: sum over expansions of min(deg, e_p) */
-    int32_t reserved[2];
+    float cost;        /* predicted distance computations of the chosen range
+                          (curve predictor), else the range itself */
+    int32_t reserved;
 } onng_query_stats;
 
 #define ONNG_QF_PADDED 1      /* fewer than k results were reachable */
@@ -263,6 +277,14 @@ onng_status onng_search(const onng_vectors *base, const onng_graph *graph,
                         onng_query_stats *stats, void *ws, size_t ws_bytes, void *stream);
 size_t onng_search_workspace_size(const onng_vectors *base, int64_t n_queries,
                                   const onng_search_params *params);
+
+/* order[0..n) = query indices by descending stats[q].cost (ties: ascending
+ * index), so that a persistent search starts the most expensive queries
+ * first and the batch ends when the cheap ones do (longest first).
+ * ws: onng_order_by_cost_workspace_size(n) bytes. */
+onng_status onng_order_by_cost(const onng_query_stats *stats, int64_t n, int32_t *order, void *ws,
+                               size_t ws_bytes, void *stream);
+size_t onng_order_by_cost_workspace_size(int64_t n);
 
 /* ------------------------------------------------------------------------ */
 /* Low-precision storage and exact rerank (not part of the paper)           */
@@ -321,9 +343,11 @@ onng_status onng_autotune_search(const onng_vectors *base, const onng_graph *gra
                                  int32_t *ids, void *dists, onng_query_stats *stats, void *ws,
                                  size_t ws_bytes, void *stream, onng_launch_config *best);
 
-/* Captures the query pipeline (seed selection against `pivots`, search with
- * its predictor and rerank) for a fixed batch into a HIP graph, returned
- * in *handle (host).  All pointers must stay valid while the handle lives. */
+/* Captures the query pipeline for a fixed batch into a HIP graph, returned
+ * in *handle (host): seed selection against `pivots`, then the search and
+ * rerank.  With a predictor the search runs as three steps: a predict-only
+ * pass, onng_order_by_cost, and the search with the predicted ranges in that
+ * order.  All pointers must stay valid while the handle lives. */
 typedef struct onng_pipeline onng_pipeline;
 onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *graph,
                                  const onng_vectors *queries, const int32_t *pivots,

@@ -51,7 +51,8 @@ class SearchParams_t(C.Structure):
                 ("epsilon", C.c_float), ("eps_per_query", P), ("e_p", C.c_uint32),
                 ("ep_per_query", P), ("two_phase", C.c_int32), ("ep_first", C.c_uint32),
                 ("predictor", P), ("features_out", P), ("rerank_base", P),
-                ("pool_factor", C.c_int32), ("launch", P), ("probe_hops", C.c_uint32)]
+                ("pool_factor", C.c_int32), ("launch", P), ("probe_hops", C.c_uint32),
+                ("predict_only", C.c_int32), ("range_from", P), ("order", P)]
 
 
 # exported symbols and their prototypes (must match include/onng.h)
@@ -67,6 +68,8 @@ PROTOS = {
     "onng_adjust_path_workspace_size": (C.c_size_t, [C.c_int64, C.c_int64]),
     "onng_search": (C.c_int, [P, P, P, P, C.c_int32, P, P, P, P, P, C.c_size_t, P]),
     "onng_search_workspace_size": (C.c_size_t, [P, C.c_int64, P]),
+    "onng_order_by_cost": (C.c_int, [P, C.c_int64, P, P, C.c_size_t, P]),
+    "onng_order_by_cost_workspace_size": (C.c_size_t, [C.c_int64]),
     "onng_encode": (C.c_int, [P, C.c_int64, C.c_int32, C.c_int32, P, C.c_int64, P, P]),
     "onng_rerank": (C.c_int, [P, P, P, C.c_int32, C.c_int32, C.c_int32, P, P, P]),
     "onng_mlp_forward": (C.c_int, [P, C.c_int32, C.c_int32, P, P, C.c_int32, P, P, C.c_int32,

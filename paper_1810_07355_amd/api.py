@@ -196,7 +196,9 @@ class SearchRequest:
     def __init__(self, base: Vectors, graph: Graph, queries: Vectors, seeds: torch.Tensor, k=10,
                  k_stride=None, eps=0.0, ep=L.EP_INF, two_phase=False, ep_first=L.EP_INF,
                  predictor: Predictor | None = None, want_features=False,
-                 rerank_base: Vectors | None = None, pool_factor=4, launch=None, probe_hops=1):
+                 rerank_base: Vectors | None = None, pool_factor=4, launch=None, probe_hops=1,
+                 predict_only=False, range_from: torch.Tensor | None = None,
+                 order: torch.Tensor | None = None):
         dev = queries.data.device
         nq = queries.n
         self.base, self.graph, self.queries = base, graph, queries
@@ -230,7 +232,8 @@ class SearchRequest:
             _ptr(self.features),
             C.cast(rerank_base.ref, C.c_void_p) if rerank_base else None,
             int(pool_factor), C.cast(C.byref(launch), C.c_void_p) if launch is not None else None,
-            int(probe_hops))
+            int(probe_hops), int(predict_only), _ptr(range_from), _ptr(order))
+        self._keep += [range_from, order]
         self.gs = graph.struct()
         out_dt = torch.float32 if rerank_base is not None else base.dist_dtype
         self.ids = torch.empty((nq, self.k_stride), dtype=torch.int32, device=dev)
@@ -285,6 +288,51 @@ class SearchRequest:
     @property
     def scanned(self):
         return self.stats[:, 5]
+
+    @property
+    def cost(self):
+        return self.stats[:, 6].view(torch.float32)
+
+
+def order_by_cost(stats: torch.Tensor, order: torch.Tensor | None = None) -> torch.Tensor:
+    """Query indices by descending predicted cost (longest first)."""
+    n = stats.shape[0]
+    order = torch.empty(n, dtype=torch.int32, device=stats.device) if order is None else order
+    ws = _workspace(L.load().onng_order_by_cost_workspace_size(n), stats.device)
+    L.call("onng_order_by_cost", stats.data_ptr(), n, order.data_ptr(), ws.data_ptr(), ws.numel(),
+           _stream())
+    return order
+
+
+class LearnedSearch:
+    """Search with a learned range, scheduled longest first: a predict-only
+    pass chooses each query's range and cost, the queries are ordered by
+    that cost, and the search runs with the chosen ranges in that order."""
+
+    def __init__(self, base, graph, queries, seeds, predictor: Predictor, ep_first=L.EP_INF,
+                 probe_hops=1, **kw):
+        kw.pop("two_phase", None)
+        kw.pop("eps", None)
+        kw.pop("ep", None)
+        self.pre = SearchRequest(base, graph, queries, seeds, two_phase=True, ep_first=ep_first,
+                                 probe_hops=probe_hops, predictor=predictor, predict_only=True,
+                                 **{k: v for k, v in kw.items() if k != "want_features"})
+        self.order = torch.empty(queries.n, dtype=torch.int32, device=queries.data.device)
+        self.ows = _workspace(L.load().onng_order_by_cost_workspace_size(queries.n),
+                              queries.data.device)
+        self.req = SearchRequest(base, graph, queries, seeds, range_from=self.pre.stats,
+                                 order=self.order, **kw)
+
+    def run(self):
+        self.pre.run()
+        L.call("onng_order_by_cost", self.pre.stats.data_ptr(), self.order.numel(),
+               self.order.data_ptr(), self.ows.data_ptr(), self.ows.numel(), _stream())
+        self.req.run()
+        return self.req
+
+    # result accessors of the final pass
+    def __getattr__(self, name):
+        return getattr(self.__dict__["req"], name)
 
 
 def search(base, graph, queries, seeds, **kw) -> SearchRequest:

@@ -12,6 +12,8 @@
 #include <tuple>
 #include <vector>
 
+#include <hipcub/hipcub.hpp>
+
 #include "onng_internal.h"
 #include "search_args.h"
 
@@ -251,6 +253,10 @@ static onng_status validate_search(const onng_vectors *base, const onng_graph *g
         ONNG_CHECK_ARG(pr->eps_min >= 0.0f && pr->eps_max >= pr->eps_min, "bad eps clamp");
     }
     if (p->two_phase) ONNG_CHECK_ARG(p->ep_first >= 1, "ep_first must be >= 1");
+    if (p->predict_only)
+        ONNG_CHECK_ARG(p->two_phase && p->predictor, "predict_only needs two_phase and a predictor");
+    if (p->range_from)
+        ONNG_CHECK_ARG(!p->two_phase, "range_from replaces the two-phase range; set two_phase = 0");
     return ONNG_OK;
 }
 
@@ -298,6 +304,9 @@ static onng_status run_search(const onng_vectors *base, const onng_graph *g,
     a.two_phase = p->two_phase;
     a.ep_first = p->ep_first;
     a.probe_hops = p->probe_hops ? p->probe_hops : 1;
+    a.predict_only = p->predict_only;
+    a.range_from = p->range_from;
+    a.order = p->order;
     a.has_pred = p->predictor != nullptr;
     if (p->predictor) {
         const onng_predictor *pr = p->predictor;
@@ -372,6 +381,53 @@ static bool lookup_tuned(const onng_vectors *base, const onng_search_params *p,
     if (it == g_tune.end()) return false;
     *out = it->second;
     return true;
+}
+
+// ----------------------------------------------------- order by cost -----
+
+__global__ void cost_keys_kernel(const onng_query_stats *st, int64_t n, float *cost, int32_t *idx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cost[i] = st[i].cost;
+    idx[i] = (int32_t)i;
+}
+
+static size_t sort_temp_bytes(int64_t n) {
+    size_t bytes = 0;
+    (void)hipcub::DeviceRadixSort::SortPairsDescending(nullptr, bytes, (const float *)nullptr,
+                                                       (float *)nullptr, (const int32_t *)nullptr,
+                                                       (int32_t *)nullptr, (int)n);
+    return bytes;
+}
+
+static size_t order_ws(int64_t n) {
+    Carver c(nullptr);
+    c.take<float>(n);
+    c.take<float>(n);
+    c.take<int32_t>(n);
+    c.take<char>(sort_temp_bytes(n));
+    return c.size() + 256;
+}
+
+static onng_status order_launch(const onng_query_stats *st, int64_t n, int32_t *order, void *ws,
+                                size_t ws_bytes, hipStream_t s) {
+    if (n == 0) return ONNG_OK;
+    if (!ws || ws_bytes < order_ws(n)) {
+        set_error("onng_order_by_cost: workspace too small");
+        return ONNG_ERR_WORKSPACE;
+    }
+    Carver c(ws);
+    float *cost = c.take<float>(n);
+    float *cost_sorted = c.take<float>(n);
+    int32_t *idx = c.take<int32_t>(n);
+    size_t tb = sort_temp_bytes(n);
+    void *tmp = c.take<char>(tb);
+    hipLaunchKernelGGL(cost_keys_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, st, n,
+                       cost, idx);
+    ONNG_HIP(hipcub::DeviceRadixSort::SortPairsDescending(tmp, tb, cost, cost_sorted, idx, order,
+                                                          (int)n, 0, 32, s));
+    ONNG_HIP(hipGetLastError());
+    return ONNG_OK;
 }
 
 }  // namespace onng
@@ -500,6 +556,16 @@ onng_status onng_search(const onng_vectors *base, const onng_graph *graph,
     if (params && !cfg && base && lookup_tuned(base, params, &tuned)) cfg = &tuned;
     return run_search(base, graph, queries, seeds, n_seeds, params, ids, dists, stats, ws,
                       ws_bytes, as_stream(stream), cfg);
+}
+
+size_t onng_order_by_cost_workspace_size(int64_t n) { return n < 0 ? 0 : order_ws(n); }
+
+onng_status onng_order_by_cost(const onng_query_stats *stats, int64_t n, int32_t *order, void *ws,
+                               size_t ws_bytes, void *stream) {
+    set_error("");
+    ONNG_CHECK_ARG(n >= 0 && n <= 0x7fffffffLL, "bad n");
+    ONNG_CHECK_ARG(n == 0 || (stats && order), "null pointer");
+    return order_launch(stats, n, order, ws, ws_bytes, as_stream(stream));
 }
 
 onng_status onng_autotune_search(const onng_vectors *base, const onng_graph *graph,
@@ -661,7 +727,16 @@ size_t onng_pipeline_workspace_size(const onng_vectors *base, const onng_vectors
     size_t a = onng_topk_workspace_size(queries, seed_base, n_pivots, n_seeds);
     size_t b = onng_search_workspace_size(base, queries->n, params);
     if (!a || !b) return 0;
-    return (a + 255) / 256 * 256 + b;
+    size_t extra = 0;
+    if (params->predictor) {
+        // predict-only stats, the order and its sort scratch
+        Carver c(nullptr);
+        c.take<onng_query_stats>(queries->n);
+        c.take<int32_t>(queries->n);
+        c.take<char>(order_ws(queries->n));
+        extra = c.size() + 256;
+    }
+    return (a + 255) / 256 * 256 + extra + b;
 }
 
 onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *graph,
@@ -709,9 +784,35 @@ onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *gra
     if (rc == ONNG_OK)
         rc = launch_topk(queries, seed_base, pivots, n_pivots, n_seeds, 0, seeds, seed_d, wsa, a,
                          st);
-    if (rc == ONNG_OK)
+    if (rc == ONNG_OK && !params->predictor) {
         rc = run_search(base, graph, queries, seeds, n_seeds, params, ids, dists, stats, wsa + a,
                         ws_bytes - a, st, params->launch);
+    } else if (rc == ONNG_OK) {
+        // predict the range of every query, order the queries by predicted
+        // cost (longest first), then search with the predicted ranges
+        Carver c(wsa + a);
+        onng_query_stats *pst = c.take<onng_query_stats>(queries->n);
+        int32_t *order = c.take<int32_t>(queries->n);
+        size_t ob = order_ws(queries->n);
+        void *ows = c.take<char>(ob);
+        size_t used = (c.size() + 255) / 256 * 256;
+        onng_search_params p1 = *params;
+        p1.predict_only = 1;
+        p1.features_out = nullptr;
+        onng_search_params p2 = *params;
+        p2.two_phase = 0;
+        p2.predictor = nullptr;
+        p2.predict_only = 0;
+        p2.features_out = nullptr;
+        p2.range_from = pst;
+        p2.order = order;
+        rc = run_search(base, graph, queries, seeds, n_seeds, &p1, ids, dists, pst,
+                        wsa + a + used, ws_bytes - a - used, st, params->launch);
+        if (rc == ONNG_OK) rc = order_launch(pst, queries->n, order, ows, ob, st);
+        if (rc == ONNG_OK)
+            rc = run_search(base, graph, queries, seeds, n_seeds, &p2, ids, dists, stats,
+                            wsa + a + used, ws_bytes - a - used, st, params->launch);
+    }
     hipGraph_t g = nullptr;
     hipError_t ce = hipStreamEndCapture(st, &g);
     if (rc == ONNG_OK && ce != hipSuccess) {

@@ -205,15 +205,21 @@ search_kernel(SearchKArgs a) {
     const int vis_max = a.vis_log2 > 0 ? (1 << (a.vis_log2 - 1)) : 0;   // load 1/2
 
     for (;;) {
-        int qi = 0;
-        if (lane == 0) qi = atomicAdd(a.counter, 1);
-        qi = uni(__shfl(qi, 0));
-        if (qi >= a.nq) break;
+        int ticket = 0;
+        if (lane == 0) ticket = atomicAdd(a.counter, 1);
+        ticket = uni(__shfl(ticket, 0));
+        if (ticket >= a.nq) break;
+        const int qi = a.order ? uni(a.order[ticket]) : ticket;
 
         // ---------------------------------------------- per-query setup --
         const int k = a.k_pq ? min(max(uni(a.k_pq[qi]), 1), a.k_stride) : a.k;
         float eps = a.eps_pq ? unif(a.eps_pq[qi]) : a.eps;
         uint32_t ep = a.ep_pq ? uniu(a.ep_pq[qi]) : a.ep;
+        if (a.range_from) {
+            eps = unif(a.range_from[qi].eps);
+            ep = uniu(a.range_from[qi].e_p);
+        }
+        float cost = eps;
         float f = range_factor(eps, MT);
         if (a.two_phase) {
             f = F_INF;
@@ -529,8 +535,9 @@ search_kernel(SearchKArgs a) {
                 else if (lane == 13) fv = (float)dc;
                 if (a.feat_out && lane < ONNG_NFEAT) a.feat_out[(size_t)qi * ONNG_NFEAT + lane] = fv;
                 if (a.has_pred) {
-                    eps = predict_eps(a.pred, fv, MT, qi, lane, lds.misc + 72);
+                    eps = predict_eps(a.pred, fv, MT, qi, lane, lds.misc + 72, &cost);
                     eps = unif(eps);
+                    cost = unif(cost);
                     ep = a.pred.we >= 0.0f ? dynamic_ep(eps, a.pred.e0, a.pred.we)
                                            : (a.ep_pq ? uniu(a.ep_pq[qi]) : a.ep);
                 } else {
@@ -539,12 +546,15 @@ search_kernel(SearchKArgs a) {
                 }
                 f = range_factor(eps, MT);
                 s_prune(threshold(rfull, r, f));
+                if (a.predict_only) break;   // the range is all this pass reports
             }
         }
 
         // ---------------------------------------------- rerank, output ---
         int nout = min(npool, k);
-        if (a.has_rr && npool > 0) {
+        if (a.predict_only) {
+            // no result rows in a predict-only pass
+        } else if (a.has_rr && npool > 0) {
             // exact f32 distances of the pool from the f32 rows
             for (int c0 = 0; c0 < npool; c0 += WAVE) {
                 if (c0 + lane < npool) lds.ids[lane] = (uint32_t)lds.pool[c0 + lane];
@@ -610,7 +620,7 @@ search_kernel(SearchKArgs a) {
                 }
             }
         }
-        if (nout < k) flags |= ONNG_QF_PADDED;
+        if (nout < k && !a.predict_only) flags |= ONNG_QF_PADDED;
         if (lane == 0) {
             onng_query_stats st;
             st.dc = dc;
@@ -618,8 +628,9 @@ search_kernel(SearchKArgs a) {
             st.flags = flags;
             st.e_p = ep;
             st.eps = eps;
-            st.reserved[0] = scanned;
-            st.reserved[1] = st.reserved[2] = 0;
+            st.scanned = scanned;
+            st.cost = cost;
+            st.reserved = 0;
             a.stats[qi] = st;
         }
 

@@ -57,6 +57,9 @@ struct SearchKArgs {
     int32_t two_phase;
     uint32_t ep_first;
     uint32_t probe_hops;
+    int32_t predict_only;
+    const onng_query_stats *range_from;
+    const int32_t *order;
     int32_t has_pred;
     PredArgs pred;
     float *feat_out;
@@ -95,7 +98,7 @@ struct SearchKArgs {
 // nearest seed) and log(1 + count), z-scored; the hidden layer runs one unit
 // per lane, the heads one per lane.  All lanes return the same value.
 __device__ inline float predict_eps(const PredArgs &P, float fv, int metric, int qi, int lane,
-                                    float *scratch) {
+                                    float *scratch, float *cost) {
     const float c = metric == ONNG_COSINE ? 1e-3f : 1.0f;
     float lg = logf(fmaxf(fv, 0.0f) + c);
     float lg0 = __shfl(lg, 0);
@@ -146,11 +149,14 @@ __device__ inline float predict_eps(const PredArgs &P, float fv, int metric, int
             }
         }
         best = __shfl(best, 0);
-        eps = P.eps_cand[best < G ? best : 0];
+        if (best >= G) best = 0;
+        eps = P.eps_cand[best];
+        *cost = expf(yv[G + best]) - 1.0f;
     } else {
         const int head = P.head_pq ? P.head_pq[qi] : P.head;
         float yh = yv[head] + (P.shift ? P.shift[head] : 0.0f);
         eps = exp10f(yh) - 0.01f;
+        *cost = eps;
     }
     return fminf(fmaxf(eps, P.eps_min), P.eps_max);
 }

@@ -530,3 +530,54 @@ def test_pipeline_low_precision_rows_with_rerank():
         req = pl.launch()
         torch.cuda.synchronize()
     pl.close()
+
+
+def test_scheduled_learned_search():
+    """Longest-first scheduling changes no result: the order only decides
+    which wave takes which query."""
+    P = c1_problem()
+    po, pn, _ = P["pa"]
+    A, Lb = api(), L()
+    g = np.random.default_rng(9)
+    feat = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, 0.0, orc.INF_EP, eps1=np.inf,
+                      ep1=64, probe_hops=1, want_features=True)["feat"]
+    cand = to_dev(np.array([0.0, 0.02, 0.05, 0.1], np.float32))
+    pred = _random_predictor(A, 8, Lb.PRED_CURVE, g, feat, [0.5, 0.6, 0.8, 0.9, 5.0, 5.2, 5.5, 6.0],
+                             eps_min=0.0, eps_max=0.3, e0=30.0, we=20.0, eps_cand=cand, lam=3e-3)
+    B, Q, G = gpu_vectors(P["x"], orc.L2SQ), gpu_vectors(P["q"], orc.L2SQ), gpu_graph(po, pn)
+    S = to_dev(P["seeds"])
+    say("one-pass predictor search")
+    one = A.search(B, G, Q, S, k=10, two_phase=True, ep_first=64, predictor=pred)
+    say("scheduled predictor search")
+    ls = A.LearnedSearch(B, G, Q, S, pred, ep_first=64, k=10)
+    req = ls.run()
+    torch.cuda.synchronize()
+    # the predict-only pass chose the same ranges as the one-pass search
+    assert np.array_equal(host(ls.pre.eps_used), host(one.eps_used))
+    assert np.array_equal(host(ls.pre.ep_used), host(one.ep_used))
+    # the order sorts the predicted costs, longest first
+    order = host(ls.order)
+    cost = host(ls.pre.cost)
+    assert sorted(order.tolist()) == list(range(len(order)))
+    assert np.all(np.diff(cost[order]) <= 0)
+    # the scheduled search is a plain search with those ranges
+    eps_used = host(req.eps_used)
+    ep_used = host(req.ep_used).astype(np.uint32)
+    ref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, eps_used, ep_used)
+    assert np.array_equal(host(req.ids), ref["ids"])
+    assert np.array_equal(host(req.dc), ref["dc"])
+    # unordered run of the same ranges gives the same result
+    plain = A.search(B, G, Q, S, k=10, range_from=ls.pre.stats)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(plain.ids), host(req.ids))
+    # graph pipeline of the three steps equals the eager run
+    say("learned pipeline")
+    pl = A.Pipeline(B, G, Q, to_dev(P["piv"]), 8, k=10, two_phase=True, ep_first=64,
+                    predictor=pred)
+    for rep in range(2):
+        out = pl.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out.ids), host(req.ids))
+        assert np.array_equal(host(out.dc), host(req.dc))
+        out.ids.fill_(-5)
+    pl.close()
