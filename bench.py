@@ -138,6 +138,8 @@ def main():
             ts.append(e0.elapsed_time(e1))
         return float(np.median(ts))
 
+    pq_stats = {}
+
     def measure(make, knob, name, timing=True):
         req = make(knob)
         if timing:
@@ -151,6 +153,12 @@ def main():
                   dc=float(req.dc.float().mean()), eps_mean=float(req.eps_used.mean()))
         log(f"{name:>14} knob={knob:+.4f} recall={rec:.4f} dc={pt['dc']:8.1f} {ms:8.2f} ms "
             f"{pt['qps']:12.0f} q/s")
+        if timing and args.dump:
+            st = req.stats.cpu().numpy()
+            pq_stats[f"{name.strip()}@{knob:.4f}"] = st
+            us = st[:, 7].view(np.float32)
+            log(f"{'':>14} per-query us: p50 {np.percentile(us, 50):.0f} p99 "
+                f"{np.percentile(us, 99):.0f} max {us.max():.0f}; hops max {st[:, 1].max()}")
         return pt
 
     def bisect(make, target, lo, hi, name, iters=9):
@@ -258,6 +266,11 @@ def main():
     result["learned"] = learned_pts
     knobs = {t: (learned_pts[str(t)]["knob"] if learned_pts[str(t)] else 9.0)
              for t in (0.95, 0.99)}
+
+    if args.dump:
+        np.savez_compressed(args.dump.replace(".npz", "_stats.npz"),
+                            **{k.replace("@", "_at_").replace("+", "_"): v
+                               for k, v in pq_stats.items()})
 
     # ----------------------------------------------- timed region (graph) --
     pred95 = learned_pred(0.95, knobs[0.95])

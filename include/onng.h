@@ -254,7 +254,8 @@ typedef struct onng_query_stats_s {
     int32_t scanned;   /* adjacency entries read: sum over expansions of min(deg, e_p) */
     float cost;        /* predicted distance computations of the chosen range
                           (curve predictor), else the range itself */
-    int32_t reserved;
+    float us;          /* wall time on the device from taking the query to its
+                          last write, microseconds (for tail-latency analysis) */
 } onng_query_stats;
 
 #define ONNG_QF_PADDED 1      /* fewer than k results were reachable */

@@ -24,7 +24,7 @@ P = C.c_void_p
 class Vectors_t(C.Structure):
     _fields_ = [("data", P), ("scale", P), ("n", C.c_int64), ("dim", C.c_int32),
                 ("dtype", C.c_int32), ("pitch_bytes", C.c_int64), ("metric", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("us", C.c_float)]
 
 
 class Graph_t(C.Structure):

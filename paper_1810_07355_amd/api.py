@@ -293,6 +293,11 @@ class SearchRequest:
     def cost(self):
         return self.stats[:, 6].view(torch.float32)
 
+    @property
+    def us(self):
+        """Per-query device wall time in microseconds."""
+        return self.stats[:, 7].view(torch.float32)
+
 
 def order_by_cost(stats: torch.Tensor, order: torch.Tensor | None = None) -> torch.Tensor:
     """Query indices by descending predicted cost (longest first)."""

@@ -60,6 +60,15 @@ int device_cu_count() {
     return cus > 0 ? cus : 256;
 }
 
+// period of the device's constant-rate wall clock (wall_clock64) in microseconds
+float device_us_per_tick() {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0.0f;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+        return 0.0f;
+    return 1000.0f / (float)khz;
+}
+
 onng_status check_vectors(const onng_vectors *v, const char *what) {
     std::string w(what);
     if (!v) { set_error(w + " is null"); return ONNG_ERR_INVALID_ARG; }
@@ -305,6 +314,7 @@ static onng_status run_search(const onng_vectors *base, const onng_graph *g,
     a.ep_first = p->ep_first;
     a.probe_hops = p->probe_hops ? p->probe_hops : 1;
     a.predict_only = p->predict_only;
+    a.us_per_tick = device_us_per_tick();
     a.range_from = p->range_from;
     a.order = p->order;
     a.has_pred = p->predictor != nullptr;

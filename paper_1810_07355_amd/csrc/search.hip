@@ -210,6 +210,7 @@ search_kernel(SearchKArgs a) {
         ticket = uni(__shfl(ticket, 0));
         if (ticket >= a.nq) break;
         const int qi = a.order ? uni(a.order[ticket]) : ticket;
+        const uint64_t t_start = wall_clock64();
 
         // ---------------------------------------------- per-query setup --
         const int k = a.k_pq ? min(max(uni(a.k_pq[qi]), 1), a.k_stride) : a.k;
@@ -630,7 +631,7 @@ search_kernel(SearchKArgs a) {
             st.eps = eps;
             st.scanned = scanned;
             st.cost = cost;
-            st.reserved = 0;
+            st.us = (float)(wall_clock64() - t_start) * a.us_per_tick;
             a.stats[qi] = st;
         }
 

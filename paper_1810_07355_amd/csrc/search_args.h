@@ -58,6 +58,7 @@ struct SearchKArgs {
     uint32_t ep_first;
     uint32_t probe_hops;
     int32_t predict_only;
+    float us_per_tick;          // wall-clock counter period in microseconds
     const onng_query_stats *range_from;
     const int32_t *order;
     int32_t has_pred;

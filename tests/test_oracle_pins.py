@@ -264,7 +264,7 @@ def test_path_adjust_random_vs_literal_and_witness(seed):
 
 
 def test_path_adjust_roughly_halves_outdegree_c1():
-    # Section 3.3: path adjustment almost halved the outdegrees.
+    # Section 3.2 (Effectiveness of Each Method): path adjustment roughly halves outdegrees.
     cfg = dg.PRESETS["c1"]
     x = dg.base(cfg)
     v = orc.Vectors.from_array(x, orc.L2SQ)
