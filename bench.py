@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--dump", default=None, help="save per-query sweep data (.npz)")
     ap.add_argument("--probe-hops", type=int, default=1,
                     help="expansions before the learned range is chosen")
+    ap.add_argument("--inflight", type=int, default=2,
+                    help="query batches in flight in the timed region (one stream each)")
     ap.add_argument("--search-only", action="store_true",
                     help="after the index and operating points, only loop the search kernel "
                          "(used under rocprofv3)")
@@ -252,20 +254,51 @@ def main():
         return models[tgt].predictor(mode=L.PRED_CURVE, eps_cand=cand[tgt], lam=10.0 ** (-knob),
                                      eps_min=0.0, eps_max=max(grid), e0=30.0, we=20.0)
 
-    def make_learned(tgt):
-        def make(knob):   # knob = -log10(lambda): larger spends more
+    # Distance-computation budgets bound the rare very long queries, which
+    # otherwise set the batch time.  Each variant gets the budget (a multiple
+    # of the plain operating point's mean count, or none) that serves it best.
+    def best_over_budgets(make_b, tgt, lo, hi, name):
+        base_pt = result["plain"][str(tgt)]
+        mults = [0, 1.5, 2.0, 3.0, 4.0]
+        best = None
+        for m in mults:
+            b = int(m * base_pt["dc"]) if (m and base_pt) else 0
+            pt = bisect(lambda kn: make_b(kn, b), tgt, lo, hi, f"{name} b={b}")
+            if pt is not None:
+                pt["max_dc"] = b
+                if best is None or pt["qps"] > best["qps"]:
+                    best = pt
+        return best
+
+    def make_learned_b(tgt):
+        def make(knob, b):
             pred = learned_pred(tgt, knob)
             req = A.LearnedSearch(search_rows, graph, queries, seeds, pred, ep_first=EPF,
-                                  probe_hops=PROBE, k=K, **rr)
+                                  probe_hops=PROBE, k=K, max_dc=b, **rr)
             req._pred = pred
             return req
         return make
 
     for tgt in (0.95, 0.99):
-        learned_pts[str(tgt)] = bisect(make_learned(tgt), tgt, 2.0, 9.0, f"learned@{tgt}")
+        learned_pts[str(tgt)] = best_over_budgets(make_learned_b(tgt), tgt, 2.0, 9.0,
+                                                  f"learned@{tgt}")
     result["learned"] = learned_pts
     knobs = {t: (learned_pts[str(t)]["knob"] if learned_pts[str(t)] else 9.0)
              for t in (0.95, 0.99)}
+    budgets = {t: (learned_pts[str(t)]["max_dc"] if learned_pts[str(t)] else 0)
+               for t in (0.95, 0.99)}
+    # the same budgets without the learned range, for comparison
+    if lp_rows is not None:
+        make_lp_b = lambda e, b: A.SearchRequest(lp_rows, graph, queries, seeds, k=K, eps=e,
+                                                 ep=LR.dynamic_ep(e), rerank_base=base,
+                                                 pool_factor=4, max_dc=b)
+        result["lp_budget"] = {str(t): best_over_budgets(make_lp_b, t, 0.0, 1.0,
+                                                         args.lp + "+rerank")
+                               for t in (0.95, 0.99)}
+    make_plain_b = lambda e, b: A.SearchRequest(base, graph, queries, seeds, k=K, eps=e,
+                                                ep=LR.dynamic_ep(e), max_dc=b)
+    result["plain_budget"] = {str(t): best_over_budgets(make_plain_b, t, 0.0, 1.0, "plain")
+                              for t in (0.95, 0.99)}
 
     if args.dump:
         np.savez_compressed(args.dump.replace(".npz", "_stats.npz"),
@@ -274,49 +307,66 @@ def main():
 
     # ----------------------------------------------- timed region (graph) --
     pred95 = learned_pred(0.95, knobs[0.95])
-    pipe = A.Pipeline(search_rows, graph, queries, piv, NS, k=K, eps=0.0, ep=L.EP_INF,
-                      two_phase=True, ep_first=EPF, probe_hops=PROBE, predictor=pred95, **rr)
+    NF = max(1, args.inflight)
+    # one pipeline (own outputs and workspace) and one stream per batch in flight
+    pipes = [A.Pipeline(search_rows, graph, queries, piv, NS, k=K, eps=0.0, ep=L.EP_INF,
+                        two_phase=True, ep_first=EPF, probe_hops=PROBE, predictor=pred95,
+                        max_dc=budgets[0.95], **rr) for _ in range(NF)]
+    pipe = pipes[0]
     plain95 = result["plain"]["0.95"]
-    pipe_plain = None
+    pipes_plain = []
     if plain95 is not None:
-        pipe_plain = A.Pipeline(base, graph, queries, piv, NS, k=K, eps=plain95["knob"],
-                                ep=LR.dynamic_ep(plain95["knob"]))
+        pipes_plain = [A.Pipeline(base, graph, queries, piv, NS, k=K, eps=plain95["knob"],
+                                  ep=LR.dynamic_ep(plain95["knob"])) for _ in range(NF)]
+    streams = [torch.cuda.Stream(device=dev) for _ in range(NF)]
+
+    def run_steps(pl, n):
+        """n batches, batch i on stream i mod NF; returns the last request."""
+        cur = torch.cuda.current_stream()
+        for s_ in streams:
+            s_.wait_stream(cur)
+        last = None
+        for i in range(n):
+            with torch.cuda.stream(streams[i % NF]):
+                last = pl[i % NF].launch()
+        for s_ in streams:
+            cur.wait_stream(s_)
+        return last
 
     if args.search_only:
-        req = make_learned(0.95)(knobs[0.95])
+        req = make_learned_b(0.95)(knobs[0.95], budgets[0.95])
         for _ in range(args.warmup + args.steps):
             req.run()
         torch.cuda.synchronize()
         log("search-only loop done")
         return
 
-    for _ in range(args.warmup):
-        pipe.launch()
+    run_steps(pipes, args.warmup)
     torch.cuda.synchronize()
     t = time.time()
-    for _ in range(args.steps):
-        req = pipe.launch()
+    req = run_steps(pipes, args.steps)
     torch.cuda.synchronize()
     wall = time.time() - t
     ms_step = wall * 1e3 / args.steps
     value = queries.n / (ms_step / 1e3)
-    rec95 = float(LR.recall_by_ids(req.ids.cpu().numpy(), gt, K).mean())
-    log(f"timed: {args.steps} steps, {ms_step:.2f} ms/step, {value:.0f} q/s, recall {rec95:.4f}")
+    rec95 = float(np.mean([LR.recall_by_ids(p_.req.ids.cpu().numpy(), gt, K).mean()
+                           for p_ in pipes[:min(NF, args.steps)]]))
+    log(f"timed: {args.steps} steps, {NF} in flight, {ms_step:.2f} ms/step, {value:.0f} q/s, "
+        f"recall {rec95:.4f}")
 
     plain_pipe_qps = None
-    if pipe_plain is not None:
-        for _ in range(args.warmup):
-            pipe_plain.launch()
+    if pipes_plain:
+        run_steps(pipes_plain, args.warmup)
         torch.cuda.synchronize()
         t = time.time()
-        for _ in range(args.steps):
-            rp = pipe_plain.launch()
+        run_steps(pipes_plain, args.steps)
         torch.cuda.synchronize()
         plain_pipe_qps = queries.n / ((time.time() - t) / args.steps)
-        log(f"plain f32 pipeline at eps={plain95['knob']}: {plain_pipe_qps:.0f} q/s")
+        log(f"plain f32 pipeline at eps={plain95['knob']}, {NF} in flight: "
+            f"{plain_pipe_qps:.0f} q/s")
 
     # ---------------------------------------- roofline of the search kernel --
-    lreq = make_learned(0.95)(knobs[0.95])
+    lreq = make_learned_b(0.95)(knobs[0.95], budgets[0.95])
     lreq.run()
     req = lreq.req                 # the search pass (predict pass and order excluded)
     ms_search = time_req(req, reps=5)
@@ -394,6 +444,8 @@ def main():
                          f"from {piv.numel()} pivots; learned eps for recall 0.95, "
                          f"{args.lp if not is_u8 else 'u8'} rows + f32 rerank of 4k"),
             "global_batch": cfg.n_query,
+            "batches_in_flight": NF,
+            "max_dc": {str(t): budgets[t] for t in (0.95, 0.99)},
         },
         "recall_at_timed_point": round(rec95, 4),
         "qps": {
@@ -404,6 +456,10 @@ def main():
             "plain_f32_pipeline@0.95": round(plain_pipe_qps, 1) if plain_pipe_qps else None,
             "lp_fixed_eps@0.95": qps_of(result.get("lp", {}).get("0.95")),
             "lp_fixed_eps@0.99": qps_of(result.get("lp", {}).get("0.99")),
+            "lp_fixed_eps_budget@0.95": qps_of(result.get("lp_budget", {}).get("0.95")),
+            "lp_fixed_eps_budget@0.99": qps_of(result.get("lp_budget", {}).get("0.99")),
+            "plain_f32_budget@0.95": qps_of(result["plain_budget"]["0.95"]),
+            "plain_f32_budget@0.99": qps_of(result["plain_budget"]["0.99"]),
             "learned_lp_search@0.95": qps_of(learned_pts.get("0.95")),
         },
         "speedup_vs_plain_f32@0.95": (round(value / plain_pipe_qps, 3) if plain_pipe_qps else None),
@@ -417,9 +473,8 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    pipe.close()
-    if pipe_plain is not None:
-        pipe_plain.close()
+    for p_ in pipes + pipes_plain:
+        p_.close()
 
 
 if __name__ == "__main__":

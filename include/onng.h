@@ -242,6 +242,14 @@ typedef struct {
     int32_t predict_only;
     const struct onng_query_stats_s *range_from;
     const int32_t *order;
+    /* Distance-computation budget (not in the paper): no expansion starts
+     * once a query has made max_dc distance computations (seeds included);
+     * the query then returns its current R and sets ONNG_QF_BUDGET.  0 = no
+     * budget.  max_dc_per_query [nq] (or NULL) overrides it per query, values
+     * <= 0 meaning none.  Bounds the latency of the rare queries whose range
+     * holds very many objects. */
+    int32_t max_dc;
+    const int32_t *max_dc_per_query;
 } onng_search_params;
 
 /* Per-query statistics written by onng_search. */
@@ -261,6 +269,7 @@ typedef struct onng_query_stats_s {
 #define ONNG_QF_PADDED 1      /* fewer than k results were reachable */
 #define ONNG_QF_SPILLED 2     /* exceeded on-chip capacity, finished by the exact off-chip pass */
 #define ONNG_QF_CAPACITY 4    /* exceeded even the off-chip capacity: result not exact */
+#define ONNG_QF_BUDGET 8      /* stopped by the distance-computation budget */
 
 /* Batched KnnSearch (Algorithm 1) for every query row: best-first expansion
  * from the seeds with search range r(1 + eps), at most e_p edges per node,

@@ -21,10 +21,13 @@ def _key(d, i):
     return (d, i)
 
 
-def knn_search(neigh, dist_to_q, seeds, k, thr_fn, ep=math.inf):
+def knn_search(neigh, dist_to_q, seeds, k, thr_fn, ep=math.inf, max_dc=0, trace=None):
     """Algorithm 1.  neigh[s] is the edge list of s sorted by length;
     dist_to_q(n) is d(n, q); thr_fn(r) returns r(1+eps) in the reading's
-    arithmetic.  Returns (R sorted by (d, id), distance computations, hops)."""
+    arithmetic.  max_dc > 0 adds a distance-computation budget checked before
+    each pop (not in the paper).  Returns (R sorted by (d, id), distance
+    computations, hops).  trace, if a list, receives the distance count after
+    the seeds and after every expansion."""
     C = set()
     S = []                               # list of (d, id)
     R = []                               # list of (d, id)
@@ -44,7 +47,11 @@ def knn_search(neigh, dist_to_q, seeds, k, thr_fn, ep=math.inf):
             if len(R) == k:
                 r = max(R)[0]
     hops = 0
+    if trace is not None:
+        trace.append(dc)
     while S:
+        if max_dc > 0 and dc >= max_dc:
+            break
         s = min(S)                       # argmin over S by (d, id)
         S.remove(s)
         if s[0] > thr_fn(r):
@@ -67,6 +74,8 @@ def knn_search(neigh, dist_to_q, seeds, k, thr_fn, ep=math.inf):
                     if len(R) == k:
                         r = max(R)[0]
             p += 1
+        if trace is not None:
+            trace.append(dc)
     return sorted(R), dc, hops
 
 

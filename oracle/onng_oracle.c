@@ -680,6 +680,7 @@ typedef struct {
     const float *eps, *eps1;
     const uint32_t *ep, *ep1;
     int32_t probe_hops;
+    const int32_t *max_dc;
     int32_t k_stride;
     int32_t *out_ids;
     double *out_d;
@@ -757,7 +758,9 @@ static void search_one(search_job *J, visited_t *C, heap_t *S, rset_t *R, int64_
         rset_offer(R, &r, d, s);
         heap_push(S, d, s);
     }
+    const int64_t budget = J->max_dc && J->max_dc[q] > 0 ? J->max_dc[q] : INT64_MAX;
     while (S->n > 0) {
+        if (dc >= budget) break;                            /* budget spent */
         item_t s = heap_pop(S);
         double thr = threshold(r, f, u8);
         if (S->n > 0) margin = fmin(margin, rel_gap(s.d, S->a[0].d, mfloor));
@@ -846,7 +849,7 @@ int or_search(const or_vecs *base, const int64_t *offsets, const int32_t *nbrs,
               const int32_t *seeds, int32_t n_seeds,
               const int32_t *k, const float *eps, const uint32_t *ep,
               const float *eps1, const uint32_t *ep1, int32_t probe_hops,
-              int32_t k_stride, int32_t *out_ids, double *out_d,
+              const int32_t *max_dc, int32_t k_stride, int32_t *out_ids, double *out_d,
               int64_t *out_dc, int64_t *out_hops, double *out_margin,
               double *feat, int32_t nthreads)
 {
@@ -859,7 +862,7 @@ int or_search(const or_vecs *base, const int64_t *offsets, const int32_t *nbrs,
     for (int64_t q = 0; q < nq; q++)
         if (k[q] <= 0 || k[q] > k_stride) return -1;
     search_job J = {base, queries, offsets, nbrs, n_nodes, nq, seeds, n_seeds, k, eps, eps1,
-                    ep, ep1, probe_hops < 1 ? 1 : probe_hops, k_stride, out_ids, out_d, out_dc,
+                    ep, ep1, probe_hops < 1 ? 1 : probe_hops, max_dc, k_stride, out_ids, out_d, out_dc,
                     out_hops, out_margin, feat, 0, PTHREAD_MUTEX_INITIALIZER};
     run_pool(search_worker, &J, nthreads);
     return 0;

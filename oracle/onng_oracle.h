@@ -82,14 +82,17 @@ int or_adjust_path(const int64_t *in_off, const int32_t *in_nbrs,
  * feat (optional, nq x OR_NFEAT) receives the state at the switch: 8 seed
  * distances ascending, |S|, the smallest / ceil(m/2)-th / m-th distance of the
  * m = min(|S|, 64) smallest in S, the largest distance in R, the distance
- * computations so far. */
+ * computations so far.
+ * max_dc (optional, per query; <= 0 = none): a distance-computation budget,
+ * an addition to the paper: before each pop, a query that has made max_dc[q]
+ * or more distance computations stops and returns its current R. */
 #define OR_NFEAT 14
 int or_search(const or_vecs *base, const int64_t *offsets, const int32_t *nbrs,
               int64_t n_nodes, const or_vecs *queries, int64_t nq,
               const int32_t *seeds, int32_t n_seeds,
               const int32_t *k, const float *eps, const uint32_t *ep,
               const float *eps1, const uint32_t *ep1, int32_t probe_hops,
-              int32_t k_stride, int32_t *out_ids, double *out_d,
+              const int32_t *max_dc, int32_t k_stride, int32_t *out_ids, double *out_d,
               int64_t *out_dc, int64_t *out_hops, double *out_margin,
               double *feat, int32_t nthreads);
 

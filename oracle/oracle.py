@@ -53,7 +53,7 @@ def lib():
                                           P, P, C.c_int64, P]
         _lib.or_adjust_path.argtypes = [P, P, P, C.c_int64, P, P, P, P]
         _lib.or_search.argtypes = [P, P, P, C.c_int64, P, C.c_int64, P, C.c_int32, P, P, P, P,
-                                   P, C.c_int32, C.c_int32, P, P, P, P, P, P, C.c_int32]
+                                   P, C.c_int32, P, C.c_int32, P, P, P, P, P, P, C.c_int32]
         _lib.or_hash_size.restype = C.c_int64
         _lib.or_hash_size.argtypes = [C.c_int64, C.c_int32]
         _lib.or_visited_replay.argtypes = [C.c_int64, P, C.c_int64, P]
@@ -209,7 +209,8 @@ def _per_query(v, nq, dtype):
 
 
 def search(base: Vectors, off, nbrs, queries: Vectors, seeds, k, eps, ep=INF_EP, eps1=None,
-           ep1=None, k_stride=None, want_features=False, threads=None, probe_hops=1):
+           ep1=None, k_stride=None, want_features=False, threads=None, probe_hops=1,
+           max_dc=None):
     """Algorithm 1 for every query.  Returns dict with ids, dists, dc, hops, margin[, feat]."""
     nq = queries.n
     seeds = np.ascontiguousarray(seeds, dtype=np.int32)
@@ -218,6 +219,7 @@ def search(base: Vectors, off, nbrs, queries: Vectors, seeds, k, eps, ep=INF_EP,
     pp = _per_query(ep, nq, np.uint32)
     e1 = None if eps1 is None else _per_query(eps1, nq, np.float32)
     p1 = None if ep1 is None else _per_query(ep1, nq, np.uint32)
+    md = None if max_dc is None else _per_query(max_dc, nq, np.int32)
     ks = int(kk.max()) if k_stride is None else k_stride
     off = np.ascontiguousarray(off, dtype=np.int64)
     nbrs = np.ascontiguousarray(nbrs, dtype=np.int32)
@@ -229,7 +231,8 @@ def search(base: Vectors, off, nbrs, queries: Vectors, seeds, k, eps, ep=INF_EP,
     feat = np.zeros((nq, NFEAT), dtype=np.float64) if want_features else None
     rc = lib().or_search(base.ref, off.ctypes.data, nbrs.ctypes.data, base.n, queries.ref, nq,
                          seeds.ctypes.data, seeds.shape[1], kk.ctypes.data, ee.ctypes.data,
-                         pp.ctypes.data, _ptr(e1), _ptr(p1), probe_hops, ks, ids.ctypes.data,
+                         pp.ctypes.data, _ptr(e1), _ptr(p1), probe_hops, _ptr(md), ks,
+                         ids.ctypes.data,
                          ds.ctypes.data, dc.ctypes.data, hops.ctypes.data, margin.ctypes.data,
                          _ptr(feat), threads or nthreads())
     assert rc == 0, rc

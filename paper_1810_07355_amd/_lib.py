@@ -14,7 +14,7 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_CAPACITY, ERR_WORKSPACE, ERR_DEVICE = 
 U8, F32, F16, BF16, FP8_E4M3 = 0, 1, 2, 3, 4
 L2SQ, COSINE = 0, 1
 NFEAT = 14
-QF_PADDED, QF_SPILLED, QF_CAPACITY = 1, 2, 4
+QF_PADDED, QF_SPILLED, QF_CAPACITY, QF_BUDGET = 1, 2, 4, 8
 PRED_LOG_EPS, PRED_CURVE = 0, 1
 EP_INF = 0xFFFFFFFF
 
@@ -52,7 +52,8 @@ class SearchParams_t(C.Structure):
                 ("ep_per_query", P), ("two_phase", C.c_int32), ("ep_first", C.c_uint32),
                 ("predictor", P), ("features_out", P), ("rerank_base", P),
                 ("pool_factor", C.c_int32), ("launch", P), ("probe_hops", C.c_uint32),
-                ("predict_only", C.c_int32), ("range_from", P), ("order", P)]
+                ("predict_only", C.c_int32), ("range_from", P), ("order", P),
+                ("max_dc", C.c_int32), ("max_dc_per_query", P)]
 
 
 # exported symbols and their prototypes (must match include/onng.h)

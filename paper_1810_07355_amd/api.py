@@ -198,7 +198,7 @@ class SearchRequest:
                  predictor: Predictor | None = None, want_features=False,
                  rerank_base: Vectors | None = None, pool_factor=4, launch=None, probe_hops=1,
                  predict_only=False, range_from: torch.Tensor | None = None,
-                 order: torch.Tensor | None = None):
+                 order: torch.Tensor | None = None, max_dc=0):
         dev = queries.data.device
         nq = queries.n
         self.base, self.graph, self.queries = base, graph, queries
@@ -218,7 +218,11 @@ class SearchRequest:
         if torch.is_tensor(ep):
             epq = ep.to(device=dev, dtype=torch.int64).to(torch.int32).contiguous()
             ep = 1
-        self._keep += [kq, epsq, epq]
+        mdq = None
+        if torch.is_tensor(max_dc):
+            mdq = max_dc.to(device=dev, dtype=torch.int32).contiguous()
+            max_dc = 0
+        self._keep += [kq, epsq, epq, mdq]
         self.predictor = predictor
         self._pred_s = predictor.struct() if predictor else None
         self.features = (torch.zeros((nq, L.NFEAT), dtype=torch.float32, device=dev)
@@ -232,7 +236,8 @@ class SearchRequest:
             _ptr(self.features),
             C.cast(rerank_base.ref, C.c_void_p) if rerank_base else None,
             int(pool_factor), C.cast(C.byref(launch), C.c_void_p) if launch is not None else None,
-            int(probe_hops), int(predict_only), _ptr(range_from), _ptr(order))
+            int(probe_hops), int(predict_only), _ptr(range_from), _ptr(order), int(max_dc),
+            _ptr(mdq))
         self._keep += [range_from, order]
         self.gs = graph.struct()
         out_dt = torch.float32 if rerank_base is not None else base.dist_dtype

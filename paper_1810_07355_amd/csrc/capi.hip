@@ -139,10 +139,10 @@ static onng_status make_plan(const onng_vectors *base, int64_t nq, const onng_se
     int L = cfg && cfg->lanes_per_row ? cfg->lanes_per_row : 0;
     if (!L) {
         L = 4;
-        while (L < 64 && (n16 + L - 1) / L > std::min(ppl, 2)) L <<= 1;
+        while (L < 32 && (n16 + L - 1) / L > std::min(ppl, 2)) L <<= 1;
     }
-    if (L != 2 && L != 4 && L != 8 && L != 16 && L != 32 && L != 64) {
-        set_error("onng_search: lanes_per_row must be a power of two in [2, 64]");
+    if (L != 4 && L != 8 && L != 16 && L != 32) {
+        set_error("onng_search: lanes_per_row must be 4, 8, 16 or 32");
         return ONNG_ERR_INVALID_ARG;
     }
     if ((n16 + L - 1) / L > ppl) {
@@ -317,6 +317,8 @@ static onng_status run_search(const onng_vectors *base, const onng_graph *g,
     a.us_per_tick = device_us_per_tick();
     a.range_from = p->range_from;
     a.order = p->order;
+    a.max_dc = p->max_dc;
+    a.max_dc_pq = p->max_dc_per_query;
     a.has_pred = p->predictor != nullptr;
     if (p->predictor) {
         const onng_predictor *pr = p->predictor;

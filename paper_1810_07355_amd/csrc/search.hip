@@ -127,7 +127,9 @@ struct Q {
     }
     // this lane's part of sum (x - q)^2, or of <x, q> for cosine
     __device__ float fold(const u32x4 *x, float sc) const {
-        float acc = 0.0f;
+        // two accumulation chains (even / odd components) halve the
+        // dependent-FMA latency
+        float acc[2] = {0.0f, 0.0f};
 #pragma unroll
         for (int t = 0; t < PPL; t++) {
             float v[N];
@@ -138,13 +140,13 @@ struct Q {
                 if constexpr (DT == ONNG_FP8_E4M3) xv *= sc;
                 if constexpr (MT == ONNG_L2SQ) {
                     float df = xv - q[t][e];
-                    acc = fmaf(df, df, acc);
+                    acc[e & 1] = fmaf(df, df, acc[e & 1]);
                 } else {
-                    acc = fmaf(xv, q[t][e], acc);
+                    acc[e & 1] = fmaf(xv, q[t][e], acc[e & 1]);
                 }
             }
         }
-        return acc;
+        return acc[0] + acc[1];
     }
 };
 
@@ -227,6 +229,8 @@ search_kernel(SearchKArgs a) {
             ep = a.ep_first;
         }
         const int pool_q = a.has_rr ? min(a.pool_cap, max(k, a.pool_factor * k)) : k;
+        int max_dc = a.max_dc_pq ? uni(a.max_dc_pq[qi]) : a.max_dc;
+        if (max_dc <= 0) max_dc = INT32_MAX;
 
         QT qr;
         const uint8_t *qrow = a.qry + (size_t)qi * a.q_pitch;
@@ -330,10 +334,8 @@ search_kernel(SearchKArgs a) {
                 for (int up = 0; up < UP; up++) {
                     int row = r0 + up * rpp + grp;
                     typename DistTraits<DT>::acc_t acc = qr.fold(x[up], sc[up]);
-                    for (int m = L >> 1; m >= 1; m >>= 1) {
-                        if constexpr (INT) acc += (uint32_t)__shfl_xor((int)acc, m);
-                        else acc += __shfl_xor(acc, m);
-                    }
+                    // sum over the L lanes of the row (DPP, no LDS round trip)
+                    acc = group_sum_rt(acc, L);
                     if (row < u && p == 0) {
                         uint32_t dord;
                         if constexpr (INT) dord = acc;
@@ -486,6 +488,10 @@ search_kernel(SearchKArgs a) {
         // ------------------------------------------------- main loop -----
         for (;;) {
             if (head == size && spill_n == 0) break;                  // S empty
+            if (dc >= max_dc) {                                       // budget spent
+                flags |= ONNG_QF_BUDGET;
+                break;
+            }
             if (spill_n > 0 && (head == size || uni64(lds.S[head]) > spill_min)) {
                 refill();
                 if (head == size) break;

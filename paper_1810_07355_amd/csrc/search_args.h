@@ -61,6 +61,8 @@ struct SearchKArgs {
     float us_per_tick;          // wall-clock counter period in microseconds
     const onng_query_stats *range_from;
     const int32_t *order;
+    int32_t max_dc;
+    const int32_t *max_dc_pq;
     int32_t has_pred;
     PredArgs pred;
     float *feat_out;

@@ -48,21 +48,107 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
     return (uint64_t(hi) << 32) | lo;
 }
 
+// ---- lane exchanges without LDS traffic ---------------------------------
+// DPP controls (GCN/CDNA encoding): quad permutes act within groups of 4
+// lanes, row operations within rows of 16 lanes.
+constexpr int DPP_QP_1032 = 0xB1;       // quad_perm [1,0,3,2]: partner lane ^ 1
+constexpr int DPP_QP_2301 = 0x4E;       // quad_perm [2,3,0,1]: partner lane ^ 2
+constexpr int DPP_ROW_ROR4 = 0x124;     // lane (i + 4) mod 16 of the row
+constexpr int DPP_ROW_ROR8 = 0x128;     // lane (i + 8) mod 16 = lane ^ 8
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane 7 - i within each group of 8
+
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp(T x) {
+    static_assert(sizeof(T) == 4, "32-bit lanes");
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+
+// ds_swizzle in bit mode: partner lane ^ X within each half of the wave
+// (X < 32); goes through the LDS crossbar but needs no address.
+template <int X, typename T>
+__device__ __forceinline__ T swz_xor(T x) {
+    static_assert(sizeof(T) == 4 && X > 0 && X < 32, "32-bit lanes, xor within 32");
+    return __builtin_bit_cast(T, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, x),
+                                                             (X << 10) | 0x1F));
+}
+
+// value of lane ^ J, for a compile-time J
+template <int J, typename T>
+__device__ __forceinline__ T xor_lane(T x) {
+    if constexpr (J == 1) return dpp<DPP_QP_1032>(x);
+    else if constexpr (J == 2) return dpp<DPP_QP_2301>(x);
+    else if constexpr (J == 8) return dpp<DPP_ROW_ROR8>(x);
+    else if constexpr (J < 32) return swz_xor<J>(x);
+    else return __builtin_bit_cast(T, __shfl_xor(__builtin_bit_cast(int, x), J));
+}
+
+template <int J>
+__device__ __forceinline__ uint64_t xor_lane64(uint64_t v) {
+    uint32_t lo = xor_lane<J>((uint32_t)v);
+    uint32_t hi = xor_lane<J>((uint32_t)(v >> 32));
+    return (uint64_t(hi) << 32) | lo;
+}
+
+// Sum over aligned groups of G lanes (G = 1, 2, 4, 8, 16 or 32); every lane
+// of a group receives the group's sum.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T x) {
+    if constexpr (G >= 16) {
+        x += dpp<DPP_ROW_ROR8>(x);
+        x += dpp<DPP_ROW_ROR4>(x);
+    } else if constexpr (G == 8) {
+        x += dpp<DPP_HALF_MIRROR>(x);
+    }
+    if constexpr (G >= 4) x += dpp<DPP_QP_2301>(x);
+    if constexpr (G >= 2) x += dpp<DPP_QP_1032>(x);
+    if constexpr (G >= 32) x += swz_xor<16>(x);
+    static_assert(G <= 32, "groups of at most 32 lanes");
+    return x;
+}
+
+// Same for a wave-uniform run-time G in {4, 8, 16, 32}: quad sums first, then
+// the other quad of each 8 (half mirror), the other 8 of each 16 (rotate by
+// 8), the other 16 of each 32.
+template <typename T>
+__device__ __forceinline__ T group_sum_rt(T x, int G) {
+    x += dpp<DPP_QP_1032>(x);
+    x += dpp<DPP_QP_2301>(x);
+    if (G >= 8) x += dpp<DPP_HALF_MIRROR>(x);
+    if (G >= 16) x += dpp<DPP_ROW_ROR8>(x);
+    if (G >= 32) x += swz_xor<16>(x);
+    return x;
+}
+
+// One compare-exchange step of the bitonic network: block size K, distance J.
+template <int K, int J>
+__device__ __forceinline__ uint64_t bitonic_step(uint64_t key, int lane) {
+    uint64_t other = xor_lane64<J>(key);
+    bool up = (lane & K) == 0;
+    bool lower = (lane & J) == 0;
+    uint64_t mn = key < other ? key : other;
+    uint64_t mx = key < other ? other : key;
+    return (lower == up) ? mn : mx;
+}
+
+template <int K, int J>
+__device__ __forceinline__ uint64_t bitonic_merge(uint64_t key, int lane) {
+    key = bitonic_step<K, J>(key, lane);
+    if constexpr (J > 1) key = bitonic_merge<K, J / 2>(key, lane);
+    return key;
+}
+
 // Ascending bitonic sort of one key per lane over the first `width` lanes
 // (width a power of two, 1..64, wave-uniform); lanes >= width must hold
 // keys no smaller than the keys being sorted (KEY_MAX padding).
 __device__ __forceinline__ uint64_t wave_sort(uint64_t key, int width) {
     const int lane = lane_id();
-    for (int k = 2; k <= width; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            uint64_t other = shfl_xor64(key, j);
-            bool up = (lane & k) == 0;
-            bool lower = (lane & j) == 0;
-            uint64_t mn = key < other ? key : other;
-            uint64_t mx = key < other ? other : key;
-            key = (lower == up) ? mn : mx;
-        }
-    }
+    if (width >= 2) key = bitonic_merge<2, 1>(key, lane);
+    if (width >= 4) key = bitonic_merge<4, 2>(key, lane);
+    if (width >= 8) key = bitonic_merge<8, 4>(key, lane);
+    if (width >= 16) key = bitonic_merge<16, 8>(key, lane);
+    if (width >= 32) key = bitonic_merge<32, 16>(key, lane);
+    if (width >= 64) key = bitonic_merge<64, 32>(key, lane);
     return key;
 }
 

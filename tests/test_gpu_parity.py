@@ -272,6 +272,40 @@ def test_search_mixed_k_eps_ep_per_query():
     assert np.array_equal(host(r.hops), ref["hops"])
 
 
+@pytest.mark.parametrize("per_query,shape", [(False, None), (True, None),
+                                               (True, dict(s_capacity=64, visited_log2=8))])
+def test_search_dc_budget(per_query, shape):
+    """Distance-computation budget: ids, distances, counts and expansions equal
+    the oracle's with the same budget; the flag marks budget stops only."""
+    P = c1_problem()
+    po, pn, _ = P["pa"]
+    nq = len(P["q"])
+    g = np.random.default_rng(11)
+    full = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, 0.2, orc.INF_EP)
+    if per_query:
+        frac = g.choice([-1.0, 0.0, 0.1, 0.3, 0.5, 0.9, 1.0, 2.0], nq)
+        md = np.where(frac < 0, 0, np.maximum(1, frac * full["dc"])).astype(np.int32)
+    else:
+        md = int(np.median(full["dc"]))
+    say("search distance budget", per_query, shape)
+    ref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, 0.2, orc.INF_EP, max_dc=md)
+    A = api()
+    cfg = A.launch_config(**shape) if shape else None
+    r = A.search(gpu_vectors(P["x"], orc.L2SQ), gpu_graph(po, pn), gpu_vectors(P["q"], orc.L2SQ),
+                 to_dev(P["seeds"]), k=10, eps=0.2,
+                 max_dc=to_dev(md) if per_query else md, launch=cfg)
+    torch.cuda.synchronize()
+    _assert_exact(r, ref, 10)
+    b = np.broadcast_to(np.asarray(md), (nq,))
+    stopped = (host(r.flags) & L().QF_BUDGET) != 0
+    assert np.all(ref["dc"][stopped] >= b[stopped])
+    # a budget that was never reached changes nothing
+    same = (b <= 0) | (b > full["dc"])
+    assert not np.any(stopped & same)
+    assert np.array_equal(ref["ids"][same], full["ids"][same])
+    assert np.any(stopped)
+
+
 @pytest.mark.parametrize("probe,shape", [(1, None), (3, None), (3, dict(s_capacity=64))])
 def test_two_phase_features(probe, shape):
     """Features after `probe` expansions equal the oracle's, also when the

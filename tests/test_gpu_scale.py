@@ -1,0 +1,263 @@
+"""Parity at the full one-million-object sizes, in the launch configuration the
+benchmark uses (library defaults): every GPU stage runs on the whole input,
+and sampled outputs are checked one by one against the oracle or against the
+definition of the stage.
+
+u8 (1,000,000 x 128, 1,000 clusters; kNN k=100, e_o=20/e_i=60):
+  kNN rows bit-exact on sampled rows; static degree adjustment equal to the
+  closed form F(o) u Rv(o) of Algorithm 2 on sampled nodes; path adjustment:
+  every decision of Algorithm 4 on sampled nodes consistent with the returned
+  graph (see test_c2_path_adjustment_decisions); search ids, distances,
+  distance computations and expansions bit-exact on sampled queries.
+f32 cosine (1,000,000 x 100, Zipf clusters): sampled kNN rows and searches
+  (plain f32 and f16 rows + f32 rerank) under the margin rule.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1810_07355_amd import datagen as dg
+
+from gpu_common import api, gpu_vectors, have_gpu, host, L, margin_ok, say, to_dev, torch
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not have_gpu(), reason="needs an MI355X GPU")]
+
+NS = 8           # seeds per query
+N_ROWS = 256     # sampled kNN rows
+N_NODES = 1500   # sampled nodes for the graph adjustments
+N_Q = 200        # sampled queries
+
+
+def _sample(n, m, seed):
+    return np.sort(np.random.default_rng(seed).choice(n, size=m, replace=False))
+
+
+@functools.lru_cache(maxsize=None)
+def c2():
+    cfg = dg.PRESETS["c2"]
+    say("c2: generating", cfg.n_base, "x", cfg.dim, "u8")
+    x, q = dg.base(cfg), dg.queries(cfg)
+    A, Lb = api(), L()
+    B, Q = gpu_vectors(x, orc.L2SQ), gpu_vectors(q, orc.L2SQ)
+    say("c2: kNN, degree adjustment, path adjustment on the GPU")
+    ids, d = A.build_knn(B, cfg.knn_k)
+    sa = A.adjust_degree(ids, d, Lb.U8, Lb.L2SQ, cfg.e_o, cfg.e_i)
+    pa = A.adjust_path(sa, Lb.U8, Lb.L2SQ)
+    piv = dg.pivots(cfg)
+    seeds, _ = A.topk(Q, B, NS, cand=to_dev(piv))
+    torch.cuda.synchronize()
+    return dict(cfg=cfg, x=x, q=q, B=B, Q=Q, knn=host(ids), kd=host(d),
+                sa=(host(sa.offsets), host(sa.nbrs), host(sa.lens)),
+                pa=(host(pa.offsets), host(pa.nbrs), host(pa.lens)), pa_graph=pa, piv=piv,
+                seeds=host(seeds))
+
+
+def test_c2_knn_rows_sampled():
+    P = c2()
+    rows = _sample(P["cfg"].n_base, N_ROWS, 1)
+    say("c2: oracle kNN of", len(rows), "sampled rows")
+    bv = orc.Vectors.from_array(P["x"], orc.L2SQ)
+    rid, rd = orc.knn_graph(bv, P["cfg"].knn_k, rows=rows)
+    assert np.array_equal(P["knn"][rows], rid)
+    assert np.array_equal(P["kd"][rows], rd.astype(np.int32))
+
+
+def test_c2_seeds_sampled():
+    P = c2()
+    qs = _sample(P["cfg"].n_query, N_Q, 2)
+    bv = orc.Vectors.from_array(P["x"], orc.L2SQ)
+    qv = orc.Vectors.from_array(P["q"][qs], orc.L2SQ)
+    sid, _ = orc.topk(qv, bv, NS, cand=P["piv"])
+    assert np.array_equal(P["seeds"][qs], sid)
+
+
+def test_c2_degree_adjustment_closed_form():
+    """Algorithm 2 (loop guard read with "or"): N(o) = the first e_o entries of
+    kNN(o) together with every m that has o among the first e_i entries of
+    kNN(m), each list sorted by (length, id); u8 lengths are symmetric."""
+    P = c2()
+    cfg = P["cfg"]
+    knn, kd = P["knn"], P["kd"]
+    off, nb, ln = P["sa"]
+    nodes = _sample(cfg.n_base, N_NODES, 3)
+    ei = min(cfg.e_i, cfg.knn_k)
+    eo = min(cfg.e_o, cfg.knn_k)
+    tgt = knn[:, :ei].ravel()
+    hit = np.isin(tgt, nodes)
+    src = np.nonzero(hit)[0] // ei
+    pos = np.nonzero(hit)[0] % ei
+    tg = tgt[hit]
+    order = np.argsort(tg, kind="stable")
+    src, pos, tg = src[order], pos[order], tg[order]
+    starts = np.searchsorted(tg, nodes, side="left")
+    ends = np.searchsorted(tg, nodes, side="right")
+    for o, s0, s1 in zip(nodes, starts, ends):
+        edges = {}
+        for j in range(eo):
+            edges[int(knn[o, j])] = int(kd[o, j])
+        for m, p in zip(src[s0:s1], pos[s0:s1]):
+            edges.setdefault(int(m), int(kd[m, p]))
+        want = sorted(edges.items(), key=lambda t: (t[1], t[0]))
+        got_n = nb[off[o]:off[o + 1]]
+        got_l = ln[off[o]:off[o + 1]]
+        assert got_n.tolist() == [m for m, _ in want], o
+        assert got_l.tolist() == [l for _, l in want], o
+
+
+def test_c2_path_adjustment_decisions():
+    """Algorithm 4 visits, in round j, every node n (ascending id) with more
+    than j edges in the degree-adjusted graph G_e and keeps its j-th edge
+    n -> t unless some c already kept by n (round < j) has t in its kept list
+    with len(c, t) < len(n, t) (Algorithm 5, strict).  Kept edges of c count
+    if c kept t in a round < j, or in round j with c < n.  Taking the returned
+    graph as the set of kept edges, every decision of every sampled node must
+    agree with that rule; consistency at all nodes would imply, by induction
+    over (j, n), that the returned graph is the sequential result."""
+    P = c2()
+    so, sn, sl = P["sa"]
+    po, pn, pl = P["pa"]
+    nodes = _sample(P["cfg"].n_base, N_NODES, 4)
+
+    def sa_rank(c):
+        return {int(t): j for j, t in enumerate(sn[so[c]:so[c + 1]])}
+
+    rank_cache = {}
+
+    def kept(c):
+        """c's kept targets -> (round, length)."""
+        if c not in rank_cache:
+            rk = sa_rank(c)
+            rank_cache[c] = {int(t): (rk[int(t)], int(l))
+                             for t, l in zip(pn[po[c]:po[c + 1]], pl[po[c]:po[c + 1]])}
+        return rank_cache[c]
+
+    removed = 0
+    for n in nodes:
+        n = int(n)
+        mine = kept(n)
+        # the returned list is an order-preserving subset of the input list
+        sa_list = sn[so[n]:so[n + 1]].tolist()
+        it = iter(sa_list)
+        assert all(t in it for t in pn[po[n]:po[n + 1]].tolist()), n
+        for j, (t, l) in enumerate(zip(sa_list, sl[so[n]:so[n + 1]].tolist())):
+            witness = False
+            for c, (jc, _) in mine.items():
+                if jc >= j:
+                    continue
+                e = kept(c).get(t)
+                if e is None:
+                    continue
+                jt, lt = e
+                if (jt < j or (jt == j and c < n)) and lt < l:
+                    witness = True
+                    break
+            assert (t in mine) == (not witness), (n, j, t)
+            removed += witness
+    assert removed > 0
+
+
+@pytest.mark.parametrize("k,eps", [(10, 0.0), (10, 0.05), (10, 0.1), (100, 0.05)])
+def test_c2_search_sampled_exact(k, eps):
+    P = c2()
+    A = api()
+    ep = orc.dynamic_ep(eps)
+    say("c2: search k", k, "eps", eps, "e_p", ep)
+    r = A.search(P["B"], P["pa_graph"], P["Q"], to_dev(P["seeds"]), k=k, eps=eps, ep=ep)
+    torch.cuda.synchronize()
+    qs = _sample(P["cfg"].n_query, N_Q, 5)
+    po, pn, _ = P["pa"]
+    bv = orc.Vectors.from_array(P["x"], orc.L2SQ)
+    qv = orc.Vectors.from_array(P["q"][qs], orc.L2SQ)
+    ref = orc.search(bv, po, pn, qv, P["seeds"][qs], k, eps, ep)
+    gi, gd = host(r.ids)[qs], host(r.dists)[qs]
+    assert np.array_equal(gi, ref["ids"])
+    rd = np.where(np.isinf(ref["dists"]), 2 ** 31 - 1, ref["dists"]).astype(np.int64)
+    assert np.array_equal(gd.astype(np.int64), rd)
+    assert np.array_equal(host(r.dc)[qs], ref["dc"])
+    assert np.array_equal(host(r.hops)[qs], ref["hops"])
+    assert not np.any(host(r.flags) & L().QF_CAPACITY)
+
+
+# ------------------------------------------------------ f32 cosine, 1M --
+
+@functools.lru_cache(maxsize=None)
+def c3():
+    cfg = dg.PRESETS["c3"]
+    say("c3: generating", cfg.n_base, "x", cfg.dim, "f32 cosine")
+    x, q = dg.base(cfg), dg.queries(cfg)
+    A, Lb = api(), L()
+    B, Q = gpu_vectors(x, orc.COS), gpu_vectors(q, orc.COS)
+    say("c3: kNN, degree adjustment, path adjustment on the GPU")
+    ids, d = A.build_knn(B, cfg.knn_k)
+    sa = A.adjust_degree(ids, d, Lb.F32, Lb.COSINE, cfg.e_o, cfg.e_i)
+    pa = A.adjust_path(sa, Lb.F32, Lb.COSINE)
+    del sa
+    piv = dg.pivots(cfg)
+    seeds, _ = A.topk(Q, B, NS, cand=to_dev(piv))
+    torch.cuda.synchronize()
+    return dict(cfg=cfg, x=x, q=q, B=B, Q=Q, knn=host(ids), kd=host(d),
+                pa=(host(pa.offsets), host(pa.nbrs)), pa_graph=pa, seeds=host(seeds))
+
+
+def test_c3_knn_rows_sampled():
+    P = c3()
+    rows = _sample(P["cfg"].n_base, 64, 6)
+    bv = orc.Vectors.from_array(P["x"], orc.COS)
+    rid, rd = orc.knn_graph(bv, P["cfg"].knn_k, rows=rows)
+    gi, gd = P["knn"][rows], P["kd"][rows].astype(np.float64)
+    assert np.all(np.abs(gd - rd) <= 1e-4 * np.maximum(np.abs(rd), 1e-2))
+    for r in range(len(rows)):
+        diff = set(gi[r].tolist()) ^ set(rid[r].tolist())
+        kth = rd[r, -1]
+        for j in diff:          # only objects tied with the k-th within 1e-5 may differ
+            dj = orc.lib().or_dist(bv.ref, int(j), bv.ref, int(rows[r]))
+            assert abs(dj - kth) <= 1e-5 * max(kth, 1e-2)
+
+
+@pytest.mark.parametrize("lp", [None, "f16"])
+def test_c3_search_sampled_margin(lp):
+    """Plain f32 search, and f16 rows (the oracle searches the decoded rows)
+    with the f32 rerank of the 4k best, at the recall-0.95 range of the
+    benchmark (eps 0.111, dynamic e_p)."""
+    P = c3()
+    A, Lb = api(), L()
+    eps = 0.1113
+    ep = orc.dynamic_ep(eps)
+    qs = _sample(P["cfg"].n_query, N_Q, 7)
+    po, pn = P["pa"]
+    qv = orc.Vectors.from_array(P["q"][qs], orc.COS)
+    if lp is None:
+        base, bv = P["B"], orc.Vectors.from_array(P["x"], orc.COS)
+        kw = {}
+    else:
+        base = A.encode(to_dev(P["x"]), Lb.F16, Lb.COSINE)
+        bv = orc.Vectors(host(base.data), orc.F16, orc.COS, dim=P["x"].shape[1])
+        kw = dict(rerank_base=P["B"], pool_factor=4)
+    say("c3: search", lp or "f32", "eps", eps)
+    r = A.search(base, P["pa_graph"], P["Q"], to_dev(P["seeds"]), k=10, eps=eps, ep=ep)
+    ref = orc.search(bv, po, pn, qv, P["seeds"][qs], 10, eps, ep)
+    gi = host(r.ids)[qs]
+    ok, info = margin_ok(ref, gi, host(r.dists)[qs], ref["margin"])
+    assert ok, f"sampled query {info} differs beyond the margin"
+    assert info <= 0.1 * len(qs), f"{info} sampled queries differ"
+    assert np.array_equal(host(r.dc)[qs][ref["margin"] >= 1e-4],
+                          ref["dc"][ref["margin"] >= 1e-4])
+    if lp is not None:
+        # with the rerank: the distances are exact f32 distances of the ids,
+        # ascending, and recall does not drop against the unreranked result
+        rr = A.search(base, P["pa_graph"], P["Q"], to_dev(P["seeds"]), k=10, eps=eps, ep=ep,
+                      **kw)
+        ri, rdist = host(rr.ids)[qs], host(rr.dists)[qs]
+        fb = orc.Vectors.from_array(P["x"], orc.COS)
+        for i in range(len(qs)):
+            for j in range(10):
+                dj = orc.lib().or_dist(fb.ref, int(ri[i, j]), qv.ref, i)
+                assert abs(rdist[i, j] - dj) <= 1e-5 * max(dj, 1e-2)
+            assert np.all(np.diff(rdist[i]) >= 0)
+        gt, _ = A.ground_truth(P["Q"], P["B"], 10)
+        gt = host(gt)[qs]
+        rec = lambda ids: np.mean([len(set(a) & set(b)) / 10 for a, b in zip(ids, gt)])
+        assert rec(ri) >= rec(gi) - 1e-9

@@ -383,6 +383,40 @@ def test_search_c_oracle_equals_literal_transcription(kind, seed):
             assert r["dc"][qi] == dc and r["hops"][qi] == hops
 
 
+def test_search_budget_is_a_prefix_of_the_full_search():
+    """A distance-computation budget b (an addition to Algorithm 1) stops
+    before the first pop at which the count has reached b, so the budgeted
+    run equals the unbudgeted run cut after that many expansions: its hops
+    and count are read off the full run's per-expansion trace."""
+    n = 400
+    cfg = dg.scaled(dg.PRESETS["c1"], n, 10, n_clusters=3)
+    cfg = dataclass_replace(cfg, config_id=77)
+    x = dg._vectors(cfg, n, 1)
+    q = dg._vectors(cfg, 10, 2)
+    bv = orc.Vectors.from_array(x, orc.L2SQ)
+    qv = orc.Vectors.from_array(q, orc.L2SQ)
+    knn, kd = orc.knn_graph(bv, 12)
+    off, nb, ln = orc.adjust_degree(knn, kd, 4, 10)
+    seeds = dg.random_seeds(cfg, 10, 4)
+    adj = [nb[off[u]:off[u + 1]].tolist() for u in range(n)]
+    f = orc.range_factor(0.3, orc.L2SQ)
+    thr = lambda rr: math.inf if math.isinf(rr) else float(np.float32(rr) * f)
+    for qi in range(10):
+        dfun = lambda u: orc.lib().or_dist(bv.ref, u, qv.ref, qi)
+        trace = []
+        R_full, dc_full, hops_full = literal.knn_search(adj, dfun, seeds[qi].tolist(), 5, thr,
+                                                        trace=trace)
+        assert trace[-1] == dc_full and len(trace) == hops_full + 1
+        for b in sorted({1, 4, 5, trace[min(2, hops_full)], trace[hops_full // 2] + 1,
+                         dc_full, dc_full + 10}):
+            h = next((i for i, c in enumerate(trace) if c >= b), hops_full)
+            r = orc.search(bv, off, nb, orc.Vectors.from_array(q[qi:qi + 1], orc.L2SQ),
+                           seeds[qi:qi + 1], 5, 0.3, max_dc=b)
+            assert r["hops"][0] == h and r["dc"][0] == trace[h], (qi, b)
+            if b > dc_full:
+                assert r["ids"][0].tolist()[:len(R_full)] == [i for _, i in R_full]
+
+
 def test_search_pads_when_few_reachable():
     x = dg.random_vectors(10, 4, "u8", 3)
     bv = orc.Vectors.from_array(x, orc.L2SQ)
