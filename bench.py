@@ -37,6 +37,37 @@ def log(*a):
     print(f"[bench {time.time() - T0:7.1f}s]", *a, file=sys.stderr, flush=True)
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "search_kernel_c3_counters.txt")
+KERNEL_SOURCES = ["search.hip", "search_args.h", "wave.h", "dist.h", "onng_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1810_07355_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the timed search kernel from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's
+    reading), or None when that summary was taken on other kernel sources."""
+    try:
+        with open(COUNTERS) as fh:
+            kv = dict(l.split(":", 1) for l in fh if ":" in l and not l.startswith(" "))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +82,11 @@ def parse():
     ap.add_argument("--dump", default=None, help="save per-query sweep data (.npz)")
     ap.add_argument("--probe-hops", type=int, default=1,
                     help="expansions before the learned range is chosen")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB device buffer 5 times and exit (the plain copy "
+                         "whose counters calibrate FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--row-align", type=int, default=128,
+                    help="pad searched rows to a multiple of this many bytes (cache lines)")
     ap.add_argument("--inflight", type=int, default=2,
                     help="query batches in flight in the timed region (one stream each)")
     ap.add_argument("--search-only", action="store_true",
@@ -68,6 +104,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_probe:
+        n = args.copy_probe << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_probe} MiB 5 times")
+        return
 
     from paper_1810_07355_amd import _lib as L
     from paper_1810_07355_amd import api as A
@@ -120,6 +166,11 @@ def main():
                                                           cfg.e_i))
     graph = timed("adjust_path_s", lambda: A.adjust_path(sa, base.dtype, metric))
     del ids, d
+    if args.row_align > 16:
+        # searched rows start on cache-line boundaries, so a gathered row
+        # touches the fewest lines
+        base = A.Vectors.from_tensor(xt, metric,
+                                     pitch=A.row_pitch(cfg.dim, base.dtype, args.row_align))
     log(f"edges: SA {sa.nnz}, PA {graph.nnz} (mean outdegree {graph.nnz / cfg.n_base:.1f})")
     del sa
     seeds, _ = A.topk(queries, base, NS, cand=piv)
@@ -187,7 +238,8 @@ def main():
     learned_pts = {}
     if not is_u8:
         lp_dt = {"f16": L.F16, "bf16": L.BF16, "fp8": L.FP8_E4M3}[args.lp]
-        lp_rows = A.encode(xt, lp_dt, metric)
+        lp_rows = A.encode(xt, lp_dt, metric,
+                           pitch=A.row_pitch(cfg.dim, lp_dt, max(16, args.row_align)))
         make_lp = lambda e: A.SearchRequest(lp_rows, graph, queries, seeds, k=K, eps=e,
                                             ep=LR.dynamic_ep(e), rerank_base=base, pool_factor=4)
         curve["lp"] = [measure(make_lp, e, args.lp + "+rerank") for e in curve_eps]
@@ -257,45 +309,50 @@ def main():
     # Distance-computation budgets bound the rare very long queries, which
     # otherwise set the batch time.  Each variant gets the budget (a multiple
     # of the plain operating point's mean count, or none) that serves it best.
-    def best_over_budgets(make_b, tgt, lo, hi, name):
+    def best_over_budgets(make_b, tgt, lo, hi, name, factors=(0.0,)):
         base_pt = result["plain"][str(tgt)]
-        mults = [0, 1.5, 2.0, 3.0, 4.0]
+        mults = [0, 1.5, 2.0, 3.0, 4.0] if factors == (0.0,) else [0, 2.0, 3.0]
         best = None
         for m in mults:
             b = int(m * base_pt["dc"]) if (m and base_pt) else 0
-            pt = bisect(lambda kn: make_b(kn, b), tgt, lo, hi, f"{name} b={b}")
-            if pt is not None:
-                pt["max_dc"] = b
-                if best is None or pt["qps"] > best["qps"]:
-                    best = pt
+            for fac in factors:
+                pt = bisect(lambda kn: make_b(kn, b, fac), tgt, lo, hi,
+                            f"{name} b={b} f={fac:g}")
+                if pt is not None:
+                    pt["max_dc"] = b
+                    pt["max_dc_factor"] = fac
+                    if best is None or pt["qps"] > best["qps"]:
+                        best = pt
         return best
 
     def make_learned_b(tgt):
-        def make(knob, b):
+        def make(knob, b, fac=0.0):
             pred = learned_pred(tgt, knob)
             req = A.LearnedSearch(search_rows, graph, queries, seeds, pred, ep_first=EPF,
-                                  probe_hops=PROBE, k=K, max_dc=b, **rr)
+                                  probe_hops=PROBE, k=K, max_dc=b, max_dc_factor=fac, **rr)
             req._pred = pred
             return req
         return make
 
     for tgt in (0.95, 0.99):
         learned_pts[str(tgt)] = best_over_budgets(make_learned_b(tgt), tgt, 2.0, 9.0,
-                                                  f"learned@{tgt}")
+                                                  f"learned@{tgt}", factors=(0.0, 2.0, 4.0))
     result["learned"] = learned_pts
     knobs = {t: (learned_pts[str(t)]["knob"] if learned_pts[str(t)] else 9.0)
              for t in (0.95, 0.99)}
     budgets = {t: (learned_pts[str(t)]["max_dc"] if learned_pts[str(t)] else 0)
                for t in (0.95, 0.99)}
+    bfactors = {t: (learned_pts[str(t)]["max_dc_factor"] if learned_pts[str(t)] else 0.0)
+                for t in (0.95, 0.99)}
     # the same budgets without the learned range, for comparison
     if lp_rows is not None:
-        make_lp_b = lambda e, b: A.SearchRequest(lp_rows, graph, queries, seeds, k=K, eps=e,
+        make_lp_b = lambda e, b, fac=0.0: A.SearchRequest(lp_rows, graph, queries, seeds, k=K, eps=e,
                                                  ep=LR.dynamic_ep(e), rerank_base=base,
                                                  pool_factor=4, max_dc=b)
         result["lp_budget"] = {str(t): best_over_budgets(make_lp_b, t, 0.0, 1.0,
                                                          args.lp + "+rerank")
                                for t in (0.95, 0.99)}
-    make_plain_b = lambda e, b: A.SearchRequest(base, graph, queries, seeds, k=K, eps=e,
+    make_plain_b = lambda e, b, fac=0.0: A.SearchRequest(base, graph, queries, seeds, k=K, eps=e,
                                                 ep=LR.dynamic_ep(e), max_dc=b)
     result["plain_budget"] = {str(t): best_over_budgets(make_plain_b, t, 0.0, 1.0, "plain")
                               for t in (0.95, 0.99)}
@@ -311,7 +368,8 @@ def main():
     # one pipeline (own outputs and workspace) and one stream per batch in flight
     pipes = [A.Pipeline(search_rows, graph, queries, piv, NS, k=K, eps=0.0, ep=L.EP_INF,
                         two_phase=True, ep_first=EPF, probe_hops=PROBE, predictor=pred95,
-                        max_dc=budgets[0.95], **rr) for _ in range(NF)]
+                        max_dc=budgets[0.95], max_dc_factor=bfactors[0.95], **rr)
+             for _ in range(NF)]
     pipe = pipes[0]
     plain95 = result["plain"]["0.95"]
     pipes_plain = []
@@ -334,7 +392,7 @@ def main():
         return last
 
     if args.search_only:
-        req = make_learned_b(0.95)(knobs[0.95], budgets[0.95])
+        req = make_learned_b(0.95)(knobs[0.95], budgets[0.95], bfactors[0.95])
         for _ in range(args.warmup + args.steps):
             req.run()
         torch.cuda.synchronize()
@@ -366,7 +424,7 @@ def main():
             f"{plain_pipe_qps:.0f} q/s")
 
     # ---------------------------------------- roofline of the search kernel --
-    lreq = make_learned_b(0.95)(knobs[0.95], budgets[0.95])
+    lreq = make_learned_b(0.95)(knobs[0.95], budgets[0.95], bfactors[0.95])
     lreq.run()
     req = lreq.req                 # the search pass (predict pass and order excluded)
     ms_search = time_req(req, reps=5)
@@ -384,7 +442,7 @@ def main():
     bytes_launch = float(per_query.sum())
     achieved = bytes_launch / (ms_search / 1e3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=8000.0, unit="GB/s",
-                    frac=round(achieved / 8000.0, 4), traffic=None,
+                    frac=round(achieved / 8000.0, 4), traffic=measured_traffic(),
                     kernel="search_kernel", bytes_per_launch=bytes_launch,
                     ms_per_launch=round(ms_search, 4),
                     bytes_per_query_mean=round(float(per_query.mean()), 1))
@@ -446,6 +504,7 @@ def main():
             "global_batch": cfg.n_query,
             "batches_in_flight": NF,
             "max_dc": {str(t): budgets[t] for t in (0.95, 0.99)},
+            "max_dc_factor": {str(t): bfactors[t] for t in (0.95, 0.99)},
         },
         "recall_at_timed_point": round(rec95, 4),
         "qps": {

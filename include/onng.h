@@ -250,6 +250,12 @@ typedef struct {
      * holds very many objects. */
     int32_t max_dc;
     const int32_t *max_dc_per_query;
+    /* With a learned range (range_from, or the predictor in curve mode):
+     * when > 0, each query's budget is further limited to
+     * max(64, (int32)(max_dc_factor * its predicted distance computations)),
+     * the product taken in fp32, so that a query far costlier than predicted
+     * is cut short. */
+    float max_dc_factor;
 } onng_search_params;
 
 /* Per-query statistics written by onng_search. */

@@ -53,7 +53,7 @@ class SearchParams_t(C.Structure):
                 ("predictor", P), ("features_out", P), ("rerank_base", P),
                 ("pool_factor", C.c_int32), ("launch", P), ("probe_hops", C.c_uint32),
                 ("predict_only", C.c_int32), ("range_from", P), ("order", P),
-                ("max_dc", C.c_int32), ("max_dc_per_query", P)]
+                ("max_dc", C.c_int32), ("max_dc_per_query", P), ("max_dc_factor", C.c_float)]
 
 
 # exported symbols and their prototypes (must match include/onng.h)

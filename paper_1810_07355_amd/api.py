@@ -28,9 +28,9 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
-def row_pitch(dim: int, dtype: int) -> int:
-    """Smallest 16-byte multiple holding `dim` elements of `dtype`."""
-    return (dim * _DTYPE_BYTES[dtype] + 15) // 16 * 16
+def row_pitch(dim: int, dtype: int, align: int = 16) -> int:
+    """Smallest multiple of `align` bytes holding `dim` elements of `dtype`."""
+    return (dim * _DTYPE_BYTES[dtype] + align - 1) // align * align
 
 
 class Vectors:
@@ -59,12 +59,13 @@ class Vectors:
         return torch.int32 if (self.dtype == L.U8 and self.metric == L.L2SQ) else torch.float32
 
     @staticmethod
-    def from_tensor(x: torch.Tensor, metric: int) -> "Vectors":
-        """u8 or f32 rows, padded to a 16-byte pitch with zeros."""
+    def from_tensor(x: torch.Tensor, metric: int, pitch: int | None = None) -> "Vectors":
+        """u8 or f32 rows, padded with zeros to a 16-byte pitch (or to
+        `pitch` bytes, e.g. whole 128-byte cache lines)."""
         n, dim = x.shape
         dtype = L.U8 if x.dtype == torch.uint8 else L.F32
         esz = _DTYPE_BYTES[dtype]
-        cols = row_pitch(dim, dtype) // esz
+        cols = max(row_pitch(dim, dtype), pitch or 0) // esz
         if cols != dim:
             buf = torch.zeros((n, cols), dtype=x.dtype, device=x.device)
             buf[:, :dim] = x
@@ -198,7 +199,7 @@ class SearchRequest:
                  predictor: Predictor | None = None, want_features=False,
                  rerank_base: Vectors | None = None, pool_factor=4, launch=None, probe_hops=1,
                  predict_only=False, range_from: torch.Tensor | None = None,
-                 order: torch.Tensor | None = None, max_dc=0):
+                 order: torch.Tensor | None = None, max_dc=0, max_dc_factor=0.0):
         dev = queries.data.device
         nq = queries.n
         self.base, self.graph, self.queries = base, graph, queries
@@ -237,7 +238,7 @@ class SearchRequest:
             C.cast(rerank_base.ref, C.c_void_p) if rerank_base else None,
             int(pool_factor), C.cast(C.byref(launch), C.c_void_p) if launch is not None else None,
             int(probe_hops), int(predict_only), _ptr(range_from), _ptr(order), int(max_dc),
-            _ptr(mdq))
+            _ptr(mdq), float(max_dc_factor))
         self._keep += [range_from, order]
         self.gs = graph.struct()
         out_dt = torch.float32 if rerank_base is not None else base.dist_dtype

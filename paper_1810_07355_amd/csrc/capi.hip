@@ -122,9 +122,15 @@ struct SearchPlan {
 };
 
 // 16-byte pieces of a row per lane (matches the search kernel's query registers)
-static int ppl_for(int dtype) { return dtype == ONNG_FP8_E4M3 ? 1 : 2; }
+static int ppl_for(int) { return 2; }
 
 static int align16(int x) { return (x + 15) / 16 * 16; }
+
+// 16-byte pieces that hold a row's components (rows may be padded further,
+// e.g. to whole cache lines; the padding is zero and never read)
+static int row_pieces(const onng_vectors *v) {
+    return (int)(((int64_t)v->dim * elem_bytes(v->dtype) + 15) / 16);
+}
 
 static onng_status make_plan(const onng_vectors *base, int64_t nq, const onng_search_params *p,
                              const onng_launch_config *cfg, SearchPlan *plan) {
@@ -134,7 +140,7 @@ static onng_status make_plan(const onng_vectors *base, int64_t nq, const onng_se
         set_error("onng_search: unsupported dtype/metric");
         return ONNG_ERR_UNSUPPORTED;
     }
-    const int n16 = (int)(base->pitch_bytes / 16);
+    const int n16 = row_pieces(base);
     const int ppl = ppl_for(base->dtype);
     int L = cfg && cfg->lanes_per_row ? cfg->lanes_per_row : 0;
     if (!L) {
@@ -181,10 +187,15 @@ static onng_status make_plan(const onng_vectors *base, int64_t nq, const onng_se
     P.off_s = o; o = align16(o + P.s_cap * 8);
     P.off_stage = o; o = align16(o + 64 * 8);
     P.off_stage2 = o; o = align16(o + 64 * 8);
-    P.off_ids = o; o = align16(o + 64 * 4);
+    P.off_ids = o; o = align16(o + 128 * 4);
     P.off_vis = o; o = align16(o + (P.vis_log2 ? (4 << P.vis_log2) : 0));
     P.off_misc = o; o = align16(o + 168 * 4);
     P.lds_per_wave = o;
+    // the kernel uses the two stages as one 128-key buffer
+    if (P.off_stage2 != P.off_stage + 64 * 8) {
+        set_error("onng_search: internal LDS layout");
+        return ONNG_ERR_UNSUPPORTED;
+    }
     size_t lds = (size_t)o * P.wpb;
     if (lds > 160 * 1024) {
         set_error("onng_search: on-chip state above 160 KiB per block");
@@ -295,7 +306,7 @@ static onng_status run_search(const onng_vectors *base, const onng_graph *g,
     a.base_pitch = base->pitch_bytes;
     a.n_base = base->n;
     a.dim = base->dim;
-    a.n16 = (int)(base->pitch_bytes / 16);
+    a.n16 = row_pieces(base);
     a.offsets = g->offsets;
     a.nbrs = g->nbrs;
     a.qry = static_cast<const uint8_t *>(queries->data);
@@ -319,6 +330,7 @@ static onng_status run_search(const onng_vectors *base, const onng_graph *g,
     a.order = p->order;
     a.max_dc = p->max_dc;
     a.max_dc_pq = p->max_dc_per_query;
+    a.max_dc_factor = p->max_dc_factor;
     a.has_pred = p->predictor != nullptr;
     if (p->predictor) {
         const onng_predictor *pr = p->predictor;
@@ -591,7 +603,7 @@ onng_status onng_autotune_search(const onng_vectors *base, const onng_graph *gra
     if (lookup_tuned(base, params, best)) return ONNG_OK;
     hipStream_t st = as_stream(stream);
     std::vector<onng_launch_config> cands;
-    const int n16 = (int)(base->pitch_bytes / 16);
+    const int n16 = row_pieces(base);
     for (int L : {4, 8, 16, 32})
         for (int s_cap : {128, 256, 512})
             for (int vl : {10, 11, 12, -1})

@@ -101,7 +101,7 @@ struct Q<ONNG_U8, ONNG_L2SQ> {
 // ------------------------------------------------------ float storage ----
 template <int DT, int MT>
 struct Q {
-    static constexpr int PPL = DT == ONNG_FP8_E4M3 ? 1 : 2;
+    static constexpr int PPL = 2;
     static constexpr int N = Piece<DT>::N;
     static constexpr bool INT = false;
     float q[PPL][N];
@@ -137,7 +137,9 @@ struct Q {
 #pragma unroll
             for (int e = 0; e < N; e++) {
                 float xv = v[e];
-                if constexpr (DT == ONNG_FP8_E4M3) xv *= sc;
+                // fp8 rows carry a per-row scale: applied per component for
+                // L2, once to the dot product for cosine
+                if constexpr (DT == ONNG_FP8_E4M3 && MT == ONNG_L2SQ) xv *= sc;
                 if constexpr (MT == ONNG_L2SQ) {
                     float df = xv - q[t][e];
                     acc[e & 1] = fmaf(df, df, acc[e & 1]);
@@ -146,6 +148,7 @@ struct Q {
                 }
             }
         }
+        if constexpr (DT == ONNG_FP8_E4M3 && MT != ONNG_L2SQ) return (acc[0] + acc[1]) * sc;
         return acc[0] + acc[1];
     }
 };
@@ -181,7 +184,7 @@ search_kernel(SearchKArgs a) {
     constexpr bool INT = QT::INT;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int lane = lane_id();
-    const int wib = threadIdx.x / WAVE;
+    const int wib = uni(threadIdx.x / WAVE);   // wave-uniform: derived pointers stay scalar
     const int slot = blockIdx.x * a.waves_per_block + wib;
 
     char *w = smem + (size_t)wib * a.lds_per_wave;
@@ -193,6 +196,8 @@ search_kernel(SearchKArgs a) {
     lds.ids = reinterpret_cast<uint32_t *>(w + a.off_ids);
     lds.vis = reinterpret_cast<uint32_t *>(w + a.off_vis);
     lds.misc = reinterpret_cast<float *>(w + a.off_misc);
+    // 128 keys: the two 64-key stages are adjacent
+    uint64_t *const kbuf = lds.stage;
 
     uint32_t *gbits = a.gbits + (size_t)slot * a.gbits_words;
     int32_t *vlog = a.vlog + (size_t)slot * a.vlog_cap;
@@ -231,6 +236,14 @@ search_kernel(SearchKArgs a) {
         const int pool_q = a.has_rr ? min(a.pool_cap, max(k, a.pool_factor * k)) : k;
         int max_dc = a.max_dc_pq ? uni(a.max_dc_pq[qi]) : a.max_dc;
         if (max_dc <= 0) max_dc = INT32_MAX;
+        // budget relative to the predicted cost of the chosen range
+        auto cost_budget = [&](float c) {
+            if (a.max_dc_factor > 0.0f) {
+                float b = fminf(a.max_dc_factor * c, 2.0e9f);
+                max_dc = min(max_dc, max(64, (int)b));
+            }
+        };
+        if (a.range_from) cost_budget(unif(a.range_from[qi].cost));
 
         QT qr;
         const uint8_t *qrow = a.qry + (size_t)qi * a.q_pitch;
@@ -250,6 +263,12 @@ search_kernel(SearchKArgs a) {
         int flags = 0;
         bool rfull = false;
         float r = F_INF;
+        // guessed next expansion (see the expansion loop)
+        constexpr uint32_t NO_SPEC = 0xFFFFFFFFu;
+        uint32_t spec_id = NO_SPEC;
+        int64_t spec_e0 = 0, spec_deg = 0;
+        uint32_t spec_nb = 0, spec_nb1 = 0;
+        bool spec_vis = false, spec_bit = false, spec_bit1 = false;
 
         // clear the on-chip visited table
         for (int i = lane; i <= (int)vmask && a.vis_log2 > 0; i += WAVE) lds.vis[i] = VIS_EMPTY;
@@ -262,7 +281,9 @@ search_kernel(SearchKArgs a) {
 
         // -------------------------------------------------- helpers ------
         // Mark a batch of ids visited; returns whether this lane's id is new.
-        auto visit = [&](bool valid, uint32_t id) -> bool {
+        // known_ok: in global mode the caller already read the bit (known_bit)
+        auto visit = [&](bool valid, uint32_t id, bool known_ok = false,
+                         bool known_bit = false) -> bool {
             bool isnew = false;
             if (!gmode) {
                 if (valid) {
@@ -295,7 +316,14 @@ search_kernel(SearchKArgs a) {
                     gbits_clean = false;
                 }
             } else {
-                if (valid) {
+                if (known_ok) {
+                    // ids of one adjacency list are distinct, so the bits read
+                    // before this expansion decide; the marks need no reply
+                    isnew = valid && !known_bit;
+                    if (isnew)
+                        __hip_atomic_fetch_or(&gbits[id >> 5], 1u << (id & 31), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                } else if (valid) {
                     uint32_t bit = 1u << (id & 31);
                     uint32_t old = atomicOr(&gbits[id >> 5], bit);
                     isnew = (old & bit) == 0;
@@ -308,7 +336,7 @@ search_kernel(SearchKArgs a) {
             return isnew;
         };
 
-        // Distances of rows lds.ids[0..u) -> lds.stage2[i] as keys.  A lane
+        // Distances of rows lds.ids[0..u) -> kbuf[i] as keys (u <= 128).  A lane
         // group of L lanes takes one row; the loads of UP row passes are
         // issued together so that several rows per lane are in flight.
         auto batch_keys = [&](int u) {
@@ -340,7 +368,7 @@ search_kernel(SearchKArgs a) {
                         uint32_t dord;
                         if constexpr (INT) dord = acc;
                         else dord = ord_f32(MT == ONNG_COSINE ? 1.0f - acc : acc);
-                        lds.stage2[row] = make_key(dord, rid[up]);
+                        kbuf[row] = make_key(dord, rid[up]);
                     }
                 }
             }
@@ -396,18 +424,37 @@ search_kernel(SearchKArgs a) {
         // Drop S entries beyond the range (a suffix of the sorted array).
         auto s_prune = [&](float thr) {
             if (size == head || __builtin_isinf(thr)) return;
-            // first index with d > thr
-            int lo = head, hi = size;
-            while (lo < hi) {
-                int mid = (lo + hi) >> 1;
-                if (key_dist<INT>(lds.S[mid]) > thr) hi = mid;
-                else lo = mid + 1;
+            if (key_dist<INT>(lds.S[size - 1]) <= thr) return;   // all within range
+            // first index with d > thr: every stride-th entry first, then the
+            // entries between the last sample within range and the next one
+            const int n = size - head;
+            const int stride = (n + WAVE - 1) / WAVE;
+            const int i1 = head + lane * stride;
+            uint64_t m = ballot(i1 < size && key_dist<INT>(lds.S[i1]) > thr);
+            const int ns = (n + stride - 1) / stride;
+            const int b = m ? (int)__builtin_ctzll(m) : ns;
+            if (b == 0) {
+                size = head;
+                return;
             }
-            size = uni(lo);
+            const int lo = head + (b - 1) * stride + 1;
+            const int hi = min(head + b * stride, size);
+            int cut = hi;
+            for (int c = lo; c < hi; c += WAVE) {
+                const int i2 = c + lane;
+                uint64_t m2 = ballot(i2 < hi && key_dist<INT>(lds.S[i2]) > thr);
+                if (m2) {
+                    cut = c + (int)__builtin_ctzll(m2);
+                    break;
+                }
+            }
+            size = uni(cut);
         };
 
         // Merge sorted keys into the pool (R and rerank candidates).
         auto pool_insert = [&](uint64_t key, int nb) {
+            // a full pool only takes keys below its last one (a sorted prefix)
+            if (npool == pool_q) nb = __popcll(ballot(lane < nb && key < lds.pool[pool_q - 1]));
             if (nb == 0) return;
             int total = merge_sorted(lds.pool, 0, npool, key, nb, pool_q, lds.stage, NoSpill());
             npool = min(total, pool_q);
@@ -418,21 +465,22 @@ search_kernel(SearchKArgs a) {
             }
         };
 
-        // Process a sorted batch: R first, then the range test with the new r.
-        auto absorb = [&](uint64_t key, int u, bool to_s) {
-            pool_insert(key, u);
+        // Process a sorted batch: R first (absorb_pool), then the range test
+        // with the new r and the insertion into S (absorb_s).
+        auto absorb_pool = [&](uint64_t key, int u) { pool_insert(key, u); };
+        auto absorb_s = [&](uint64_t key, int u, bool to_s) {
             float thr = threshold(rfull, r, f);
+            // the batch is sorted, so the keys within range are a prefix
             bool keep = lane < u && key_dist<INT>(key) <= thr;
             if (!to_s) keep = lane < u;
-            uint64_t m = ballot(keep);
-            int nk = __popcll(m);
-            // compact (order preserved)
-            if (keep) lds.stage2[mbcnt(m)] = key;
-            wave_sync();
-            uint64_t ck = lane < nk ? lds.stage2[lane] : KEY_MAX;
-            wave_sync();
+            const int nk = __popcll(ballot(keep));
+            const uint64_t ck = lane < nk ? key : KEY_MAX;
             s_prune(thr);
             s_insert(ck, nk);
+        };
+        auto absorb = [&](uint64_t key, int u, bool to_s) {
+            absorb_pool(key, u);
+            absorb_s(key, u, to_s);
         };
 
         // Bring spilled keys back: merge every live spilled key into S, the
@@ -476,7 +524,7 @@ search_kernel(SearchKArgs a) {
             wave_sync();
             batch_keys(u);
             dc += u;
-            uint64_t key = lane < u ? lds.stage2[lane] : KEY_MAX;
+            uint64_t key = lane < u ? kbuf[lane] : KEY_MAX;
             wave_sync();
             key = wave_sort(key, pow2_at_least(u));
             if (a.two_phase) lds.misc[lane] = lane < u ? key_dist<INT>(key) : 0.0f;
@@ -502,26 +550,122 @@ search_kernel(SearchKArgs a) {
             if (key_dist<INT>(sk) > thr) break;                        // d(s,q) > r(1+eps)
             hops++;
             const uint32_t s = (uint32_t)sk;
-            const int64_t e0 = a.offsets[s];
-            const int64_t deg = a.offsets[s + 1] - e0;
+            // adjacency of s: prefetched during the previous expansion when
+            // that one guessed this pop, else read now
+            const bool hit = s == spec_id;
+            spec_id = NO_SPEC;
+            int64_t e0, deg;
+            if (hit) {
+                e0 = spec_e0;
+                deg = spec_deg;
+            } else {
+                e0 = a.offsets[s];
+                deg = a.offsets[s + 1] - e0;
+            }
             const int64_t np = (int64_t)ep < deg ? (int64_t)ep : deg;
             scanned += (int)np;
-            for (int64_t c0 = 0; c0 < np; c0 += WAVE) {
-                int64_t j = c0 + lane;
-                uint32_t id = j < np ? (uint32_t)a.nbrs[e0 + j] : 0u;
-                bool valid = j < np && (int64_t)id < a.n_base;
-                bool isnew = visit(valid, id);
-                uint64_t m = ballot(isnew);
-                int u = __popcll(m);
+            // The edges in groups of up to two 64-edge chunks: ids and visited
+            // marks of the group, then one distance batch for its new nodes.
+            for (int64_t g0 = 0; g0 < np; g0 += 2 * WAVE) {
+                int u = 0;
+#pragma unroll
+                for (int cc = 0; cc < 2; cc++) {
+                    const int64_t c0 = g0 + cc * WAVE;
+                    if (c0 >= np) break;
+                    const int64_t j = c0 + lane;
+                    const bool pre = hit && g0 == 0;
+                    uint32_t id;
+                    if (pre) id = j < np ? (cc == 0 ? spec_nb : spec_nb1) : 0u;
+                    else id = j < np ? (uint32_t)a.nbrs[e0 + j] : 0u;
+                    bool valid = j < np && (int64_t)id < a.n_base;
+                    bool isnew = visit(valid, id, pre && spec_vis, cc == 0 ? spec_bit : spec_bit1);
+                    uint64_t m = ballot(isnew);
+                    if (isnew) lds.ids[u + mbcnt(m)] = id;
+                    u += __popcll(m);
+                }
                 if (u == 0) continue;
-                if (isnew) lds.ids[mbcnt(m)] = id;
                 wave_sync();
                 batch_keys(u);
                 dc += u;
-                uint64_t key = lane < u ? lds.stage2[lane] : KEY_MAX;
+                uint64_t k0 = lane < u ? kbuf[lane] : KEY_MAX;
+                uint64_t k1 = lane + WAVE < u ? kbuf[lane + WAVE] : KEY_MAX;
                 wave_sync();
-                key = wave_sort(key, pow2_at_least(u));
-                absorb(key, u, true);
+                // Keys that can neither enter S (beyond the current range,
+                // which only shrinks) nor the pool (beyond its last key when
+                // full) are dropped before sorting.
+                int nk;
+                {
+                    const float thr0 = threshold(rfull, r, f);
+                    const uint64_t plast = npool == pool_q ? lds.pool[pool_q - 1] : KEY_MAX;
+                    bool keep0 = lane < u && (key_dist<INT>(k0) <= thr0 || k0 < plast);
+                    bool keep1 = lane + WAVE < u && (key_dist<INT>(k1) <= thr0 || k1 < plast);
+                    uint64_t m0 = ballot(keep0), m1 = ballot(keep1);
+                    const int n0 = __popcll(m0);
+                    nk = n0 + __popcll(m1);
+                    if (nk < u) {
+                        if (keep0) kbuf[mbcnt(m0)] = k0;
+                        if (keep1) kbuf[n0 + mbcnt(m1)] = k1;
+                        wave_sync();
+                        k0 = lane < nk ? kbuf[lane] : KEY_MAX;
+                        k1 = lane + WAVE < nk ? kbuf[lane + WAVE] : KEY_MAX;
+                        wave_sync();
+                    }
+                }
+                const int na = min(nk, WAVE), nb2 = nk - na;
+                // Guess the next pop (the smaller of S's head and this group's
+                // minimum, when within range and no spilled key is smaller)
+                // and start reading its adjacency (two chunks) and visited bits
+                // while the batch is sorted and merged.  A wrong guess only
+                // wastes the reads.
+                bool go = false;
+                int64_t spec_ofs = 0;
+                if (g0 + 2 * WAVE >= np) {
+                    uint64_t bmin = nk > 0 ? wave_min64(k0 < k1 ? k0 : k1) : KEY_MAX;
+                    uint64_t smin = head < size ? lds.S[head] : KEY_MAX;
+                    uint64_t cand = uni64(bmin < smin ? bmin : smin);
+                    go = cand != KEY_MAX && !(spill_n > 0 && spill_min < cand) &&
+                         key_dist<INT>(cand) <= threshold(rfull, r, f);
+                    if (go) {
+                        spec_id = (uint32_t)cand;
+                        // lanes 0 and 1 read the two offsets with a vector load,
+                        // which the sort's LDS traffic does not wait for
+                        spec_ofs = a.offsets[spec_id + (lane & 1)];
+                    }
+                }
+                if (na > 0) k0 = wave_sort(k0, pow2_at_least(na));
+                int nl0 = 0, nl1 = 0;
+                if (go) {
+                    // the marks of this expansion are complete before the
+                    // adjacency and the visited bits of the guess are read
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    spec_e0 = readlane64(spec_ofs, 0);
+                    spec_deg = readlane64(spec_ofs, 1) - spec_e0;
+                    nl0 = (int)(spec_deg < WAVE ? spec_deg : WAVE);
+                    nl1 = (int)(spec_deg < 2 * WAVE ? spec_deg - nl0 : WAVE);
+                    spec_nb = lane < nl0 ? (uint32_t)a.nbrs[spec_e0 + lane] : 0u;
+                    spec_nb1 = lane < nl1 ? (uint32_t)a.nbrs[spec_e0 + WAVE + lane] : 0u;
+                }
+                if (na > 0) absorb_pool(k0, na);
+                spec_vis = go && gmode;
+                if (spec_vis) {
+                    spec_bit = false;
+                    spec_bit1 = false;
+                    if (lane < nl0 && (int64_t)spec_nb < a.n_base) {
+                        uint32_t wd = __hip_atomic_load(&gbits[spec_nb >> 5], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+                        spec_bit = (wd >> (spec_nb & 31)) & 1u;
+                    }
+                    if (lane < nl1 && (int64_t)spec_nb1 < a.n_base) {
+                        uint32_t wd = __hip_atomic_load(&gbits[spec_nb1 >> 5], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+                        spec_bit1 = (wd >> (spec_nb1 & 31)) & 1u;
+                    }
+                }
+                if (na > 0) absorb_s(k0, na, true);
+                if (nb2 > 0) {
+                    k1 = wave_sort(k1, pow2_at_least(nb2));
+                    absorb(k1, nb2, true);
+                }
             }
 
             if (a.two_phase && hops == (int)a.probe_hops) {
@@ -545,6 +689,7 @@ search_kernel(SearchKArgs a) {
                     eps = predict_eps(a.pred, fv, MT, qi, lane, lds.misc + 72, &cost);
                     eps = unif(eps);
                     cost = unif(cost);
+                    if (a.pred.mode == ONNG_PRED_CURVE) cost_budget(cost);
                     ep = a.pred.we >= 0.0f ? dynamic_ep(eps, a.pred.e0, a.pred.we)
                                            : (a.ep_pq ? uniu(a.ep_pq[qi]) : a.ep);
                 } else {

@@ -63,6 +63,7 @@ struct SearchKArgs {
     const int32_t *order;
     int32_t max_dc;
     const int32_t *max_dc_pq;
+    float max_dc_factor;
     int32_t has_pred;
     PredArgs pred;
     float *feat_out;

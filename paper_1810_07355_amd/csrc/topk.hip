@@ -6,12 +6,17 @@
 // and |<x', y'>| <= 128^3 keeps int32 exact), f32 x f32 -> f32 (16x16x4)
 // for float data.  Cosine distance on unit vectors is 1 - <x, y>.
 //
-// A block owns BM query rows (16 per wave) and sweeps all base rows in tiles
+// A block owns BM query rows (16 per wave) and sweeps the base rows in tiles
 // of 64 staged in LDS.  Each row keeps its current k best keys sorted in LDS
 // and a buffer of candidates that beat its k-th key; the buffer is sorted and
 // merged into the list when it could overflow on the next tile and at the end.
+// When the query rows alone give too few blocks to fill the chip (e.g. seed
+// selection for one query batch), the base tiles are split among several
+// blocks per row block, each writes its k best keys, and a second kernel
+// merges them (the top k of the union of the parts' top k lists).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "onng_internal.h"
@@ -45,6 +50,9 @@ struct TopkArgs {
     int32_t lds_pitch;        // bytes per staged base row
     int32_t *out_ids;
     void *out_d;
+    int32_t splits;           // blocks sharing one row block's base tiles
+    int32_t tiles_per_split;
+    uint64_t *part;           // splits > 1: [nq][splits][k] keys of each part
 };
 
 // ---- per-row norms (int32 |x-128|^2 for u8, f32 |x|^2 otherwise) ----------
@@ -191,7 +199,9 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
 
     const int ntiles = (int)((a.nb + BN - 1) / BN);
     const int chunks_per_row = a.lds_pitch / 16;
-    for (int t = 0; t < ntiles; t++) {
+    const int split = blockIdx.y;
+    const int t_end = min(ntiles, (split + 1) * a.tiles_per_split);
+    for (int t = split * a.tiles_per_split; t < t_end; t++) {
         const int64_t col0 = (int64_t)t * BN;
         __syncthreads();
         // stage 64 base rows
@@ -294,6 +304,11 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
         flush_row(lr);
         int nl = uni(nlist[lr]);
         const uint64_t *lst = lists + (size_t)lr * a.kcap;
+        if (a.splits > 1) {
+            uint64_t *dst = a.part + ((size_t)grow * a.splits + split) * a.k;
+            for (int i = lane; i < a.k; i += WAVE) dst[i] = i < nl ? lst[i] : KEY_MAX;
+            continue;
+        }
         for (int i = lane; i < a.k; i += WAVE) {
             uint64_t key = i < nl ? lst[i] : KEY_MAX;
             a.out_ids[grow * a.k + i] = i < nl ? (int32_t)(uint32_t)key : -1;
@@ -307,6 +322,54 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
         }
     }
 }
+
+// One wave per query row: the k best of the splits * k part keys.
+template <bool U8>
+__global__ void __launch_bounds__(256) merge_parts_kernel(const uint64_t *part, int64_t nq,
+                                                          int splits, int k, int kcap,
+                                                          int32_t *out_ids, void *out_d) {
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int lane = lane_id();
+    const int wv = threadIdx.x / WAVE;
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / WAVE) + wv;
+    if (row >= nq) return;
+    uint64_t *lst = reinterpret_cast<uint64_t *>(smem) + (size_t)wv * (kcap + WAVE);
+    uint64_t *stage = lst + kcap;
+    const uint64_t *src = part + (size_t)row * splits * k;
+    const int n = splits * k;
+    int nl = 0;
+    for (int c0 = 0; c0 < n; c0 += WAVE) {
+        uint64_t key = c0 + lane < n ? src[c0 + lane] : KEY_MAX;
+        key = wave_sort(key, WAVE);
+        // KEY_MAX pads missing entries; they sort last
+        int nb = __popcll(ballot(key != KEY_MAX));
+        if (nb == 0) continue;
+        nl = min(merge_sorted(lst, 0, nl, key, nb, k, stage, NoSpill()), k);
+    }
+    for (int i = lane; i < k; i += WAVE) {
+        uint64_t key = i < nl ? lst[i] : KEY_MAX;
+        out_ids[row * k + i] = i < nl ? (int32_t)(uint32_t)key : -1;
+        if constexpr (U8)
+            reinterpret_cast<int32_t *>(out_d)[row * k + i] = i < nl ? (int32_t)(key >> 32) : INT32_MAX;
+        else
+            reinterpret_cast<float *>(out_d)[row * k + i] =
+                i < nl ? unord_f32((uint32_t)(key >> 32)) : __builtin_inff();
+    }
+}
+
+// Parts per row block: enough blocks for about four per compute unit, each
+// part keeping at least 8 tiles.
+int topk_splits(int64_t nq, int64_t nb, int bm) {
+    const int64_t row_blocks = (nq + bm - 1) / bm;
+    const int64_t ntiles = (nb + BN - 1) / BN;
+    const int64_t want = 4LL * device_cu_count();
+    if (row_blocks >= want || ntiles < 16) return 1;
+    int64_t sp = (want + row_blocks - 1) / row_blocks;
+    sp = std::min<int64_t>(sp, ntiles / 8);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(sp, 64));
+}
+
+int topk_bm(int32_t k) { return (k + 63) / 64 * 64 <= 128 ? 64 : 32; }
 
 int lds_pitch_for(int dtype, int64_t pitch) {
     // +16 bytes keeps the 16 rows read by one MFMA operand on distinct banks
@@ -328,6 +391,8 @@ size_t topk_ws_size(const onng_vectors *Q, const onng_vectors *B, int64_t n_cand
     c.take<float>(Q->n);
     c.take<float>(nb);
     if (n_cand > 0) c.take<uint8_t>((size_t)nb * B->pitch_bytes);
+    const int sp = topk_splits(Q->n, nb, topk_bm(k));
+    if (sp > 1) c.take<uint64_t>((size_t)Q->n * sp * k);
     return c.size() + 256;
 }
 
@@ -351,6 +416,8 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     Carver c(ws);
     void *qn = c.take<float>(Q->n);
     void *bn = c.take<float>(nb);
+    const int sp = topk_splits(Q->n, nb, topk_bm(k));
+    uint64_t *part = sp > 1 ? c.take<uint64_t>((size_t)Q->n * sp * k) : nullptr;
     const uint8_t *brows = static_cast<const uint8_t *>(B->data);
     if (cand && nb > 0) {
         uint8_t *g = c.take<uint8_t>((size_t)nb * B->pitch_bytes);
@@ -392,7 +459,7 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     a.dim = Q->dim;
     a.k = k;
     a.kcap = (k + 63) / 64 * 64;
-    a.bm = a.kcap <= 128 ? 64 : 32;
+    a.bm = topk_bm(k);
     a.exclude_self = exclude_self;
     a.lds_pitch = lds_pitch_for(Q->dtype, B->pitch_bytes);
     a.out_ids = ids;
@@ -407,9 +474,26 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     else if (Q->metric == ONNG_L2SQ) fn = (const void *)topk_kernel<ONNG_F32, ONNG_L2SQ>;
     else fn = (const void *)topk_kernel<ONNG_F32, ONNG_COSINE>;
     ONNG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    dim3 grid((unsigned)((Q->n + a.bm - 1) / a.bm)), block((unsigned)(a.bm / 16 * 64));
+    const int ntiles = (int)((nb + BN - 1) / BN);
+    a.splits = sp;
+    a.tiles_per_split = (ntiles + sp - 1) / sp;
+    a.part = part;
+    dim3 grid((unsigned)((Q->n + a.bm - 1) / a.bm), (unsigned)sp),
+        block((unsigned)(a.bm / 16 * 64));
     void *args[] = {&a};
     ONNG_HIP(hipLaunchKernel(fn, grid, block, args, lds, st));
+    if (sp > 1) {
+        const int wpb = 4;
+        const size_t mlds = (size_t)wpb * (a.kcap + WAVE) * 8;
+        const void *mf = u8 ? (const void *)merge_parts_kernel<true>
+                            : (const void *)merge_parts_kernel<false>;
+        ONNG_HIP(hipFuncSetAttribute(mf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlds));
+        int64_t nq = Q->n;
+        int splits = sp, kk = k, kcap = a.kcap;
+        void *margs[] = {&part, &nq, &splits, &kk, &kcap, &ids, &dists};
+        ONNG_HIP(hipLaunchKernel(mf, dim3((unsigned)((Q->n + wpb - 1) / wpb)), dim3(wpb * WAVE),
+                                 margs, mlds, st));
+    }
     return ONNG_OK;
 }
 

@@ -22,6 +22,12 @@ __device__ __forceinline__ uint64_t uni64(uint64_t x) {
     return (uint64_t(hi) << 32) | lo;
 }
 __device__ __forceinline__ float unif(float x) { return __int_as_float(uni(__float_as_int(x))); }
+// value of lane l (wave-uniform l)
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
@@ -120,6 +126,18 @@ __device__ __forceinline__ T group_sum_rt(T x, int G) {
     return x;
 }
 
+// Minimum over all 64 lanes (every lane receives it).
+__device__ __forceinline__ uint64_t wave_min64(uint64_t v) {
+    uint64_t o;
+    o = xor_lane64<1>(v); v = o < v ? o : v;
+    o = xor_lane64<2>(v); v = o < v ? o : v;
+    o = xor_lane64<4>(v); v = o < v ? o : v;
+    o = xor_lane64<8>(v); v = o < v ? o : v;
+    o = xor_lane64<16>(v); v = o < v ? o : v;
+    o = xor_lane64<32>(v); v = o < v ? o : v;
+    return v;
+}
+
 // One compare-exchange step of the bitonic network: block size K, distance J.
 template <int K, int J>
 __device__ __forceinline__ uint64_t bitonic_step(uint64_t key, int lane) {
@@ -188,8 +206,11 @@ __device__ __forceinline__ int merge_sorted(PA A, int base, int na, uint64_t bke
     // destination of my batch key
     int bpos = 0;
     if (lane < nb) bpos = lane + lower_bound_u64(A + base, na, bkey);
-    // move A's elements, top chunk first
+    // move A's elements, top chunk first; a chunk whose largest element is
+    // below the smallest batch key stays in place, and so do all below it
+    const uint64_t bmin = nb > 0 ? stage[0] : ~0ull;
     for (int c0 = ((na - 1) >> 6) << 6; c0 >= 0; c0 -= WAVE) {
+        if (A[base + min(c0 + WAVE, na) - 1] < bmin) break;
         int i = c0 + lane;
         uint64_t a = 0;
         int apos = 0;

@@ -272,6 +272,34 @@ def test_search_mixed_k_eps_ep_per_query():
     assert np.array_equal(host(r.hops), ref["hops"])
 
 
+def test_search_padded_rows():
+    """Rows padded past the 16-byte pitch (to whole cache lines) give the
+    same results: u8 bit-exact against the oracle, f16 identical to the
+    unpadded rows."""
+    P = c1_problem()
+    po, pn, _ = P["pa"]
+    A, Lb = api(), L()
+    say("search with padded rows")
+    Bp = A.Vectors.from_tensor(to_dev(P["x"]), Lb.L2SQ, pitch=256)
+    assert Bp.pitch == 256
+    r = A.search(Bp, gpu_graph(po, pn), gpu_vectors(P["q"], orc.L2SQ), to_dev(P["seeds"]),
+                 k=10, eps=0.1)
+    ref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, 0.1)
+    torch.cuda.synchronize()
+    _assert_exact(r, ref, 10)
+    F = _float_problem("f32cos")
+    G = gpu_graph(F["off"], F["nb"])
+    Q = gpu_vectors(F["q"], F["metric"])
+    outs = []
+    for pitch in (None, 256):
+        lp = A.encode(to_dev(F["x"]), Lb.F16, Lb.COSINE, pitch=pitch)
+        rr = A.search(lp, G, Q, to_dev(F["seeds"]), k=10, eps=0.1)
+        torch.cuda.synchronize()
+        outs.append((host(rr.ids), host(rr.dists), host(rr.dc)))
+    for a_, b_ in zip(*outs):
+        assert np.array_equal(a_, b_)
+
+
 @pytest.mark.parametrize("per_query,shape", [(False, None), (True, None),
                                                (True, dict(s_capacity=64, visited_log2=8))])
 def test_search_dc_budget(per_query, shape):
@@ -600,6 +628,18 @@ def test_scheduled_learned_search():
     ref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, eps_used, ep_used)
     assert np.array_equal(host(req.ids), ref["ids"])
     assert np.array_equal(host(req.dc), ref["dc"])
+    # a budget relative to the predicted cost: the oracle with the budget
+    # max(64, int32(factor * cost)) in fp32 gives the same result
+    for factor in (0.5, 1.0):
+        say("cost-relative budget", factor)
+        rb = A.search(B, G, Q, S, k=10, range_from=ls.pre.stats, max_dc_factor=factor)
+        torch.cuda.synchronize()
+        bud = np.maximum(64, (np.float32(factor) * cost.astype(np.float32)).astype(np.int64))
+        bud = np.minimum(bud, 2 ** 31 - 1).astype(np.int32)
+        refb = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, eps_used, ep_used, max_dc=bud)
+        assert np.array_equal(host(rb.ids), refb["ids"])
+        assert np.array_equal(host(rb.dc), refb["dc"])
+        assert np.array_equal(host(rb.hops), refb["hops"])
     # unordered run of the same ranges gives the same result
     plain = A.search(B, G, Q, S, k=10, range_from=ls.pre.stats)
     torch.cuda.synchronize()
