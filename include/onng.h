@@ -58,8 +58,11 @@ typedef enum { ONNG_L2SQ = 0, ONNG_COSINE = 1 } onng_metric;
 
 /* A set of vectors: n rows of `dim` components, `pitch_bytes` apart (a
  * multiple of 16 and at least dim * element size; bytes past the last
- * component must be zero).  `scale` is the per-row f32 scale of FP8 rows and
- * NULL otherwise.  The objects of the paper's Section 2 problem statement. */
+ * component must be zero).  `scale` is the per-row f32 scale of FP8 rows, or
+ * NULL for FP8 rows that carry their scale as an f32 in their last 4 bytes
+ * (then pitch_bytes >= 16 * ceil(dim / 16) + 16, so a 100-component row fits
+ * one 128-byte line); NULL for the other types.  The objects of the paper's
+ * Section 2 problem statement. */
 typedef struct {
     const void *data;
     const float *scale;
@@ -309,7 +312,8 @@ size_t onng_order_by_cost_workspace_size(int64_t n);
 /* f32 rows [n][dim] (row stride dim) -> rows of `dtype`, dst_pitch bytes
  * apart, padding zero.  Round-to-nearest-even; FP8 saturates at +-448 after
  * dividing by the per-row scale maxabs/448 (scale 1 for an all-zero row),
- * written to `scale` [n]. */
+ * written to `scale` [n], or, when scale is NULL, into the last 4 bytes of
+ * each row (dst_pitch >= 16 * ceil(dim / 16) + 16). */
 onng_status onng_encode(const float *src, int64_t n, int32_t dim, int32_t dtype, void *dst,
                         int64_t dst_pitch, float *scale, void *stream);
 

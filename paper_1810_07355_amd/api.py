@@ -352,13 +352,24 @@ def search(base, graph, queries, seeds, **kw) -> SearchRequest:
 
 # ------------------------------------------------------ codecs and rerank --
 
-def encode(x: torch.Tensor, dtype: int, metric: int, pitch: int | None = None) -> Vectors:
-    """f32 rows -> stored rows of `dtype` (Vectors with uint8 storage)."""
+def fp8_inrow_pitch(dim: int) -> int:
+    """Smallest pitch of FP8 rows that carry their scale in the last 4 bytes."""
+    return (dim + 15) // 16 * 16 + 16
+
+
+def encode(x: torch.Tensor, dtype: int, metric: int, pitch: int | None = None,
+           scale_in_row: bool = False) -> Vectors:
+    """f32 rows -> stored rows of `dtype` (Vectors with uint8 storage).
+    FP8 rows keep their per-row scale in a separate array, or with
+    scale_in_row in the last 4 bytes of the row (one cache line per row for
+    up to 112 components at a 128-byte pitch)."""
     x = x.contiguous().to(torch.float32)
     n, dim = x.shape
-    pitch = pitch or row_pitch(dim, dtype)
+    inrow = scale_in_row and dtype == L.FP8_E4M3
+    pitch = pitch or (fp8_inrow_pitch(dim) if inrow else row_pitch(dim, dtype))
     out = torch.empty((n, pitch), dtype=torch.uint8, device=x.device)
-    scale = torch.empty(n, dtype=torch.float32, device=x.device) if dtype == L.FP8_E4M3 else None
+    scale = (torch.empty(n, dtype=torch.float32, device=x.device)
+             if dtype == L.FP8_E4M3 and not inrow else None)
     L.call("onng_encode", x.data_ptr(), n, dim, dtype, out.data_ptr(), pitch, _ptr(scale),
            _stream())
     return Vectors(out, dtype, metric, dim, scale)

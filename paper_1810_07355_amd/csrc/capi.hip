@@ -90,8 +90,8 @@ onng_status check_vectors(const onng_vectors *v, const char *what) {
         set_error(w + ": data must be 16-byte aligned");
         return ONNG_ERR_INVALID_ARG;
     }
-    if (v->dtype == ONNG_FP8_E4M3 && !v->scale && v->n > 0) {
-        set_error(w + ": FP8 rows need a scale array");
+    if (v->dtype == ONNG_FP8_E4M3 && !v->scale && v->pitch_bytes < fp8_inrow_pitch(v->dim)) {
+        set_error(w + ": FP8 rows need a scale array or room for the scale in the row");
         return ONNG_ERR_INVALID_ARG;
     }
     if (v->dtype == ONNG_U8 && v->metric != ONNG_L2SQ) {
@@ -303,6 +303,7 @@ static onng_status run_search(const onng_vectors *base, const onng_graph *g,
     a.spill = c.take<uint64_t>((size_t)P.slots * 2 * P.spill_cap);
     a.base = static_cast<const uint8_t *>(base->data);
     a.base_scale = base->scale;
+    a.scale_in_row = base->dtype == ONNG_FP8_E4M3 && !base->scale;
     a.base_pitch = base->pitch_bytes;
     a.n_base = base->n;
     a.dim = base->dim;
@@ -665,7 +666,8 @@ onng_status onng_encode(const float *src, int64_t n, int32_t dim, int32_t dtype,
     ONNG_CHECK_ARG(n == 0 || (src && dst), "null pointer");
     ONNG_CHECK_ARG(dtype >= ONNG_F32 && dtype <= ONNG_FP8_E4M3, "dtype must be a float format");
     ONNG_CHECK_ARG(dst_pitch >= (int64_t)dim * elem_bytes(dtype), "dst_pitch too small");
-    ONNG_CHECK_ARG(dtype != ONNG_FP8_E4M3 || scale, "FP8 needs a scale array");
+    ONNG_CHECK_ARG(dtype != ONNG_FP8_E4M3 || scale || dst_pitch >= fp8_inrow_pitch(dim),
+                   "FP8 needs a scale array or room for the scale in the row");
     return encode_launch(src, n, dim, dtype, dst, dst_pitch, scale, as_stream(stream));
 }
 

@@ -56,10 +56,14 @@ __global__ void encode_kernel(const float *src, int64_t n, int dim, int dtype, u
         for (int c = lane; c < dim; c += 64) mx = fmaxf(mx, fabsf(x[c]));
         for (int m = 32; m >= 1; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
         s = mx > 0.0f ? __fdiv_rn(mx, 448.0f) : 1.0f;
-        if (lane == 0) scale[row] = s;
+        if (lane == 0) {
+            if (scale) scale[row] = s;
+            else *reinterpret_cast<float *>(out + pitch - 4) = s;   // in the row's tail
+        }
     }
     int esz = dtype == ONNG_F32 ? 4 : (dtype == ONNG_F16 || dtype == ONNG_BF16) ? 2 : 1;
-    for (int64_t c = lane; c * esz < pitch; c += 64) {
+    const int64_t fill = dtype == ONNG_FP8_E4M3 && !scale ? pitch - 4 : pitch;
+    for (int64_t c = lane; c * esz < fill; c += 64) {
         if (c >= dim) {
             for (int b = 0; b < esz; b++) out[c * esz + b] = 0;
             continue;

@@ -37,6 +37,10 @@ const char *get_error();
 
 // ------------------------------------------------------------- dtypes ----
 
+// smallest pitch of FP8 rows that keep their scale in the last 4 bytes,
+// past every 16-byte piece that holds components
+inline int64_t fp8_inrow_pitch(int32_t dim) { return ((int64_t)dim + 15) / 16 * 16 + 16; }
+
 inline int elem_bytes(int dtype) {
     switch (dtype) {
     case ONNG_U8: return 1;

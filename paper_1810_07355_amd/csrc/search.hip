@@ -356,7 +356,15 @@ search_kernel(SearchKArgs a) {
                     const uint8_t *rp = a.base + (size_t)rid[up] * a.base_pitch;
                     qr.fetch(rp, p, L, row < u ? a.n16 : 0, x[up]);
                     sc[up] = 1.0f;
-                    if constexpr (DT == ONNG_FP8_E4M3) sc[up] = row < u ? a.base_scale[rid[up]] : 1.0f;
+                    if constexpr (DT == ONNG_FP8_E4M3) {
+                        // the row's scale (in its own line when the rows carry
+                        // it); the lanes of a row read one address
+                        float v = 1.0f;
+                        if (row < u)
+                            v = a.scale_in_row ? *reinterpret_cast<const float *>(rp + a.base_pitch - 4)
+                                               : a.base_scale[rid[up]];
+                        sc[up] = v;
+                    }
                 }
 #pragma unroll
                 for (int up = 0; up < UP; up++) {

@@ -33,6 +33,7 @@ struct SearchKArgs {
     // stored rows
     const uint8_t *base;
     const float *base_scale;
+    int32_t scale_in_row;       // FP8 rows keep their scale in the last 4 bytes
     int64_t base_pitch;
     int64_t n_base;
     int32_t dim;

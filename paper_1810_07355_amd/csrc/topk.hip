@@ -461,7 +461,8 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     a.kcap = (k + 63) / 64 * 64;
     a.bm = topk_bm(k);
     a.exclude_self = exclude_self;
-    a.lds_pitch = lds_pitch_for(Q->dtype, B->pitch_bytes);
+    // the staged tile holds a row's components only, not any padding past them
+    a.lds_pitch = lds_pitch_for(Q->dtype, ((int64_t)B->dim * elem_bytes(B->dtype) + 15) / 16 * 16);
     a.out_ids = ids;
     a.out_d = dists;
     size_t lds = topk_lds_bytes(a.bm, a.kcap, a.lds_pitch);

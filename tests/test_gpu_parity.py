@@ -272,6 +272,32 @@ def test_search_mixed_k_eps_ep_per_query():
     assert np.array_equal(host(r.hops), ref["hops"])
 
 
+def test_fp8_scale_in_row():
+    """FP8 rows that carry their scale in the last 4 bytes: the same codes
+    and scale as the separate array, and the same search results."""
+    F = _float_problem("f32l2")
+    A, Lb = api(), L()
+    say("fp8 with the scale in the row")
+    x = to_dev(F["x"])
+    sep = A.encode(x, Lb.FP8_E4M3, Lb.L2SQ)
+    inr = A.encode(x, Lb.FP8_E4M3, Lb.L2SQ, scale_in_row=True)
+    dim = F["x"].shape[1]
+    assert inr.scale is None and inr.pitch == A.fp8_inrow_pitch(dim)
+    cs, ci = host(sep.data), host(inr.data)
+    assert np.array_equal(ci[:, :dim], cs[:, :dim])
+    assert np.all(ci[:, dim:inr.pitch - 4] == 0)
+    assert np.array_equal(ci[:, inr.pitch - 4:].copy().view(np.float32)[:, 0], host(sep.scale))
+    G = gpu_graph(F["off"], F["nb"])
+    Q = gpu_vectors(F["q"], F["metric"])
+    outs = []
+    for rows in (sep, inr):
+        r = A.search(rows, G, Q, to_dev(F["seeds"]), k=10, eps=0.1)
+        torch.cuda.synchronize()
+        outs.append((host(r.ids), host(r.dists), host(r.dc)))
+    for a_, b_ in zip(*outs):
+        assert np.array_equal(a_, b_)
+
+
 def test_search_padded_rows():
     """Rows padded past the 16-byte pitch (to whole cache lines) give the
     same results: u8 bit-exact against the oracle, f16 identical to the
@@ -298,6 +324,13 @@ def test_search_padded_rows():
         outs.append((host(rr.ids), host(rr.dists), host(rr.dc)))
     for a_, b_ in zip(*outs):
         assert np.array_equal(a_, b_)
+    # the top-k (kNN build, ground truth, seeds) on padded rows is unchanged
+    Bf = A.Vectors.from_tensor(to_dev(F["x"]), Lb.COSINE)
+    Bfp = A.Vectors.from_tensor(to_dev(F["x"]), Lb.COSINE, pitch=512)
+    for k in (8, 74):
+        i0, d0 = A.topk(Q, Bf, k)
+        i1, d1 = A.topk(Q, Bfp, k)
+        assert np.array_equal(host(i0), host(i1)) and np.array_equal(host(d0), host(d1))
 
 
 @pytest.mark.parametrize("per_query,shape", [(False, None), (True, None),
