@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times and exit (the plain copy "
                          "whose counters calibrate FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--no-reorder", action="store_true",
+                    help="keep the generated row order (default: group rows by nearest pivot)")
     ap.add_argument("--row-align", type=int, default=128,
                     help="pad searched rows to a multiple of this many bytes (cache lines)")
     ap.add_argument("--inflight", type=int, default=2,
@@ -161,6 +163,23 @@ def main():
         log(f"{name}: {build[name]} s")
         return out
 
+    perm = None
+    if not args.no_reorder:
+        # rows grouped by nearest pivot: a query's visited rows and bits sit
+        # in fewer lines; outputs are mapped back to the generated ids
+        def reorder():
+            p_ = A.locality_order(base, piv)
+            return p_, A.gather_rows(xt, p_)
+        perm, xt = timed("locality_order_s", reorder)
+        inv = torch.empty_like(perm)
+        inv[perm.long()] = torch.arange(perm.numel(), dtype=torch.int32, device=dev)
+        piv = inv[piv.long()].sort().values.contiguous()
+        base = A.Vectors.from_tensor(xt, metric)
+    idm = dict(id_map=perm) if perm is not None else {}
+
+    def to_orig(ids_t):
+        return perm[ids_t.long()] if perm is not None else ids_t
+
     ids, d = timed("knn_s", lambda: A.build_knn(base, cfg.knn_k))
     sa = timed("adjust_degree_s", lambda: A.adjust_degree(ids, d, base.dtype, metric, cfg.e_o,
                                                           cfg.e_i))
@@ -175,7 +194,7 @@ def main():
     del sa
     seeds, _ = A.topk(queries, base, NS, cand=piv)
     gt_ids, _ = timed("ground_truth_s", lambda: A.ground_truth(queries, base, K))
-    gt = gt_ids.cpu().numpy()
+    gt = to_orig(gt_ids).cpu().numpy()
 
     # ------------------------------------------- operating points (recall) --
     def time_req(req, reps=3):
@@ -229,7 +248,7 @@ def main():
         return measure(make, hi, name)
 
     curve_eps = [0.0, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3]
-    make_plain = lambda e: A.SearchRequest(base, graph, queries, seeds, k=K, eps=e,
+    make_plain = lambda e: A.SearchRequest(base, graph, queries, seeds, k=K, eps=e, **idm,
                                            ep=LR.dynamic_ep(e))
     curve = {"plain": [measure(make_plain, e, "plain") for e in curve_eps]}
     result = {"plain": {str(t): bisect(make_plain, t, 0.0, 1.0, "plain") for t in (0.95, 0.99)}}
@@ -246,7 +265,7 @@ def main():
         else:
             lp_rows = A.encode(xt, lp_dt, metric,
                                pitch=A.row_pitch(cfg.dim, lp_dt, max(16, args.row_align)))
-        make_lp = lambda e: A.SearchRequest(lp_rows, graph, queries, seeds, k=K, eps=e,
+        make_lp = lambda e: A.SearchRequest(lp_rows, graph, queries, seeds, k=K, eps=e, **idm,
                                             ep=LR.dynamic_ep(e), rerank_base=base, pool_factor=4)
         curve["lp"] = [measure(make_lp, e, args.lp + "+rerank") for e in curve_eps]
         result["lp"] = {str(t): bisect(make_lp, t, 0.0, 1.0, args.lp + "+rerank")
@@ -269,12 +288,12 @@ def main():
     tq = A.Vectors.from_tensor(torch.from_numpy(tq_np).to(dev), metric)
     tseeds, _ = A.topk(tq, base, NS, cand=piv)
     tgt_ids, _ = A.ground_truth(tq, base, K)
-    tgt_np = tgt_ids.cpu().numpy()
+    tgt_np = to_orig(tgt_ids).cpu().numpy()
 
     def label_sweep(vq, vseeds, vgt):
         feats, recs, dcs = None, [], []
         for i, eps in enumerate(grid):
-            req = A.SearchRequest(search_rows, graph, vq, vseeds, k=K, eps=eps,
+            req = A.SearchRequest(search_rows, graph, vq, vseeds, k=K, eps=eps, **idm,
                                   ep=LR.dynamic_ep(eps), two_phase=True, ep_first=EPF,
                                   probe_hops=PROBE, want_features=(i == 0), **rr)
             req.run()
@@ -334,7 +353,7 @@ def main():
     def make_learned_b(tgt):
         def make(knob, b, fac=0.0):
             pred = learned_pred(tgt, knob)
-            req = A.LearnedSearch(search_rows, graph, queries, seeds, pred, ep_first=EPF,
+            req = A.LearnedSearch(search_rows, graph, queries, seeds, pred, ep_first=EPF, **idm,
                                   probe_hops=PROBE, k=K, max_dc=b, max_dc_factor=fac, **rr)
             req._pred = pred
             return req
@@ -352,13 +371,13 @@ def main():
                 for t in (0.95, 0.99)}
     # the same budgets without the learned range, for comparison
     if lp_rows is not None:
-        make_lp_b = lambda e, b, fac=0.0: A.SearchRequest(lp_rows, graph, queries, seeds, k=K, eps=e,
+        make_lp_b = lambda e, b, fac=0.0: A.SearchRequest(lp_rows, graph, queries, seeds, k=K, eps=e, **idm,
                                                  ep=LR.dynamic_ep(e), rerank_base=base,
                                                  pool_factor=4, max_dc=b)
         result["lp_budget"] = {str(t): best_over_budgets(make_lp_b, t, 0.0, 1.0,
                                                          args.lp + "+rerank")
                                for t in (0.95, 0.99)}
-    make_plain_b = lambda e, b, fac=0.0: A.SearchRequest(base, graph, queries, seeds, k=K, eps=e,
+    make_plain_b = lambda e, b, fac=0.0: A.SearchRequest(base, graph, queries, seeds, k=K, eps=e, **idm,
                                                 ep=LR.dynamic_ep(e), max_dc=b)
     result["plain_budget"] = {str(t): best_over_budgets(make_plain_b, t, 0.0, 1.0, "plain")
                               for t in (0.95, 0.99)}
@@ -372,7 +391,7 @@ def main():
     pred95 = learned_pred(0.95, knobs[0.95])
     NF = max(1, args.inflight)
     # one pipeline (own outputs and workspace) and one stream per batch in flight
-    pipes = [A.Pipeline(search_rows, graph, queries, piv, NS, k=K, eps=0.0, ep=L.EP_INF,
+    pipes = [A.Pipeline(search_rows, graph, queries, piv, NS, k=K, eps=0.0, ep=L.EP_INF, **idm,
                         two_phase=True, ep_first=EPF, probe_hops=PROBE, predictor=pred95,
                         max_dc=budgets[0.95], max_dc_factor=bfactors[0.95], **rr)
              for _ in range(NF)]
@@ -380,7 +399,7 @@ def main():
     plain95 = result["plain"]["0.95"]
     pipes_plain = []
     if plain95 is not None:
-        pipes_plain = [A.Pipeline(base, graph, queries, piv, NS, k=K, eps=plain95["knob"],
+        pipes_plain = [A.Pipeline(base, graph, queries, piv, NS, k=K, eps=plain95["knob"], **idm,
                                   ep=LR.dynamic_ep(plain95["knob"])) for _ in range(NF)]
     streams = [torch.cuda.Stream(device=dev) for _ in range(NF)]
 
@@ -448,14 +467,14 @@ def main():
     if learned_pts.get("0.99") is not None:
         pred99 = learned_pred(0.99, knobs[0.99])
         learned99_pipe = pipe_qps([A.Pipeline(
-            search_rows, graph, queries, piv, NS, k=K, eps=0.0, ep=L.EP_INF, two_phase=True,
+            search_rows, graph, queries, piv, NS, k=K, **idm, eps=0.0, ep=L.EP_INF, two_phase=True,
             ep_first=EPF, probe_hops=PROBE, predictor=pred99, max_dc=budgets[0.99],
             max_dc_factor=bfactors[0.99], **rr) for _ in range(NF)])
         log(f"learned pipeline at 0.99, {NF} in flight: {learned99_pipe[0]:.0f} q/s, "
             f"recall {learned99_pipe[1]:.4f}")
     plain99 = result["plain"]["0.99"]
     if plain99 is not None:
-        plain99_pipe = pipe_qps([A.Pipeline(base, graph, queries, piv, NS, k=K,
+        plain99_pipe = pipe_qps([A.Pipeline(base, graph, queries, piv, NS, k=K, **idm,
                                             eps=plain99["knob"], ep=LR.dynamic_ep(plain99["knob"]))
                                  for _ in range(NF)])
         log(f"plain f32 pipeline at 0.99, {NF} in flight: {plain99_pipe[0]:.0f} q/s")
@@ -493,7 +512,8 @@ def main():
         off = graph.offsets.cpu().numpy()
         nb = graph.nbrs.cpu().numpy()
         sd = seeds.cpu().numpy()
-        bv = orc.Vectors.from_array(x, orc.COS if metric == L.COSINE else orc.L2SQ)
+        x_or = xt.cpu().numpy() if perm is not None else x     # rows in the graph's order
+        bv = orc.Vectors.from_array(x_or, orc.COS if metric == L.COSINE else orc.L2SQ)
         qv_all = q
         eps0 = plain95["knob"]
         ep0 = LR.dynamic_ep(eps0)

@@ -259,6 +259,9 @@ typedef struct {
      * the product taken in fp32, so that a query far costlier than predicted
      * is cut short. */
     float max_dc_factor;
+    /* Output ids are id_map[id] when non-NULL (e.g. the permutation of
+     * onng_locality_order, to report original row ids). */
+    const int32_t *id_map;
 } onng_search_params;
 
 /* Per-query statistics written by onng_search. */
@@ -304,6 +307,24 @@ size_t onng_search_workspace_size(const onng_vectors *base, int64_t n_queries,
 onng_status onng_order_by_cost(const onng_query_stats *stats, int64_t n, int32_t *order, void *ws,
                                size_t ws_bytes, void *stream);
 size_t onng_order_by_cost_workspace_size(int64_t n);
+
+/* Locality order of a base (not part of the paper; a memory layout for the
+ * search): perm[0..n) lists the rows grouped by their nearest pivot (pivot
+ * ids ascending, rows ascending within a group), so that objects close in
+ * space get close positions.  Searching rows gathered in this order touches
+ * fewer cache lines and fewer bits of the visited set per query.  pivots:
+ * [n_pivots] row ids of `base` (device).  ws: onng_locality_order_workspace_size.
+ * A graph built on the reordered rows has reordered ids; search outputs are
+ * mapped back with onng_search_params.id_map = perm. */
+onng_status onng_locality_order(const onng_vectors *base, const int32_t *pivots,
+                                int64_t n_pivots, int32_t *perm, void *ws, size_t ws_bytes,
+                                void *stream);
+size_t onng_locality_order_workspace_size(const onng_vectors *base, int64_t n_pivots);
+
+/* dst row i = src row ids[i], for n rows of pitch_bytes (a multiple of 16;
+ * any type; device).  Every ids[i] must be a row of src. */
+onng_status onng_gather_rows(const void *src, int64_t pitch_bytes, const int32_t *ids, int64_t n,
+                             void *dst, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Low-precision storage and exact rerank (not part of the paper)           */

@@ -53,7 +53,8 @@ class SearchParams_t(C.Structure):
                 ("predictor", P), ("features_out", P), ("rerank_base", P),
                 ("pool_factor", C.c_int32), ("launch", P), ("probe_hops", C.c_uint32),
                 ("predict_only", C.c_int32), ("range_from", P), ("order", P),
-                ("max_dc", C.c_int32), ("max_dc_per_query", P), ("max_dc_factor", C.c_float)]
+                ("max_dc", C.c_int32), ("max_dc_per_query", P), ("max_dc_factor", C.c_float),
+                ("id_map", P)]
 
 
 # exported symbols and their prototypes (must match include/onng.h)
@@ -71,6 +72,9 @@ PROTOS = {
     "onng_search_workspace_size": (C.c_size_t, [P, C.c_int64, P]),
     "onng_order_by_cost": (C.c_int, [P, C.c_int64, P, P, C.c_size_t, P]),
     "onng_order_by_cost_workspace_size": (C.c_size_t, [C.c_int64]),
+    "onng_locality_order": (C.c_int, [P, P, C.c_int64, P, P, C.c_size_t, P]),
+    "onng_locality_order_workspace_size": (C.c_size_t, [P, C.c_int64]),
+    "onng_gather_rows": (C.c_int, [P, C.c_int64, P, C.c_int64, P, P]),
     "onng_encode": (C.c_int, [P, C.c_int64, C.c_int32, C.c_int32, P, C.c_int64, P, P]),
     "onng_rerank": (C.c_int, [P, P, P, C.c_int32, C.c_int32, C.c_int32, P, P, P]),
     "onng_mlp_forward": (C.c_int, [P, C.c_int32, C.c_int32, P, P, C.c_int32, P, P, C.c_int32,

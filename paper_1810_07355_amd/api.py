@@ -199,7 +199,8 @@ class SearchRequest:
                  predictor: Predictor | None = None, want_features=False,
                  rerank_base: Vectors | None = None, pool_factor=4, launch=None, probe_hops=1,
                  predict_only=False, range_from: torch.Tensor | None = None,
-                 order: torch.Tensor | None = None, max_dc=0, max_dc_factor=0.0):
+                 order: torch.Tensor | None = None, max_dc=0, max_dc_factor=0.0,
+                 id_map: torch.Tensor | None = None):
         dev = queries.data.device
         nq = queries.n
         self.base, self.graph, self.queries = base, graph, queries
@@ -238,8 +239,8 @@ class SearchRequest:
             C.cast(rerank_base.ref, C.c_void_p) if rerank_base else None,
             int(pool_factor), C.cast(C.byref(launch), C.c_void_p) if launch is not None else None,
             int(probe_hops), int(predict_only), _ptr(range_from), _ptr(order), int(max_dc),
-            _ptr(mdq), float(max_dc_factor))
-        self._keep += [range_from, order]
+            _ptr(mdq), float(max_dc_factor), _ptr(id_map))
+        self._keep += [range_from, order, id_map]
         self.gs = graph.struct()
         out_dt = torch.float32 if rerank_base is not None else base.dist_dtype
         self.ids = torch.empty((nq, self.k_stride), dtype=torch.int32, device=dev)
@@ -303,6 +304,28 @@ class SearchRequest:
     def us(self):
         """Per-query device wall time in microseconds."""
         return self.stats[:, 7].view(torch.float32)
+
+
+def locality_order(base: Vectors, pivots: torch.Tensor) -> torch.Tensor:
+    """Permutation grouping the rows by nearest pivot (see onng_locality_order)."""
+    pivots = pivots.contiguous().to(torch.int32)
+    perm = torch.empty(base.n, dtype=torch.int32, device=base.data.device)
+    n_ws = L.load().onng_locality_order_workspace_size(base.ref, pivots.numel())
+    ws = _workspace(n_ws, base.data.device)
+    L.call("onng_locality_order", base.ref, pivots.data_ptr(), pivots.numel(), perm.data_ptr(),
+           ws.data_ptr(), ws.numel(), _stream())
+    return perm
+
+
+def gather_rows(x: torch.Tensor, ids: torch.Tensor) -> torch.Tensor:
+    """Rows of a device tensor [n, ...] in the order `ids` (library kernel)."""
+    x = x.contiguous()
+    ids = ids.contiguous().to(torch.int32)
+    out = torch.empty((ids.numel(),) + tuple(x.shape[1:]), dtype=x.dtype, device=x.device)
+    pitch = x[0].numel() * x.element_size() if x.shape[0] else 16
+    L.call("onng_gather_rows", x.data_ptr(), pitch, ids.data_ptr(), ids.numel(),
+           out.data_ptr(), _stream())
+    return out
 
 
 def order_by_cost(stats: torch.Tensor, order: torch.Tensor | None = None) -> torch.Tensor:

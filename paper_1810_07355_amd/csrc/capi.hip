@@ -332,6 +332,7 @@ static onng_status run_search(const onng_vectors *base, const onng_graph *g,
     a.max_dc = p->max_dc;
     a.max_dc_pq = p->max_dc_per_query;
     a.max_dc_factor = p->max_dc_factor;
+    a.id_map = p->id_map;
     a.has_pred = p->predictor != nullptr;
     if (p->predictor) {
         const onng_predictor *pr = p->predictor;
@@ -453,6 +454,45 @@ static onng_status order_launch(const onng_query_stats *st, int64_t n, int32_t *
                                                           (int)n, 0, 32, s));
     ONNG_HIP(hipGetLastError());
     return ONNG_OK;
+}
+
+// ------------------------------------------------------ locality order ---
+
+__global__ void nearest_key_kernel(const int32_t *nn, int64_t n, uint32_t *key, int32_t *idx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    key[i] = (uint32_t)nn[i];
+    idx[i] = (int32_t)i;
+}
+
+__global__ void gather_bytes_kernel(const uint8_t *src, int64_t pitch, const int32_t *ids,
+                                    int64_t n, uint8_t *dst) {
+    int64_t i = blockIdx.x;
+    if (i >= n) return;
+    const uint8_t *s = src + (int64_t)ids[i] * pitch;
+    uint8_t *d = dst + i * pitch;
+    for (int64_t c = threadIdx.x * 16; c < pitch; c += blockDim.x * 16)
+        *reinterpret_cast<uint4 *>(d + c) = *reinterpret_cast<const uint4 *>(s + c);
+}
+
+static size_t locality_sort_bytes(int64_t n) {
+    size_t bytes = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t *)nullptr,
+                                             (uint32_t *)nullptr, (const int32_t *)nullptr,
+                                             (int32_t *)nullptr, (int)n);
+    return bytes;
+}
+
+static size_t locality_ws(const onng_vectors *base, int64_t n_pivots) {
+    Carver c(nullptr);
+    c.take<int32_t>(base->n);                 // nearest pivot
+    c.take<float>(base->n);                   // its distance (unused)
+    c.take<uint32_t>(base->n);
+    c.take<uint32_t>(base->n);
+    c.take<int32_t>(base->n);
+    c.take<char>(locality_sort_bytes(base->n));
+    c.take<char>(topk_ws_size(base, base, n_pivots, 1));
+    return c.size() + 256;
 }
 
 }  // namespace onng
@@ -658,6 +698,59 @@ onng_status onng_autotune_search(const onng_vectors *base, const onng_graph *gra
 }
 
 // ------------------------------------------------------ codecs, rerank ----
+
+size_t onng_locality_order_workspace_size(const onng_vectors *base, int64_t n_pivots) {
+    if (!base || n_pivots < 1) return 0;
+    return locality_ws(base, n_pivots);
+}
+
+onng_status onng_locality_order(const onng_vectors *base, const int32_t *pivots,
+                                int64_t n_pivots, int32_t *perm, void *ws, size_t ws_bytes,
+                                void *stream) {
+    set_error("");
+    ONNG_TRY(check_vectors(base, "base"));
+    ONNG_CHECK_ARG(pivots && perm && n_pivots >= 1, "bad arguments");
+    ONNG_CHECK_ARG(base->dtype == ONNG_U8 || base->dtype == ONNG_F32, "base must be u8 or f32");
+    ONNG_CHECK_ARG(base->n < (int64_t)INT32_MAX, "too many rows");
+    if (!ws || ws_bytes < locality_ws(base, n_pivots)) {
+        set_error("onng_locality_order: workspace too small");
+        return ONNG_ERR_WORKSPACE;
+    }
+    const int64_t n = base->n;
+    if (n == 0) return ONNG_OK;
+    hipStream_t st = as_stream(stream);
+    Carver c(ws);
+    int32_t *nn = c.take<int32_t>(n);
+    float *nd = c.take<float>(n);
+    uint32_t *key = c.take<uint32_t>(n);
+    uint32_t *key_sorted = c.take<uint32_t>(n);
+    int32_t *idx = c.take<int32_t>(n);
+    size_t tb = locality_sort_bytes(n);
+    void *tmp = c.take<char>(tb);
+    size_t tkb = topk_ws_size(base, base, n_pivots, 1);
+    void *tk = c.take<char>(tkb);
+    ONNG_TRY(launch_topk(base, base, pivots, n_pivots, 1, 0, nn, nd, tk, tkb, st));
+    hipLaunchKernelGGL(nearest_key_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, nn,
+                       n, key, idx);
+    // radix sort is stable: rows stay ascending within a pivot's group
+    ONNG_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, key, key_sorted, idx, perm, (int)n, 0,
+                                                32, st));
+    ONNG_HIP(hipGetLastError());
+    return ONNG_OK;
+}
+
+onng_status onng_gather_rows(const void *src, int64_t pitch_bytes, const int32_t *ids, int64_t n,
+                             void *dst, void *stream) {
+    set_error("");
+    ONNG_CHECK_ARG(n >= 0 && pitch_bytes > 0 && pitch_bytes % 16 == 0, "bad sizes");
+    ONNG_CHECK_ARG(n == 0 || (src && ids && dst), "null pointer");
+    if (n == 0) return ONNG_OK;
+    hipLaunchKernelGGL(gather_bytes_kernel, dim3((unsigned)n), dim3(64), 0, as_stream(stream),
+                       static_cast<const uint8_t *>(src), pitch_bytes, ids, n,
+                       static_cast<uint8_t *>(dst));
+    ONNG_HIP(hipGetLastError());
+    return ONNG_OK;
+}
 
 onng_status onng_encode(const float *src, int64_t n, int32_t dim, int32_t dtype, void *dst,
                         int64_t dst_pitch, float *scale, void *stream) {

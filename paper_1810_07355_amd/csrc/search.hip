@@ -761,6 +761,7 @@ search_kernel(SearchKArgs a) {
                     uint64_t key = lds.S[i];
                     id = (int32_t)(uint32_t)key;
                     d = unord_f32((uint32_t)(key >> 32));
+                    if (a.id_map) id = a.id_map[id];
                 }
                 a.out_ids[(size_t)qi * a.k_stride + i] = id;
                 reinterpret_cast<float *>(a.out_d)[(size_t)qi * a.k_stride + i] = d;
@@ -770,6 +771,7 @@ search_kernel(SearchKArgs a) {
                 int32_t id = -1;
                 uint64_t key = i < nout ? lds.pool[i] : KEY_MAX;
                 if (i < nout) id = (int32_t)(uint32_t)key;
+                if (i < nout && a.id_map) id = a.id_map[id];
                 a.out_ids[(size_t)qi * a.k_stride + i] = id;
                 if constexpr (INT) {
                     reinterpret_cast<int32_t *>(a.out_d)[(size_t)qi * a.k_stride + i] =

@@ -65,6 +65,7 @@ struct SearchKArgs {
     int32_t max_dc;
     const int32_t *max_dc_pq;
     float max_dc_factor;
+    const int32_t *id_map;
     int32_t has_pred;
     PredArgs pred;
     float *feat_out;

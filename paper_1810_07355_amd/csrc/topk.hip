@@ -200,33 +200,68 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
     const int ntiles = (int)((a.nb + BN - 1) / BN);
     const int chunks_per_row = a.lds_pitch / 16;
     const int split = blockIdx.y;
+    const int t_beg = split * a.tiles_per_split;
     const int t_end = min(ntiles, (split + 1) * a.tiles_per_split);
-    for (int t = split * a.tiles_per_split; t < t_end; t++) {
+    // The next tile's rows are read into registers while the current tile is
+    // computed (up to STG 16-byte chunks per thread), then stored to LDS.
+    constexpr int STG = 9;
+    const int total = BN * chunks_per_row;
+    const bool piped = total <= STG * (int)blockDim.x;
+    uint4 stg[STG];
+    auto fetch_tile = [&](int t) {
+        const int64_t c0 = (int64_t)t * BN;
+#pragma unroll
+        for (int j = 0; j < STG; j++) {
+            const int i = threadIdx.x + j * blockDim.x;
+            stg[j] = uint4{0, 0, 0, 0};
+            if (i < total) {
+                const int r = i / chunks_per_row, c = i % chunks_per_row;
+                const int64_t br = c0 + r;
+                if (br < a.nb && (int64_t)c * 16 < a.b_pitch)
+                    stg[j] = *reinterpret_cast<const uint4 *>(a.b + br * a.b_pitch + c * 16);
+            }
+        }
+    };
+    auto put_chunk = [&](int i, uint4 v) {
+        const int r = i / chunks_per_row, c = i % chunks_per_row;
+        if constexpr (U8) {
+            // x - 128 as int8 is x ^ 0x80; components past dim become 0
+            uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int w = 0; w < 4; w++) {
+                uint32_t x = w4[w] ^ 0x80808080u;
+                int valid = a.dim - (c * 16 + 4 * w);
+                if (valid <= 0) x = 0u;
+                else if (valid < 4) x &= (1u << (8 * valid)) - 1u;
+                w4[w] = x;
+            }
+            v = uint4{w4[0], w4[1], w4[2], w4[3]};
+        }
+        *reinterpret_cast<uint4 *>(btile + r * a.lds_pitch + c * 16) = v;
+    };
+    if (piped && t_beg < t_end) fetch_tile(t_beg);
+    for (int t = t_beg; t < t_end; t++) {
         const int64_t col0 = (int64_t)t * BN;
         __syncthreads();
         // stage 64 base rows
-        for (int i = threadIdx.x; i < BN * chunks_per_row; i += blockDim.x) {
-            int r = i / chunks_per_row, c = i % chunks_per_row;
-            int64_t br = col0 + r;
-            uint4 v = {0, 0, 0, 0};
-            if (br < a.nb && (int64_t)c * 16 < a.b_pitch)
-                v = *reinterpret_cast<const uint4 *>(a.b + br * a.b_pitch + c * 16);
-            if constexpr (U8) {
-                // x - 128 as int8 is x ^ 0x80; components past dim become 0
-                uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+        if (piped) {
 #pragma unroll
-                for (int w = 0; w < 4; w++) {
-                    uint32_t x = w4[w] ^ 0x80808080u;
-                    int valid = a.dim - (c * 16 + 4 * w);
-                    if (valid <= 0) x = 0u;
-                    else if (valid < 4) x &= (1u << (8 * valid)) - 1u;
-                    w4[w] = x;
-                }
-                v = uint4{w4[0], w4[1], w4[2], w4[3]};
+            for (int j = 0; j < STG; j++) {
+                const int i = threadIdx.x + j * blockDim.x;
+                if (i < total) put_chunk(i, stg[j]);
             }
-            *reinterpret_cast<uint4 *>(btile + r * a.lds_pitch + c * 16) = v;
+        } else {
+            for (int i = threadIdx.x; i < total; i += blockDim.x) {
+                const int r = i / chunks_per_row, c = i % chunks_per_row;
+                const int64_t br = col0 + r;
+                uint4 v = {0, 0, 0, 0};
+                if (br < a.nb && (int64_t)c * 16 < a.b_pitch)
+                    v = *reinterpret_cast<const uint4 *>(a.b + br * a.b_pitch + c * 16);
+                put_chunk(i, v);
+            }
         }
         __syncthreads();
+        if (piped && t + 1 < t_end) fetch_tile(t + 1);
         if (row0 + wv * 16 >= a.nq) continue;
 
         uint64_t thr[4];

@@ -272,6 +272,30 @@ def test_search_mixed_k_eps_ep_per_query():
     assert np.array_equal(host(r.hops), ref["hops"])
 
 
+def test_locality_order_gather_and_id_map():
+    """The locality order sorts rows by (nearest pivot, row) with the nearest
+    pivot by (distance, id) as the oracle's top-1; rows gather exactly; an id
+    map rewrites only the output ids."""
+    P = c1_problem()
+    A, Lb = api(), L()
+    say("locality order")
+    B = gpu_vectors(P["x"], orc.L2SQ)
+    perm = host(A.locality_order(B, to_dev(P["piv"])))
+    nn, _ = orc.topk(P["bv"], P["bv"], 1, cand=P["piv"])
+    want = np.lexsort((np.arange(len(perm)), nn[:, 0]))
+    assert np.array_equal(perm, want)
+    xg = host(A.gather_rows(to_dev(P["x"]), to_dev(perm)))
+    assert np.array_equal(xg, P["x"][perm])
+    po, pn, _ = P["pa"]
+    G, Q, S = gpu_graph(po, pn), gpu_vectors(P["q"], orc.L2SQ), to_dev(P["seeds"])
+    r0 = A.search(B, G, Q, S, k=10, eps=0.05)
+    r1 = A.search(B, G, Q, S, k=10, eps=0.05, id_map=to_dev(perm.astype(np.int32)))
+    torch.cuda.synchronize()
+    i0, i1 = host(r0.ids), host(r1.ids)
+    assert np.array_equal(np.where(i0 >= 0, perm[np.maximum(i0, 0)], -1), i1)
+    assert np.array_equal(host(r0.dists), host(r1.dists))
+
+
 def test_fp8_scale_in_row():
     """FP8 rows that carry their scale in the last 4 bytes: the same codes
     and scale as the separate array, and the same search results."""
