@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--workload", default="c3", choices=["c3", "c2"])
     ap.add_argument("--n-base", type=int, default=None, help="smaller base for quick runs")
     ap.add_argument("--n-train", type=int, default=None)
-    ap.add_argument("--lp", default="f16", choices=["f16", "bf16", "fp8"])
+    ap.add_argument("--lp", default="fp8", choices=["f16", "bf16", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--dump", default=None, help="save per-query sweep data (.npz)")

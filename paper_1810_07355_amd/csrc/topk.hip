@@ -30,6 +30,9 @@ typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BN = 64;        // base rows per tile
+
+// f32 k-steps per MFMA k-group: ceil(dim / 4) rounded up to a multiple of 4
+__host__ __device__ inline int f32_kq(int dim) { return ((dim + 3) / 4 + 3) / 4 * 4; }
 constexpr int CB = 128;       // candidate slots per query row
 
 struct TopkArgs {
@@ -50,6 +53,7 @@ struct TopkArgs {
     int32_t lds_pitch;        // bytes per staged base row
     int32_t *out_ids;
     void *out_d;
+    int32_t side_norms;       // stage the tile's base norms in LDS (L2 metrics)
     int32_t splits;           // blocks sharing one row block's base tiles
     int32_t tiles_per_split;
     uint64_t *part;           // splits > 1: [nq][splits][k] keys of each part
@@ -133,6 +137,11 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
     int32_t *nlist = reinterpret_cast<int32_t *>(p);
     p += (size_t)a.bm * 4;
     uint64_t *stage = reinterpret_cast<uint64_t *>(p) + wv * WAVE;
+    p += (size_t)nwaves * WAVE * 8;
+    // per tile: base norms and global ids of its 64 rows, when needed
+    uint32_t *t_norm = reinterpret_cast<uint32_t *>(p);
+    if (a.side_norms) p += BN * 4;
+    uint32_t *t_gid = reinterpret_cast<uint32_t *>(p);
 
     for (int i = threadIdx.x; i < a.bm; i += blockDim.x) {
         tau[i] = KEY_MAX;
@@ -147,7 +156,10 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
     const bool qvalid = qrow < a.nq;
     const uint8_t *qp = a.q + (qvalid ? qrow : 0) * a.q_pitch;
     constexpr int MAXS = U8 ? 8 : 64;    // k-steps held in registers
-    const int ksteps = U8 ? (a.dim + 63) / 64 : (a.dim + 3) / 4;
+    // f32: k-group kg of the MFMA covers the KQ consecutive components
+    // [kg*KQ, kg*KQ + KQ), KQ a multiple of 4, so a lane reads four k-steps
+    // of its B column with one 16-byte LDS read
+    const int ksteps = U8 ? (a.dim + 63) / 64 : f32_kq(a.dim);
     i32x4 A8[U8 ? MAXS : 1];
     float AF[U8 ? 1 : MAXS];
     if constexpr (U8) {
@@ -158,7 +170,7 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
         const float *qf = reinterpret_cast<const float *>(qp);
 #pragma unroll
         for (int s = 0; s < MAXS; s++) {
-            int c = s * 4 + kg;
+            int c = kg * ksteps + s;
             if (s < ksteps) AF[s] = (qvalid && c < a.dim) ? qf[c] : 0.0f;
         }
     }
@@ -208,7 +220,24 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
     const int total = BN * chunks_per_row;
     const bool piped = total <= STG * (int)blockDim.x;
     uint4 stg[STG];
+    uint32_t side_n = 0, side_g = 0;
+    auto fetch_side = [&](int t) {
+        const int64_t col = (int64_t)t * BN + threadIdx.x;
+        side_n = 0;
+        side_g = 0;
+        if (threadIdx.x < BN && col < a.nb) {
+            if (a.side_norms) side_n = reinterpret_cast<const uint32_t *>(a.bn)[col];
+            if (a.b_ids) side_g = (uint32_t)a.b_ids[col];
+        }
+    };
+    auto put_side = [&]() {
+        if (threadIdx.x < BN) {
+            if (a.side_norms) t_norm[threadIdx.x] = side_n;
+            if (a.b_ids) t_gid[threadIdx.x] = side_g;
+        }
+    };
     auto fetch_tile = [&](int t) {
+        fetch_side(t);
         const int64_t c0 = (int64_t)t * BN;
 #pragma unroll
         for (int j = 0; j < STG; j++) {
@@ -250,7 +279,10 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
                 const int i = threadIdx.x + j * blockDim.x;
                 if (i < total) put_chunk(i, stg[j]);
             }
+            put_side();
         } else {
+            fetch_side(t);
+            put_side();
             for (int i = threadIdx.x; i < total; i += blockDim.x) {
                 const int r = i / chunks_per_row, c = i % chunks_per_row;
                 const int64_t br = col0 + r;
@@ -283,25 +315,28 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
                     }
                 }
             } else {
-                const float *bf = reinterpret_cast<const float *>(brow);
+                // components past dim are zero in the staged tile
+                const float *bf = reinterpret_cast<const float *>(brow) + kg * ksteps;
 #pragma unroll
-                for (int s = 0; s < MAXS; s++) {
+                for (int s = 0; s < MAXS; s += 4) {
                     if (s < ksteps) {
-                        int c = s * 4 + kg;
-                        float bv = c < a.dim ? bf[c] : 0.0f;
-                        accf = __builtin_amdgcn_mfma_f32_16x16x4f32(AF[s], bv, accf, 0, 0, 0);
+                        const f32x4 b4 = *reinterpret_cast<const f32x4 *>(bf + s);
+                        accf = __builtin_amdgcn_mfma_f32_16x16x4f32(AF[s], b4[0], accf, 0, 0, 0);
+                        accf = __builtin_amdgcn_mfma_f32_16x16x4f32(AF[s + 1], b4[1], accf, 0, 0, 0);
+                        accf = __builtin_amdgcn_mfma_f32_16x16x4f32(AF[s + 2], b4[2], accf, 0, 0, 0);
+                        accf = __builtin_amdgcn_mfma_f32_16x16x4f32(AF[s + 3], b4[3], accf, 0, 0, 0);
                     }
                 }
             }
             // C layout: lane holds rows 4*kg + r (r = 0..3) of column arow
             const int64_t col = col0 + cb * 16 + arow;
             const bool cvalid = col < a.nb;
-            const uint32_t gid = cvalid ? (a.b_ids ? (uint32_t)a.b_ids[col] : (uint32_t)col) : 0u;
+            const uint32_t gid = cvalid ? (a.b_ids ? t_gid[cb * 16 + arow] : (uint32_t)col) : 0u;
             int32_t bn8 = 0;
             float bnf = 0.0f;
             if (cvalid) {
-                if constexpr (U8) bn8 = reinterpret_cast<const int32_t *>(a.bn)[col];
-                else if constexpr (MT == ONNG_L2SQ) bnf = reinterpret_cast<const float *>(a.bn)[col];
+                if constexpr (U8) bn8 = (int32_t)t_norm[cb * 16 + arow];
+                else if constexpr (MT == ONNG_L2SQ) bnf = __uint_as_float(t_norm[cb * 16 + arow]);
             }
 #pragma unroll
             for (int r = 0; r < 4; r++) {
@@ -404,18 +439,34 @@ int topk_splits(int64_t nq, int64_t nb, int bm) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(sp, 64));
 }
 
-int topk_bm(int32_t k) { return (k + 63) / 64 * 64 <= 128 ? 64 : 32; }
 
-int lds_pitch_for(int dtype, int64_t pitch) {
-    // +16 bytes keeps the 16 rows read by one MFMA operand on distinct banks
-    (void)dtype;
-    return (int)((pitch + 15) / 16 * 16 + 16);
+// Bytes of a staged row: what the MFMA operands read (u8: whole 64-byte
+// k-steps; f32: 4 k-groups of KQ components), rounded up to an odd number of
+// 16-byte chunks, which spreads the 16 rows read together over the LDS banks
+// (no more than two rows per bank group).
+int lds_pitch_for(int dtype, int32_t dim) {
+    const int need = dtype == ONNG_U8 ? (dim + 63) / 64 * 64 : 16 * f32_kq(dim);
+    int p = (need + 15) / 16 * 16;
+    if ((p / 16) % 2 == 0) p += 16;
+    return p;
 }
 
-size_t topk_lds_bytes(int bm, int kcap, int lds_pitch) {
+size_t topk_lds_bytes(int bm, int kcap, int lds_pitch, int side_words = 0) {
     int nwaves = bm / 16;
     return (size_t)BN * lds_pitch + (size_t)bm * kcap * 8 + (size_t)bm * CB * 8 + (size_t)bm * 16 +
-           (size_t)nwaves * WAVE * 8;
+           (size_t)nwaves * WAVE * 8 + (size_t)side_words * BN * 4;
+}
+
+// Query rows per block: 64 when the block's tile, lists and buffers fit in
+// LDS, else 32.
+int topk_side_words(int dtype, int metric, bool cand) {
+    return (dtype == ONNG_U8 || metric == ONNG_L2SQ ? 1 : 0) + (cand ? 1 : 0);
+}
+
+int topk_bm(int32_t k, int dtype, int32_t dim, int side_words) {
+    const int kcap = (k + 63) / 64 * 64;
+    const int lp = lds_pitch_for(dtype, dim);
+    return kcap <= 128 && topk_lds_bytes(64, kcap, lp, side_words) <= 160 * 1024 ? 64 : 32;
 }
 
 }  // namespace
@@ -426,7 +477,7 @@ size_t topk_ws_size(const onng_vectors *Q, const onng_vectors *B, int64_t n_cand
     c.take<float>(Q->n);
     c.take<float>(nb);
     if (n_cand > 0) c.take<uint8_t>((size_t)nb * B->pitch_bytes);
-    const int sp = topk_splits(Q->n, nb, topk_bm(k));
+    const int sp = topk_splits(Q->n, nb, topk_bm(k, Q->dtype, Q->dim, topk_side_words(Q->dtype, Q->metric, n_cand > 0)));
     if (sp > 1) c.take<uint64_t>((size_t)Q->n * sp * k);
     return c.size() + 256;
 }
@@ -451,7 +502,7 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     Carver c(ws);
     void *qn = c.take<float>(Q->n);
     void *bn = c.take<float>(nb);
-    const int sp = topk_splits(Q->n, nb, topk_bm(k));
+    const int sp = topk_splits(Q->n, nb, topk_bm(k, Q->dtype, Q->dim, topk_side_words(Q->dtype, Q->metric, cand != nullptr)));
     uint64_t *part = sp > 1 ? c.take<uint64_t>((size_t)Q->n * sp * k) : nullptr;
     const uint8_t *brows = static_cast<const uint8_t *>(B->data);
     if (cand && nb > 0) {
@@ -494,13 +545,15 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     a.dim = Q->dim;
     a.k = k;
     a.kcap = (k + 63) / 64 * 64;
-    a.bm = topk_bm(k);
+    const int side_words = topk_side_words(Q->dtype, Q->metric, cand != nullptr);
+    a.side_norms = Q->dtype == ONNG_U8 || Q->metric == ONNG_L2SQ;
+    a.bm = topk_bm(k, Q->dtype, Q->dim, side_words);
     a.exclude_self = exclude_self;
-    // the staged tile holds a row's components only, not any padding past them
-    a.lds_pitch = lds_pitch_for(Q->dtype, ((int64_t)B->dim * elem_bytes(B->dtype) + 15) / 16 * 16);
+    // the staged tile holds a row's components (zero-extended), not its padding
+    a.lds_pitch = lds_pitch_for(Q->dtype, B->dim);
     a.out_ids = ids;
     a.out_d = dists;
-    size_t lds = topk_lds_bytes(a.bm, a.kcap, a.lds_pitch);
+    size_t lds = topk_lds_bytes(a.bm, a.kcap, a.lds_pitch, side_words);
     if (lds > 160 * 1024) {
         set_error("onng_topk: k or dim too large for the on-chip tile");
         return ONNG_ERR_UNSUPPORTED;

@@ -3,7 +3,7 @@
 On a 200,000-object cosine set of the benchmark's recipe, the curve
 predictor is trained with the library's own kernels on sweep labels of
 20,000 training queries.  On 2,000 held-out queries it must reach the
-same mean recall@10 as the best single search range with fewer distance
+same mean recall@10 (0.98) as the best single search range with fewer distance
 computations.  Both operating points are found by bisection (the range for
 the plain method, lambda for the learned one).  The gain is measured, not
 pinned: the paper has no learned range.
@@ -22,7 +22,7 @@ pytestmark = [pytest.mark.gpu,
 def test_learned_range_gain():
     from paper_1810_07355_amd import learned as LR
     A, Lb = api(), L()
-    K, NS, TARGET = 10, 8, 0.99
+    K, NS, TARGET = 10, 8, 0.98
     cfg = dg.scaled(dg.PRESETS["c3"], 200_000, 2000, n_clusters=400, n_train=20_000)
     say("learned gain: building the index")
     B = A.Vectors.from_tensor(to_dev(dg.base(cfg)), Lb.COSINE)
@@ -36,7 +36,7 @@ def test_learned_range_gain():
     tseeds, _ = A.topk(T, B, NS, cand=piv)
     gt = A.ground_truth(Q, B, K)[0].cpu().numpy()
     tgt = A.ground_truth(T, B, K)[0].cpu().numpy()
-    grid = [round(0.01 * i, 2) for i in range(0, 21)] + [0.25, 0.3, 0.4]
+    grid = [round(0.01 * i, 2) for i in range(0, 21)] + [0.25, 0.3, 0.4, 0.6]
     epf = LR.dynamic_ep(0.11)
     say("learned gain: label sweep")
     recs, dcs, feats = [], [], None
@@ -49,7 +49,7 @@ def test_learned_range_gain():
         recs.append(LR.recall_by_ids(r.ids.cpu().numpy(), tgt, K))
         dcs.append(r.dc.cpu().numpy())
     recs, dcs = np.stack(recs), np.stack(dcs)
-    cand = [0.10, 0.13, 0.15, 0.17, 0.19, 0.20, 0.25, 0.30]
+    cand = [0.08, 0.11, 0.14, 0.17, 0.20, 0.25, 0.40, 0.60]
     idx = [grid.index(c) if c in grid else int(np.argmin(np.abs(np.array(grid) - c)))
            for c in cand]
     say("learned gain: training")
