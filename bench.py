@@ -350,18 +350,34 @@ def main():
                         best = pt
         return best
 
-    def make_learned_b(tgt):
+    def make_learned_b(tgt, fused=False):
+        """Learned range as three steps (predict pass, longest-first order,
+        search) or fused into one search after the probe expansions."""
         def make(knob, b, fac=0.0):
             pred = learned_pred(tgt, knob)
-            req = A.LearnedSearch(search_rows, graph, queries, seeds, pred, ep_first=EPF, **idm,
-                                  probe_hops=PROBE, k=K, max_dc=b, max_dc_factor=fac, **rr)
+            if fused:
+                req = A.SearchRequest(search_rows, graph, queries, seeds, k=K, two_phase=True,
+                                      ep_first=EPF, probe_hops=PROBE, predictor=pred, max_dc=b,
+                                      max_dc_factor=fac, **rr, **idm)
+            else:
+                req = A.LearnedSearch(search_rows, graph, queries, seeds, pred, ep_first=EPF,
+                                      **idm, probe_hops=PROBE, k=K, max_dc=b, max_dc_factor=fac,
+                                      **rr)
             req._pred = pred
             return req
         return make
 
     for tgt in (0.95, 0.99):
-        learned_pts[str(tgt)] = best_over_budgets(make_learned_b(tgt), tgt, 2.0, 9.0,
-                                                  f"learned@{tgt}", factors=(0.0, 2.0, 4.0))
+        best = None
+        for fused in (False, True):
+            pt = best_over_budgets(make_learned_b(tgt, fused), tgt, 2.0, 9.0,
+                                   f"learned{'-fused' if fused else ''}@{tgt}",
+                                   factors=(0.0, 2.0, 4.0))
+            if pt is not None:
+                pt["single_pass"] = fused
+                if best is None or pt["qps"] > best["qps"]:
+                    best = pt
+        learned_pts[str(tgt)] = best
     result["learned"] = learned_pts
     knobs = {t: (learned_pts[str(t)]["knob"] if learned_pts[str(t)] else 9.0)
              for t in (0.95, 0.99)}
@@ -369,6 +385,8 @@ def main():
                for t in (0.95, 0.99)}
     bfactors = {t: (learned_pts[str(t)]["max_dc_factor"] if learned_pts[str(t)] else 0.0)
                 for t in (0.95, 0.99)}
+    single = {t: bool(learned_pts[str(t)]["single_pass"]) if learned_pts[str(t)] else False
+              for t in (0.95, 0.99)}
     # the same budgets without the learned range, for comparison
     if lp_rows is not None:
         make_lp_b = lambda e, b, fac=0.0: A.SearchRequest(lp_rows, graph, queries, seeds, k=K, eps=e, **idm,
@@ -393,7 +411,8 @@ def main():
     # one pipeline (own outputs and workspace) and one stream per batch in flight
     pipes = [A.Pipeline(search_rows, graph, queries, piv, NS, k=K, eps=0.0, ep=L.EP_INF, **idm,
                         two_phase=True, ep_first=EPF, probe_hops=PROBE, predictor=pred95,
-                        max_dc=budgets[0.95], max_dc_factor=bfactors[0.95], **rr)
+                        max_dc=budgets[0.95], max_dc_factor=bfactors[0.95],
+                        single_pass=single[0.95], **rr)
              for _ in range(NF)]
     pipe = pipes[0]
     plain95 = result["plain"]["0.95"]
@@ -417,7 +436,7 @@ def main():
         return last
 
     if args.search_only:
-        req = make_learned_b(0.95)(knobs[0.95], budgets[0.95], bfactors[0.95])
+        req = make_learned_b(0.95, single[0.95])(knobs[0.95], budgets[0.95], bfactors[0.95])
         for _ in range(args.warmup + args.steps):
             req.run()
         torch.cuda.synchronize()
@@ -469,7 +488,7 @@ def main():
         learned99_pipe = pipe_qps([A.Pipeline(
             search_rows, graph, queries, piv, NS, k=K, **idm, eps=0.0, ep=L.EP_INF, two_phase=True,
             ep_first=EPF, probe_hops=PROBE, predictor=pred99, max_dc=budgets[0.99],
-            max_dc_factor=bfactors[0.99], **rr) for _ in range(NF)])
+            max_dc_factor=bfactors[0.99], single_pass=single[0.99], **rr) for _ in range(NF)])
         log(f"learned pipeline at 0.99, {NF} in flight: {learned99_pipe[0]:.0f} q/s, "
             f"recall {learned99_pipe[1]:.4f}")
     plain99 = result["plain"]["0.99"]
@@ -480,9 +499,9 @@ def main():
         log(f"plain f32 pipeline at 0.99, {NF} in flight: {plain99_pipe[0]:.0f} q/s")
 
     # ---------------------------------------- roofline of the search kernel --
-    lreq = make_learned_b(0.95)(knobs[0.95], budgets[0.95], bfactors[0.95])
+    lreq = make_learned_b(0.95, single[0.95])(knobs[0.95], budgets[0.95], bfactors[0.95])
     lreq.run()
-    req = lreq.req                 # the search pass (predict pass and order excluded)
+    req = lreq if single[0.95] else lreq.req   # the search pass (predict pass, order excluded)
     ms_search = time_req(req, reps=5)
     st = req.stats.cpu().numpy()
     log(f"queries with candidate-set spill: {(st[:, 2] & L.QF_SPILLED != 0).mean():.3f}; "
@@ -562,6 +581,7 @@ def main():
             "batches_in_flight": NF,
             "max_dc": {str(t): budgets[t] for t in (0.95, 0.99)},
             "max_dc_factor": {str(t): bfactors[t] for t in (0.95, 0.99)},
+            "learned_single_pass": {str(t): single[t] for t in (0.95, 0.99)},
         },
         "recall_at_timed_point": round(rec95, 4),
         "qps": {

@@ -262,6 +262,10 @@ typedef struct {
     /* Output ids are id_map[id] when non-NULL (e.g. the permutation of
      * onng_locality_order, to report original row ids). */
     const int32_t *id_map;
+    /* Pipelines with a predictor (onng_pipeline_create): 0 = a predict-only
+     * pass, longest-first ordering and the search (three steps); 1 = one
+     * search with the predictor fused after the probe expansions. */
+    int32_t single_pass;
 } onng_search_params;
 
 /* Per-query statistics written by onng_search. */
@@ -386,9 +390,10 @@ onng_status onng_autotune_search(const onng_vectors *base, const onng_graph *gra
 
 /* Captures the query pipeline for a fixed batch into a HIP graph, returned
  * in *handle (host): seed selection against `pivots`, then the search and
- * rerank.  With a predictor the search runs as three steps: a predict-only
+ * rerank.  With a predictor the search runs as three steps (a predict-only
  * pass, onng_order_by_cost, and the search with the predicted ranges in that
- * order.  All pointers must stay valid while the handle lives. */
+ * order), or as one fused search when params->single_pass is set.  All
+ * pointers must stay valid while the handle lives. */
 typedef struct onng_pipeline onng_pipeline;
 onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *graph,
                                  const onng_vectors *queries, const int32_t *pivots,

@@ -200,7 +200,7 @@ class SearchRequest:
                  rerank_base: Vectors | None = None, pool_factor=4, launch=None, probe_hops=1,
                  predict_only=False, range_from: torch.Tensor | None = None,
                  order: torch.Tensor | None = None, max_dc=0, max_dc_factor=0.0,
-                 id_map: torch.Tensor | None = None):
+                 id_map: torch.Tensor | None = None, single_pass=False):
         dev = queries.data.device
         nq = queries.n
         self.base, self.graph, self.queries = base, graph, queries
@@ -239,7 +239,7 @@ class SearchRequest:
             C.cast(rerank_base.ref, C.c_void_p) if rerank_base else None,
             int(pool_factor), C.cast(C.byref(launch), C.c_void_p) if launch is not None else None,
             int(probe_hops), int(predict_only), _ptr(range_from), _ptr(order), int(max_dc),
-            _ptr(mdq), float(max_dc_factor), _ptr(id_map))
+            _ptr(mdq), float(max_dc_factor), _ptr(id_map), int(single_pass))
         self._keep += [range_from, order, id_map]
         self.gs = graph.struct()
         out_dt = torch.float32 if rerank_base is not None else base.dist_dtype

@@ -903,7 +903,7 @@ onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *gra
     if (rc == ONNG_OK)
         rc = launch_topk(queries, seed_base, pivots, n_pivots, n_seeds, 0, seeds, seed_d, wsa, a,
                          st);
-    if (rc == ONNG_OK && !params->predictor) {
+    if (rc == ONNG_OK && (!params->predictor || params->single_pass)) {
         rc = run_search(base, graph, queries, seeds, n_seeds, params, ids, dists, stats, wsa + a,
                         ws_bytes - a, st, params->launch);
     } else if (rc == ONNG_OK) {

@@ -712,3 +712,12 @@ def test_scheduled_learned_search():
         assert np.array_equal(host(out.dc), host(req.dc))
         out.ids.fill_(-5)
     pl.close()
+    # the single-pass pipeline equals the one-pass search
+    pl1 = A.Pipeline(B, G, Q, to_dev(P["piv"]), 8, k=10, two_phase=True, ep_first=64,
+                     predictor=pred, single_pass=True)
+    for rep in range(2):
+        out = pl1.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out.ids), host(one.ids))
+        assert np.array_equal(host(out.dc), host(one.dc))
+    pl1.close()
