@@ -30,10 +30,24 @@ typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BN = 64;        // base rows per tile
-
-// f32 k-steps per MFMA k-group: ceil(dim / 4) rounded up to a multiple of 4
-__host__ __device__ inline int f32_kq(int dim) { return ((dim + 3) / 4 + 3) / 4 * 4; }
 constexpr int CB = 128;       // candidate slots per query row
+
+// A staged row is NCH * 64 bytes: u8, NCH k-steps of 64 components (a lane
+// feeds 16 of them per step); f32, 4 k-groups of KQ = 4 * NCH components,
+// k-group kg covering [kg * KQ, kg * KQ + KQ), so that a lane reads four
+// k-steps of its B column with one 16-byte LDS read.  NCH is a compile-time
+// constant of the kernel, taken from a short list (rows are zero-extended up
+// to it), so the contraction unrolls into one straight run of LDS reads and
+// MFMAs.
+__host__ __device__ inline int nch_for(int dtype, int dim) {
+    if (dtype == ONNG_U8) {
+        const int need = (dim + 63) / 64;
+        return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
+    }
+    const int need = (dim + 15) / 16;
+    return need <= 2 ? 2 : need <= 4 ? 4 : need <= 6 ? 6 : need <= 7 ? 7 : need <= 8 ? 8
+           : need <= 12 ? 12 : 16;
+}
 
 struct TopkArgs {
     const uint8_t *q;
@@ -113,9 +127,10 @@ __device__ __forceinline__ i32x4 shifted16(const uint8_t *row, int c, int dim) {
     return out;
 }
 
-template <int DT, int MT>
+template <int DT, int MT, int NCH>
 __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
     constexpr bool U8 = DT == ONNG_U8;
+    constexpr int KQ = 4 * NCH;      // f32: components per k-group
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int lane = lane_id();
     const int wv = threadIdx.x / WAVE;
@@ -155,23 +170,18 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
     const int64_t qrow = row0 + wv * 16 + arow;
     const bool qvalid = qrow < a.nq;
     const uint8_t *qp = a.q + (qvalid ? qrow : 0) * a.q_pitch;
-    constexpr int MAXS = U8 ? 8 : 64;    // k-steps held in registers
-    // f32: k-group kg of the MFMA covers the KQ consecutive components
-    // [kg*KQ, kg*KQ + KQ), KQ a multiple of 4, so a lane reads four k-steps
-    // of its B column with one 16-byte LDS read
-    const int ksteps = U8 ? (a.dim + 63) / 64 : f32_kq(a.dim);
-    i32x4 A8[U8 ? MAXS : 1];
-    float AF[U8 ? 1 : MAXS];
+    i32x4 A8[U8 ? NCH : 1];
+    float AF[U8 ? 1 : KQ];
     if constexpr (U8) {
 #pragma unroll
-        for (int s = 0; s < MAXS; s++)
-            if (s < ksteps) A8[s] = qvalid ? shifted16(qp, s * 64 + kg * 16, a.dim) : i32x4{0, 0, 0, 0};
+        for (int s = 0; s < NCH; s++)
+            A8[s] = qvalid ? shifted16(qp, s * 64 + kg * 16, a.dim) : i32x4{0, 0, 0, 0};
     } else {
         const float *qf = reinterpret_cast<const float *>(qp);
 #pragma unroll
-        for (int s = 0; s < MAXS; s++) {
-            int c = kg * ksteps + s;
-            if (s < ksteps) AF[s] = (qvalid && c < a.dim) ? qf[c] : 0.0f;
+        for (int s = 0; s < KQ; s++) {
+            const int c = kg * KQ + s;
+            AF[s] = (qvalid && c < a.dim) ? qf[c] : 0.0f;
         }
     }
     // norms of the 4 output rows this lane sees in C (rows 4*kg + r)
@@ -210,14 +220,14 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
     };
 
     const int ntiles = (int)((a.nb + BN - 1) / BN);
-    const int chunks_per_row = a.lds_pitch / 16;
+    constexpr int CPR = NCH * 4;     // 16-byte chunks of a staged row
     const int split = blockIdx.y;
     const int t_beg = split * a.tiles_per_split;
     const int t_end = min(ntiles, (split + 1) * a.tiles_per_split);
     // The next tile's rows are read into registers while the current tile is
     // computed (up to STG 16-byte chunks per thread), then stored to LDS.
     constexpr int STG = 9;
-    const int total = BN * chunks_per_row;
+    constexpr int total = BN * CPR;
     const bool piped = total <= STG * (int)blockDim.x;
     uint4 stg[STG];
     uint32_t side_n = 0, side_g = 0;
@@ -236,26 +246,28 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
             if (a.b_ids) t_gid[threadIdx.x] = side_g;
         }
     };
+    auto load_chunk = [&](int64_t c0, int i) {
+        const int r = i / CPR, c = i % CPR;
+        const int64_t br = c0 + r;
+        if (br < a.nb && (int64_t)c * 16 < a.b_pitch)
+            return *reinterpret_cast<const uint4 *>(a.b + br * a.b_pitch + c * 16);
+        return uint4{0, 0, 0, 0};
+    };
     auto fetch_tile = [&](int t) {
         fetch_side(t);
         const int64_t c0 = (int64_t)t * BN;
 #pragma unroll
         for (int j = 0; j < STG; j++) {
             const int i = threadIdx.x + j * blockDim.x;
-            stg[j] = uint4{0, 0, 0, 0};
-            if (i < total) {
-                const int r = i / chunks_per_row, c = i % chunks_per_row;
-                const int64_t br = c0 + r;
-                if (br < a.nb && (int64_t)c * 16 < a.b_pitch)
-                    stg[j] = *reinterpret_cast<const uint4 *>(a.b + br * a.b_pitch + c * 16);
-            }
+            stg[j] = i < total ? load_chunk(c0, i) : uint4{0, 0, 0, 0};
         }
     };
+    // components at or past dim become 0 (a row's padding may hold anything)
     auto put_chunk = [&](int i, uint4 v) {
-        const int r = i / chunks_per_row, c = i % chunks_per_row;
+        const int r = i / CPR, c = i % CPR;
+        uint32_t w4[4] = {v.x, v.y, v.z, v.w};
         if constexpr (U8) {
-            // x - 128 as int8 is x ^ 0x80; components past dim become 0
-            uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+            // x - 128 as int8 is x ^ 0x80
 #pragma unroll
             for (int w = 0; w < 4; w++) {
                 uint32_t x = w4[w] ^ 0x80808080u;
@@ -264,9 +276,13 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
                 else if (valid < 4) x &= (1u << (8 * valid)) - 1u;
                 w4[w] = x;
             }
-            v = uint4{w4[0], w4[1], w4[2], w4[3]};
+        } else {
+#pragma unroll
+            for (int w = 0; w < 4; w++)
+                if (c * 4 + w >= a.dim) w4[w] = 0u;
         }
-        *reinterpret_cast<uint4 *>(btile + r * a.lds_pitch + c * 16) = v;
+        *reinterpret_cast<uint4 *>(btile + r * a.lds_pitch + c * 16) =
+            uint4{w4[0], w4[1], w4[2], w4[3]};
     };
     if (piped && t_beg < t_end) fetch_tile(t_beg);
     for (int t = t_beg; t < t_end; t++) {
@@ -283,78 +299,94 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
         } else {
             fetch_side(t);
             put_side();
-            for (int i = threadIdx.x; i < total; i += blockDim.x) {
-                const int r = i / chunks_per_row, c = i % chunks_per_row;
-                const int64_t br = col0 + r;
-                uint4 v = {0, 0, 0, 0};
-                if (br < a.nb && (int64_t)c * 16 < a.b_pitch)
-                    v = *reinterpret_cast<const uint4 *>(a.b + br * a.b_pitch + c * 16);
-                put_chunk(i, v);
-            }
+            for (int i = threadIdx.x; i < total; i += blockDim.x) put_chunk(i, load_chunk(col0, i));
         }
         __syncthreads();
         if (piped && t + 1 < t_end) fetch_tile(t + 1);
         if (row0 + wv * 16 >= a.nq) continue;
 
-        uint64_t thr[4];
-#pragma unroll
-        for (int r = 0; r < 4; r++) thr[r] = tau[wv * 16 + 4 * kg + r];
-
+        // ---- 16 query rows x 64 tile columns: four 16x16 blocks, their
+        // accumulation chains interleaved ----
+        const uint8_t *bbase = btile + arow * a.lds_pitch + (U8 ? kg * 16 : kg * KQ * 4);
+        i32x4 acc8[4];
+        f32x4 accf[4];
 #pragma unroll
         for (int cb = 0; cb < 4; cb++) {
-            const int bcol = cb * 16 + arow;           // tile column this lane feeds
-            const uint8_t *brow = btile + bcol * a.lds_pitch;
-            i32x4 acc8 = {0, 0, 0, 0};
-            f32x4 accf = {0, 0, 0, 0};
+            acc8[cb] = i32x4{0, 0, 0, 0};
+            accf[cb] = f32x4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int c = 0; c < NCH; c++) {
             if constexpr (U8) {
+                i32x4 bv[4];
 #pragma unroll
-                for (int s = 0; s < MAXS; s++) {
-                    if (s < ksteps) {
-                        i32x4 bv = *reinterpret_cast<const i32x4 *>(brow + s * 64 + kg * 16);
-                        acc8 = __builtin_amdgcn_mfma_i32_16x16x64_i8(A8[s], bv, acc8, 0, 0, 0);
-                    }
-                }
+                for (int cb = 0; cb < 4; cb++)
+                    bv[cb] = *reinterpret_cast<const i32x4 *>(bbase + cb * 16 * a.lds_pitch + c * 64);
+#pragma unroll
+                for (int cb = 0; cb < 4; cb++)
+                    acc8[cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A8[c], bv[cb], acc8[cb], 0, 0, 0);
             } else {
-                // components past dim are zero in the staged tile
-                const float *bf = reinterpret_cast<const float *>(brow) + kg * ksteps;
+                f32x4 bv[4];
 #pragma unroll
-                for (int s = 0; s < MAXS; s += 4) {
-                    if (s < ksteps) {
-                        const f32x4 b4 = *reinterpret_cast<const f32x4 *>(bf + s);
-                        accf = __builtin_amdgcn_mfma_f32_16x16x4f32(AF[s], b4[0], accf, 0, 0, 0);
-                        accf = __builtin_amdgcn_mfma_f32_16x16x4f32(AF[s + 1], b4[1], accf, 0, 0, 0);
-                        accf = __builtin_amdgcn_mfma_f32_16x16x4f32(AF[s + 2], b4[2], accf, 0, 0, 0);
-                        accf = __builtin_amdgcn_mfma_f32_16x16x4f32(AF[s + 3], b4[3], accf, 0, 0, 0);
-                    }
-                }
+                for (int cb = 0; cb < 4; cb++)
+                    bv[cb] = *reinterpret_cast<const f32x4 *>(bbase + cb * 16 * a.lds_pitch + c * 16);
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+#pragma unroll
+                    for (int cb = 0; cb < 4; cb++)
+                        accf[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(AF[4 * c + j], bv[cb][j],
+                                                                          accf[cb], 0, 0, 0);
             }
-            // C layout: lane holds rows 4*kg + r (r = 0..3) of column arow
-            const int64_t col = col0 + cb * 16 + arow;
-            const bool cvalid = col < a.nb;
-            const uint32_t gid = cvalid ? (a.b_ids ? t_gid[cb * 16 + arow] : (uint32_t)col) : 0u;
+        }
+
+        // ---- epilogue: C layout, lane holds rows 4*kg + r of column arow
+        // of each block.  A key can beat a row's list only if its distance
+        // part is <= the high half of the row's threshold; that test alone
+        // runs on every value, the full one on the few that pass it. ----
+        uint64_t thr[4];
+        uint32_t thi[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            thr[r] = tau[wv * 16 + 4 * kg + r];
+            thi[r] = crow[r] < a.nq ? (uint32_t)(thr[r] >> 32) : 0u;
+        }
+        uint32_t dd[4][4];
+        bool any = false;
+#pragma unroll
+        for (int cb = 0; cb < 4; cb++) {
             int32_t bn8 = 0;
             float bnf = 0.0f;
-            if (cvalid) {
-                if constexpr (U8) bn8 = (int32_t)t_norm[cb * 16 + arow];
-                else if constexpr (MT == ONNG_L2SQ) bnf = __uint_as_float(t_norm[cb * 16 + arow]);
-            }
+            if constexpr (U8) bn8 = (int32_t)t_norm[cb * 16 + arow];
+            else if constexpr (MT == ONNG_L2SQ) bnf = __uint_as_float(t_norm[cb * 16 + arow]);
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 uint32_t dord;
                 if constexpr (U8) {
-                    dord = (uint32_t)(qn8[r] + bn8 - 2 * acc8[r]);
+                    dord = (uint32_t)(qn8[r] + bn8 - 2 * acc8[cb][r]);
                 } else if constexpr (MT == ONNG_L2SQ) {
-                    dord = ord_f32(qnf[r] + bnf - 2.0f * accf[r]);
+                    dord = ord_f32(qnf[r] + bnf - 2.0f * accf[cb][r]);
                 } else {
-                    dord = ord_f32(1.0f - accf[r]);
+                    dord = ord_f32(1.0f - accf[cb][r]);
                 }
-                uint64_t key = make_key(dord, gid);
-                bool ok = cvalid && crow[r] < a.nq && key < thr[r] &&
-                          !(a.exclude_self && (int64_t)gid == crow[r]);
-                if (ok) {
-                    int lr = wv * 16 + 4 * kg + r;
-                    int slot = atomicAdd(&cnt[lr], 1);
-                    cands[(size_t)lr * CB + slot] = key;
+                dd[cb][r] = dord;
+                any |= dord <= thi[r];
+            }
+        }
+        if (any) {
+#pragma unroll
+            for (int cb = 0; cb < 4; cb++) {
+                const int64_t col = col0 + cb * 16 + arow;
+                if (col >= a.nb) continue;
+                const uint32_t gid = a.b_ids ? t_gid[cb * 16 + arow] : (uint32_t)col;
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const uint64_t key = make_key(dd[cb][r], gid);
+                    if (dd[cb][r] <= thi[r] && crow[r] < a.nq && key < thr[r] &&
+                        !(a.exclude_self && (int64_t)gid == crow[r])) {
+                        int lr = wv * 16 + 4 * kg + r;
+                        int slot = atomicAdd(&cnt[lr], 1);
+                        cands[(size_t)lr * CB + slot] = key;
+                    }
                 }
             }
         }
@@ -445,10 +477,31 @@ int topk_splits(int64_t nq, int64_t nb, int bm) {
 // 16-byte chunks, which spreads the 16 rows read together over the LDS banks
 // (no more than two rows per bank group).
 int lds_pitch_for(int dtype, int32_t dim) {
-    const int need = dtype == ONNG_U8 ? (dim + 63) / 64 * 64 : 16 * f32_kq(dim);
-    int p = (need + 15) / 16 * 16;
+    int p = nch_for(dtype, dim) * 64;
     if ((p / 16) % 2 == 0) p += 16;
     return p;
+}
+
+template <int DT, int MT>
+const void *topk_fn_for(int nch) {
+    if constexpr (DT == ONNG_U8) {
+        switch (nch) {
+            case 1: return (const void *)topk_kernel<DT, MT, 1>;
+            case 2: return (const void *)topk_kernel<DT, MT, 2>;
+            case 4: return (const void *)topk_kernel<DT, MT, 4>;
+            default: return (const void *)topk_kernel<DT, MT, 8>;
+        }
+    } else {
+        switch (nch) {
+            case 2: return (const void *)topk_kernel<DT, MT, 2>;
+            case 4: return (const void *)topk_kernel<DT, MT, 4>;
+            case 6: return (const void *)topk_kernel<DT, MT, 6>;
+            case 7: return (const void *)topk_kernel<DT, MT, 7>;
+            case 8: return (const void *)topk_kernel<DT, MT, 8>;
+            case 12: return (const void *)topk_kernel<DT, MT, 12>;
+            default: return (const void *)topk_kernel<DT, MT, 16>;
+        }
+    }
 }
 
 size_t topk_lds_bytes(int bm, int kcap, int lds_pitch, int side_words = 0) {
@@ -496,6 +549,10 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     if (ws_bytes < topk_ws_size(Q, B, cand ? n_cand : 0, k)) {
         set_error("onng_topk: workspace too small");
         return ONNG_ERR_WORKSPACE;
+    }
+    if (Q->dim != B->dim || Q->dim > (Q->dtype == ONNG_U8 ? 512 : 256)) {
+        set_error("onng_topk: dims differ, or above 512 (u8) / 256 (f32)");
+        return ONNG_ERR_UNSUPPORTED;
     }
     const bool u8 = Q->dtype == ONNG_U8;
     const int64_t nb = cand ? n_cand : B->n;
@@ -558,10 +615,11 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
         set_error("onng_topk: k or dim too large for the on-chip tile");
         return ONNG_ERR_UNSUPPORTED;
     }
+    const int nch = nch_for(Q->dtype, Q->dim);
     const void *fn;
-    if (u8) fn = (const void *)topk_kernel<ONNG_U8, ONNG_L2SQ>;
-    else if (Q->metric == ONNG_L2SQ) fn = (const void *)topk_kernel<ONNG_F32, ONNG_L2SQ>;
-    else fn = (const void *)topk_kernel<ONNG_F32, ONNG_COSINE>;
+    if (u8) fn = topk_fn_for<ONNG_U8, ONNG_L2SQ>(nch);
+    else if (Q->metric == ONNG_L2SQ) fn = topk_fn_for<ONNG_F32, ONNG_L2SQ>(nch);
+    else fn = topk_fn_for<ONNG_F32, ONNG_COSINE>(nch);
     ONNG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int ntiles = (int)((nb + BN - 1) / BN);
     a.splits = sp;
