@@ -684,8 +684,8 @@ onng_status onng_autotune_search(const onng_vectors *base, const onng_graph *gra
             found = true;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (!found) {
         set_error("onng_autotune_search: no launch shape fits the workspace");
         return ONNG_ERR_WORKSPACE;
@@ -893,7 +893,7 @@ onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *gra
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         set_error("onng_pipeline_create: stream capture failed to start");
         delete pl;
-        if (own) hipStreamDestroy(st);
+        if (own) (void)hipStreamDestroy(st);
         return ONNG_ERR_DEVICE;
     }
     if (params->k_stride < n_seeds) {
@@ -943,10 +943,10 @@ onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *gra
         set_error("onng_pipeline_create: graph instantiation failed");
     }
     pl->graph = g;
-    if (own) hipStreamDestroy(st);
+    if (own) (void)hipStreamDestroy(st);
     if (rc != ONNG_OK) {
-        if (pl->exec) hipGraphExecDestroy(pl->exec);
-        if (pl->graph) hipGraphDestroy(pl->graph);
+        if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+        if (pl->graph) (void)hipGraphDestroy(pl->graph);
         delete pl;
         return rc;
     }
@@ -963,8 +963,8 @@ onng_status onng_pipeline_launch(onng_pipeline *handle, void *stream) {
 
 onng_status onng_pipeline_destroy(onng_pipeline *handle) {
     if (!handle) return ONNG_OK;
-    if (handle->exec) hipGraphExecDestroy(handle->exec);
-    if (handle->graph) hipGraphDestroy(handle->graph);
+    if (handle->exec) (void)hipGraphExecDestroy(handle->exec);
+    if (handle->graph) (void)hipGraphDestroy(handle->graph);
     delete handle;
     return ONNG_OK;
 }

@@ -246,43 +246,75 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
             if (a.b_ids) t_gid[threadIdx.x] = side_g;
         }
     };
-    auto load_chunk = [&](int64_t c0, int i) {
-        const int r = i / CPR, c = i % CPR;
-        const int64_t br = c0 + r;
-        if (br < a.nb && (int64_t)c * 16 < a.b_pitch)
-            return *reinterpret_cast<const uint4 *>(a.b + br * a.b_pitch + c * 16);
+    // A thread's chunks sit at the same place in every tile; rows are read
+    // with 32-bit offsets from the tile's first row.
+    const uint32_t bp32 = (uint32_t)a.b_pitch;
+    const int cmax = (int)min<int64_t>(CPR, a.b_pitch / 16);   // chunks a global row holds
+    auto load_chunk = [&](const uint8_t *tb, int rows, int i) {
+        const int r = i / CPR, c = i - r * CPR;
+        if (r < rows && c < cmax)
+            return *reinterpret_cast<const uint4 *>(tb + (uint32_t)r * bp32 + (uint32_t)c * 16u);
         return uint4{0, 0, 0, 0};
     };
+    auto tile_rows = [&](int t) { return (int)min<int64_t>(BN, a.nb - (int64_t)t * BN); };
+    auto tile_ptr = [&](int t) { return a.b + (int64_t)t * BN * a.b_pitch; };
+    // Pipelined staging: thread chunk j is i = threadIdx.x + j * blockDim.x,
+    // at global offset goff[j] in the tile and LDS offset loff[j] (low 24
+    // bits; its chunk index within the row in the high 8).
+    uint32_t goff[STG], loff[STG];
+#pragma unroll
+    for (int j = 0; j < STG; j++) {
+        const int i = threadIdx.x + j * blockDim.x;
+        const uint32_t r = (uint32_t)(i / CPR), c = (uint32_t)(i % CPR);
+        goff[j] = r * bp32 + c * 16u;
+        loff[j] = (r * (uint32_t)a.lds_pitch + c * 16u) | (c << 24);
+    }
+    const bool rows_long = cmax == CPR;
     auto fetch_tile = [&](int t) {
         fetch_side(t);
-        const int64_t c0 = (int64_t)t * BN;
+        const uint8_t *tb = tile_ptr(t);
+        const int rows = tile_rows(t);
+        if (rows == BN && rows_long) {
 #pragma unroll
-        for (int j = 0; j < STG; j++) {
-            const int i = threadIdx.x + j * blockDim.x;
-            stg[j] = i < total ? load_chunk(c0, i) : uint4{0, 0, 0, 0};
+            for (int j = 0; j < STG; j++) {
+                const int i = threadIdx.x + j * blockDim.x;
+                if (i < total) stg[j] = *reinterpret_cast<const uint4 *>(tb + goff[j]);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < STG; j++) {
+                const int i = threadIdx.x + j * blockDim.x;
+                stg[j] = i < total ? load_chunk(tb, rows, i) : uint4{0, 0, 0, 0};
+            }
         }
     };
     // components at or past dim become 0 (a row's padding may hold anything)
-    auto put_chunk = [&](int i, uint4 v) {
-        const int r = i / CPR, c = i % CPR;
+    auto put_chunk_at = [&](uint32_t off, int c, uint4 v) {
         uint32_t w4[4] = {v.x, v.y, v.z, v.w};
         if constexpr (U8) {
             // x - 128 as int8 is x ^ 0x80
 #pragma unroll
-            for (int w = 0; w < 4; w++) {
-                uint32_t x = w4[w] ^ 0x80808080u;
-                int valid = a.dim - (c * 16 + 4 * w);
-                if (valid <= 0) x = 0u;
-                else if (valid < 4) x &= (1u << (8 * valid)) - 1u;
-                w4[w] = x;
+            for (int w = 0; w < 4; w++) w4[w] ^= 0x80808080u;
+            if (c * 16 + 16 > a.dim) {
+#pragma unroll
+                for (int w = 0; w < 4; w++) {
+                    const int valid = a.dim - (c * 16 + 4 * w);
+                    if (valid <= 0) w4[w] = 0u;
+                    else if (valid < 4) w4[w] &= (1u << (8 * valid)) - 1u;
+                }
             }
         } else {
+            if (c * 4 + 4 > a.dim) {
 #pragma unroll
-            for (int w = 0; w < 4; w++)
-                if (c * 4 + w >= a.dim) w4[w] = 0u;
+                for (int w = 0; w < 4; w++)
+                    if (c * 4 + w >= a.dim) w4[w] = 0u;
+            }
         }
-        *reinterpret_cast<uint4 *>(btile + r * a.lds_pitch + c * 16) =
-            uint4{w4[0], w4[1], w4[2], w4[3]};
+        *reinterpret_cast<uint4 *>(btile + off) = uint4{w4[0], w4[1], w4[2], w4[3]};
+    };
+    auto put_chunk = [&](int i, uint4 v) {
+        const int r = i / CPR, c = i - r * CPR;
+        put_chunk_at((uint32_t)r * (uint32_t)a.lds_pitch + (uint32_t)c * 16u, c, v);
     };
     if (piped && t_beg < t_end) fetch_tile(t_beg);
     for (int t = t_beg; t < t_end; t++) {
@@ -293,13 +325,15 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
 #pragma unroll
             for (int j = 0; j < STG; j++) {
                 const int i = threadIdx.x + j * blockDim.x;
-                if (i < total) put_chunk(i, stg[j]);
+                if (i < total) put_chunk_at(loff[j] & 0xFFFFFFu, (int)(loff[j] >> 24), stg[j]);
             }
             put_side();
         } else {
             fetch_side(t);
             put_side();
-            for (int i = threadIdx.x; i < total; i += blockDim.x) put_chunk(i, load_chunk(col0, i));
+            const uint8_t *tb = tile_ptr(t);
+            const int rows = tile_rows(t);
+            for (int i = threadIdx.x; i < total; i += blockDim.x) put_chunk(i, load_chunk(tb, rows, i));
         }
         __syncthreads();
         if (piped && t + 1 < t_end) fetch_tile(t + 1);
@@ -343,21 +377,23 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
         // of each block.  A key can beat a row's list only if its distance
         // part is <= the high half of the row's threshold; that test alone
         // runs on every value, the full one on the few that pass it. ----
-        uint64_t thr[4];
+        uint64_t thr[4];      // 0 for rows past the end: no key is below it
         uint32_t thi[4];
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-            thr[r] = tau[wv * 16 + 4 * kg + r];
-            thi[r] = crow[r] < a.nq ? (uint32_t)(thr[r] >> 32) : 0u;
+            const uint64_t tv = tau[wv * 16 + 4 * kg + r];
+            thr[r] = crow[r] < a.nq ? tv : 0ull;
+            thi[r] = (uint32_t)(thr[r] >> 32);
         }
         uint32_t dd[4][4];
-        bool any = false;
+        uint64_t hit[4];      // per block: lanes with a value that passed the prefilter
 #pragma unroll
         for (int cb = 0; cb < 4; cb++) {
             int32_t bn8 = 0;
             float bnf = 0.0f;
             if constexpr (U8) bn8 = (int32_t)t_norm[cb * 16 + arow];
             else if constexpr (MT == ONNG_L2SQ) bnf = __uint_as_float(t_norm[cb * 16 + arow]);
+            hit[cb] = 0;
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 uint32_t dord;
@@ -369,32 +405,37 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
                     dord = ord_f32(1.0f - accf[cb][r]);
                 }
                 dd[cb][r] = dord;
-                any |= dord <= thi[r];
+                hit[cb] |= ballot(dord <= thi[r]);
             }
         }
-        if (any) {
+        const bool partial = col0 + BN > a.nb;
 #pragma unroll
-            for (int cb = 0; cb < 4; cb++) {
-                const int64_t col = col0 + cb * 16 + arow;
-                if (col >= a.nb) continue;
-                const uint32_t gid = a.b_ids ? t_gid[cb * 16 + arow] : (uint32_t)col;
+        for (int cb = 0; cb < 4; cb++) {
+            if (!hit[cb]) continue;
+            const int64_t col = col0 + cb * 16 + arow;
+            const bool cok = !partial || col < a.nb;
+            const uint32_t gid = a.b_ids ? t_gid[cb * 16 + arow] : (uint32_t)col;
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const uint64_t key = make_key(dd[cb][r], gid);
-                    if (dd[cb][r] <= thi[r] && crow[r] < a.nq && key < thr[r] &&
-                        !(a.exclude_self && (int64_t)gid == crow[r])) {
-                        int lr = wv * 16 + 4 * kg + r;
-                        int slot = atomicAdd(&cnt[lr], 1);
-                        cands[(size_t)lr * CB + slot] = key;
-                    }
+            for (int r = 0; r < 4; r++) {
+                const uint64_t key = make_key(dd[cb][r], gid);
+                if (cok && key < thr[r] && !(a.exclude_self && (int64_t)gid == crow[r])) {
+                    int lr = wv * 16 + 4 * kg + r;
+                    int slot = atomicAdd(&cnt[lr], 1);
+                    cands[(size_t)lr * CB + slot] = key;
                 }
             }
         }
         wave_sync();
         // rows whose buffer could overflow on the next tile
-        for (int r = 0; r < 16; r++) {
-            int lr = wv * 16 + r;
-            if (uni(cnt[lr]) > CB - BN) flush_row(lr);
+        // (or, while its list is still empty, that already hold k keys: the
+        // list then starts from the best k of the first tiles)
+        const int cr = cnt[wv * 16 + (lane & 15)];
+        const int nr = nlist[wv * 16 + (lane & 15)];
+        uint64_t over = ballot(lane < 16 && (cr > CB - BN || (nr == 0 && cr >= a.k)));
+        while (over) {
+            const int r = __builtin_ctzll(over);
+            over &= over - 1;
+            flush_row(wv * 16 + r);
         }
     }
     __syncthreads();
@@ -459,16 +500,24 @@ __global__ void __launch_bounds__(256) merge_parts_kernel(const uint64_t *part, 
     }
 }
 
-// Parts per row block: enough blocks for about four per compute unit, each
-// part keeping at least 8 tiles.
+// Parts per row block.  With one block per compute unit (the LDS holds one
+// block's tile, lists and buffers), the launch takes ceil(blocks / CUs)
+// rounds, each as long as one part: about its tiles plus a few tiles' worth
+// of list warm-up.  The part count minimises that product (parts keep at
+// least 8 tiles).
 int topk_splits(int64_t nq, int64_t nb, int bm) {
     const int64_t row_blocks = (nq + bm - 1) / bm;
     const int64_t ntiles = (nb + BN - 1) / BN;
-    const int64_t want = 4LL * device_cu_count();
-    if (row_blocks >= want || ntiles < 16) return 1;
-    int64_t sp = (want + row_blocks - 1) / row_blocks;
-    sp = std::min<int64_t>(sp, ntiles / 8);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(sp, 64));
+    const int64_t cus = device_cu_count();
+    if (row_blocks >= 4 * cus || ntiles < 16) return 1;
+    const int64_t top = std::min<int64_t>(64, ntiles / 8);
+    int64_t best = 1, best_cost = INT64_MAX;
+    for (int64_t sp = 1; sp <= top; sp++) {
+        const int64_t rounds = (row_blocks * sp + cus - 1) / cus;
+        const int64_t cost = rounds * ((ntiles + sp - 1) / sp + 4);
+        if (cost < best_cost) best = sp, best_cost = cost;
+    }
+    return (int)best;
 }
 
 
