@@ -93,6 +93,8 @@ def parse():
                     help="pad searched rows to a multiple of this many bytes (cache lines)")
     ap.add_argument("--inflight", type=int, default=4,
                     help="query batches in flight in the timed region (one stream each)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the library's default launch shape instead of a tuned one")
     ap.add_argument("--search-only", action="store_true",
                     help="after the index and operating points, only loop the search kernel "
                          "(used under rocprofv3)")
@@ -411,6 +413,23 @@ def main():
                             **{k.replace("@", "_at_").replace("+", "_"): v
                                for k, v in pq_stats.items()})
 
+    # launch shapes: each timed search is tuned once on its own operating
+    # point; later searches and pipelines over the same index use that shape
+    tuned = {}
+    if not args.no_autotune:
+        def shape(c):
+            return dict(waves_per_block=c.waves_per_block, lanes_per_row=c.lanes_per_row,
+                        s_capacity=c.s_capacity, visited_log2=c.visited_log2)
+        if single[0.95]:
+            treq = make_learned_b(0.95, True)(knobs[0.95], budgets[0.95], bfactors[0.95])
+            tuned["learned"] = shape(treq.autotune())
+        p95 = result["plain"]["0.95"]
+        if p95 is not None:
+            treq = A.SearchRequest(base, graph, queries, seeds, k=K, eps=p95["knob"], **idm,
+                                   ep=LR.dynamic_ep(p95["knob"]))
+            tuned["plain"] = shape(treq.autotune())
+        log(f"tuned launch shapes: {tuned}")
+
     # ----------------------------------------------- timed region (graph) --
     pred95 = learned_pred(0.95, knobs[0.95])
     NF = max(1, args.inflight)
@@ -588,6 +607,7 @@ def main():
             "max_dc": {str(t): budgets[t] for t in (0.95, 0.99)},
             "max_dc_factor": {str(t): bfactors[t] for t in (0.95, 0.99)},
             "learned_single_pass": {str(t): single[t] for t in (0.95, 0.99)},
+            "launch_shapes": tuned,
         },
         "recall_at_timed_point": round(rec95, 4),
         "qps": {
@@ -747,9 +767,12 @@ def main_mixed(args, torch):
         torch.cuda.synchronize()
         ms = (time.time() - t0) * 1e3 / args.steps
         cr = class_recall(last.ids.cpu().numpy())
+        dcn = last.dc.cpu().numpy()
+        cdc = {f"k={kk}": round(float(dcn[kq_np == kk].mean()), 1) for kk in KS}
         res[name] = dict(qps=round(cfg.n_query / (ms / 1e3), 1), ms_per_step=round(ms, 3),
                          pool_factor=extra.get("pool_factor", 1),
-                         class_recall=cr, eps={f"k={k},t={t}": v for (k, t), v in eps_of.items()},
+                         class_recall=cr, class_dc=cdc,
+                         eps={f"k={k},t={t}": v for (k, t), v in eps_of.items()},
                          launch=dict(waves_per_block=tuned.waves_per_block,
                                      lanes_per_row=tuned.lanes_per_row,
                                      s_capacity=tuned.s_capacity,
@@ -758,7 +781,8 @@ def main_mixed(args, torch):
             f"class recall {cr}")
         for p_ in pipes:
             p_.close()
-    best = max(("fp8+rerank4", "fp8+rerank2"), key=lambda n: res[n]["qps"])
+    best = max(res, key=lambda n: res[n]["qps"])
+    lp_best = max(("fp8+rerank4", "fp8+rerank2"), key=lambda n: res[n]["qps"])
     out = {
         "metric": "queries/sec, one persistent launch of mixed k and target recall",
         "value": res[best]["qps"],
@@ -771,19 +795,19 @@ def main_mixed(args, torch):
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "storage": "fp8",
+        "storage": "f32" if best == "plain_f32" else "fp8",
         "data": "synthetic",
         "config": {
             "workload": (f"{cfg.name}: {cfg.n_base:,} base + {cfg.n_query:,} queries, dim "
                          f"{cfg.dim}, anisotropic Gaussian mixture of {cfg.n_clusters} clusters, "
                          f"squared L2; kNN k={cfg.knn_k}, e_o={cfg.e_o}/e_i={cfg.e_i}, path "
                          f"adjustment; per-query k in {KS} and target recall in {TS}, "
-                         f"range per class; fp8 rows + f32 rerank of the best "
-                         f"{res[best]['pool_factor']}*100 (timed) vs plain f32 rows"),
+                         f"range per class; timed: {best} (fp8 rows with an f32 rerank of "
+                         f"pool_factor*100, or plain f32 rows: the fastest of the three)"),
             "global_batch": cfg.n_query,
             "batches_in_flight": max(1, args.inflight),
         },
-        "speedup_vs_plain_f32": round(res[best]["qps"] / res["plain_f32"]["qps"], 3),
+        "lp_speedup_vs_plain_f32": round(res[lp_best]["qps"] / res["plain_f32"]["qps"], 3),
         "timed": best,
         "results": res,
         "build_s": build,

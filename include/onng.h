@@ -392,8 +392,10 @@ onng_status onng_autotune_search(const onng_vectors *base, const onng_graph *gra
  * in *handle (host): seed selection against `pivots`, then the search and
  * rerank.  With a predictor the search runs as three steps (a predict-only
  * pass, onng_order_by_cost, and the search with the predicted ranges in that
- * order), or as one fused search when params->single_pass is set.  All
- * pointers must stay valid while the handle lives. */
+ * order), or as one fused search when params->single_pass is set.  The
+ * launch shape is params->launch, else the one onng_autotune_search cached
+ * for this index and parameters, else the default.  All pointers must stay
+ * valid while the handle lives. */
 typedef struct onng_pipeline onng_pipeline;
 onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *graph,
                                  const onng_vectors *queries, const int32_t *pivots,

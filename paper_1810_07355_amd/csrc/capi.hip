@@ -888,6 +888,10 @@ onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *gra
     // seed distances are not needed: write them into the search outputs,
     // which the search overwrites afterwards
     void *seed_d = dists;
+    // the launch shape: the caller's, else a tuned one for this index, else the default
+    onng_launch_config tuned;
+    const onng_launch_config *cfg = params->launch;
+    if (!cfg && lookup_tuned(base, params, &tuned)) cfg = &tuned;
     onng_pipeline *pl = new onng_pipeline();
     onng_status rc = ONNG_OK;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -905,7 +909,7 @@ onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *gra
                          st);
     if (rc == ONNG_OK && (!params->predictor || params->single_pass)) {
         rc = run_search(base, graph, queries, seeds, n_seeds, params, ids, dists, stats, wsa + a,
-                        ws_bytes - a, st, params->launch);
+                        ws_bytes - a, st, cfg);
     } else if (rc == ONNG_OK) {
         // predict the range of every query, order the queries by predicted
         // cost (longest first), then search with the predicted ranges
@@ -926,11 +930,11 @@ onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *gra
         p2.range_from = pst;
         p2.order = order;
         rc = run_search(base, graph, queries, seeds, n_seeds, &p1, ids, dists, pst,
-                        wsa + a + used, ws_bytes - a - used, st, params->launch);
+                        wsa + a + used, ws_bytes - a - used, st, cfg);
         if (rc == ONNG_OK) rc = order_launch(pst, queries->n, order, ows, ob, st);
         if (rc == ONNG_OK)
             rc = run_search(base, graph, queries, seeds, n_seeds, &p2, ids, dists, stats,
-                            wsa + a + used, ws_bytes - a - used, st, params->launch);
+                            wsa + a + used, ws_bytes - a - used, st, cfg);
     }
     hipGraph_t g = nullptr;
     hipError_t ce = hipStreamEndCapture(st, &g);
