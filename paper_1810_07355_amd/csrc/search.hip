@@ -641,11 +641,12 @@ search_kernel(SearchKArgs a) {
                     }
                 }
                 if (na > 0) k0 = wave_sort(k0, pow2_at_least(na));
+                // The guess's reads form a dependent chain (offsets, then
+                // adjacency, then visited bits); each step is issued one
+                // merge after the previous one so that its latency overlaps it.
+                if (na > 0) absorb_pool(k0, na);
                 int nl0 = 0, nl1 = 0;
                 if (go) {
-                    // the marks of this expansion are complete before the
-                    // adjacency and the visited bits of the guess are read
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                     spec_e0 = readlane64(spec_ofs, 0);
                     spec_deg = readlane64(spec_ofs, 1) - spec_e0;
                     nl0 = (int)(spec_deg < WAVE ? spec_deg : WAVE);
@@ -653,9 +654,12 @@ search_kernel(SearchKArgs a) {
                     spec_nb = lane < nl0 ? (uint32_t)a.nbrs[spec_e0 + lane] : 0u;
                     spec_nb1 = lane < nl1 ? (uint32_t)a.nbrs[spec_e0 + WAVE + lane] : 0u;
                 }
-                if (na > 0) absorb_pool(k0, na);
+                if (na > 0) absorb_s(k0, na, true);
                 spec_vis = go && gmode;
                 if (spec_vis) {
+                    // the marks of this expansion are complete before the
+                    // visited bits of the guess are read
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                     spec_bit = false;
                     spec_bit1 = false;
                     if (lane < nl0 && (int64_t)spec_nb < a.n_base) {
@@ -669,7 +673,6 @@ search_kernel(SearchKArgs a) {
                         spec_bit1 = (wd >> (spec_nb1 & 31)) & 1u;
                     }
                 }
-                if (na > 0) absorb_s(k0, na, true);
                 if (nb2 > 0) {
                     k1 = wave_sort(k1, pow2_at_least(nb2));
                     absorb(k1, nb2, true);
