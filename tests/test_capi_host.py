@@ -6,6 +6,8 @@ import os
 import re
 import subprocess
 
+import numpy as np
+
 import pytest
 
 from paper_1810_07355_amd import _lib as L
@@ -149,3 +151,22 @@ def test_other_entry_points_validate(lib):
     assert lib.onng_adjust_degree(p, p, 10, 4, L.U8, L.L2SQ, 2, 2, p, p, p, 80, C.byref(nnz), p,
                                   16, None) == L.ERR_WORKSPACE
     assert lib.onng_pipeline_destroy(None) == L.OK
+
+
+def test_recall_by_ids_definition():
+    """recall@k by ids: the share of the k true neighbour ids among the first
+    k returned ids; padding (-1) never counts, order does not matter."""
+    from paper_1810_07355_amd import learned as LR
+    gt = np.array([[3, 1, 4, 9], [2, 7, 1, 8]], dtype=np.int32)
+    res = np.array([[4, 3, 5, 1], [-1, 8, 7, 2]], dtype=np.int32)
+    assert np.allclose(LR.recall_by_ids(res, gt, 4), [3 / 4, 3 / 4])
+    assert np.allclose(LR.recall_by_ids(res, gt, 2), [1 / 2, 0.0])
+    assert np.allclose(LR.recall_by_ids(gt, gt, 4), [1.0, 1.0])
+    g = np.random.default_rng(3)
+    a = g.integers(0, 50, size=(20, 10)).astype(np.int32)
+    b = np.stack([g.permutation(50)[:10] for _ in range(20)]).astype(np.int32)
+    brute = [sum(1 for x in set(a[i].tolist()) if x in set(b[i].tolist())) for i in range(20)]
+    # a result with repeated ids counts each repetition (the search never repeats one)
+    rep = [sum(1 for x in a[i].tolist() if x in set(b[i].tolist())) for i in range(20)]
+    assert np.allclose(LR.recall_by_ids(a, b, 10) * 10, rep)
+    assert all(r >= u for r, u in zip(rep, brute))

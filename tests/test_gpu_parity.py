@@ -546,6 +546,40 @@ def test_rerank_standalone_matches_oracle():
             assert np.allclose(host(d), rd, rtol=0, atol=2e-6)
 
 
+def test_ground_truth_and_recall_against_oracle():
+    """The measurement path: exact top-k of float rows (f32 screen of k+64,
+    fp64 rerank) against the oracle's fp64 brute force, with more rows than
+    one tile and a ragged tail; recall@k of that result against itself is 1,
+    and the library's recall by ids agrees with the oracle's tie-tolerant
+    recall on a perturbed result."""
+    say("ground truth")
+    A = api()
+    from paper_1810_07355_amd import learned as LR
+    for kind, metric in (("f32cos", orc.COS), ("f32", orc.L2SQ)):
+        x = dg.random_vectors(3001, 48, kind, 31)
+        q = dg.random_vectors(67, 48, kind, 32)
+        bv, qv = orc.Vectors.from_array(x, metric), orc.Vectors.from_array(q, metric)
+        for k in (1, 10, 100):
+            rid, rd = orc.topk(qv, bv, k)
+            ids, d = A.ground_truth(gpu_vectors(q, metric), gpu_vectors(x, metric), k)
+            gi, gd = host(ids), host(d)
+            assert np.array_equal(gi, rid), (kind, k)
+            assert np.allclose(gd, rd, rtol=1e-6, atol=1e-7), (kind, k)
+            assert np.all(LR.recall_by_ids(gi, rid, k) == 1.0)
+            # drop the last true neighbour of every query for the next one out
+            if k > 1:
+                nxt, nd = orc.topk(qv, bv, k + 1)
+                pert = gi.copy()
+                pert[:, k - 1] = nxt[:, k]
+                pd = rd.copy()
+                pd[:, k - 1] = nd[:, k]
+                by_ids = LR.recall_by_ids(pert, rid, k)
+                tol = orc.recall_at_k(pert, pd, rd, k)
+                assert np.allclose(by_ids, (k - 1) / k)
+                # ties with the k-th true distance count in the oracle's recall only
+                assert np.all(tol >= by_ids - 1e-12)
+
+
 # ------------------------------------------------------------------- MLP
 
 def test_mlp_forward_backward_adam_against_oracle():
