@@ -313,11 +313,17 @@ onng_status onng_order_by_cost(const onng_query_stats *stats, int64_t n, int32_t
 size_t onng_order_by_cost_workspace_size(int64_t n);
 
 /* Locality order of a base (not part of the paper; a memory layout for the
- * search): perm[0..n) lists the rows grouped by their nearest pivot (pivot
- * ids ascending, rows ascending within a group), so that objects close in
- * space get close positions.  Searching rows gathered in this order touches
- * fewer cache lines and fewer bits of the visited set per query.  pivots:
- * [n_pivots] row ids of `base` (device).  ws: onng_locality_order_workspace_size.
+ * search): perm[0..n) lists the rows grouped by their nearest pivot (rows
+ * ascending within a group), and the groups follow a hierarchical order of
+ * the pivots, so that objects close in space get close positions.  Level 0
+ * is `pivots` as given; level i + 1 is every 10th pivot of level i, up to the
+ * first level with at most 16.  The top level keeps its given order; each
+ * level below is ordered by (position of each pivot's nearest pivot of the
+ * ordered level above, its own position); the rows likewise against the
+ * ordered level 0.  Nearest means smallest (distance, id), as everywhere.
+ * Searching rows gathered in this order touches fewer cache lines and fewer
+ * words of the visited set per query.  pivots: [n_pivots] row ids of `base`
+ * (device), n_pivots <= n.  ws: onng_locality_order_workspace_size.
  * A graph built on the reordered rows has reordered ids; search outputs are
  * mapped back with onng_search_params.id_map = perm. */
 onng_status onng_locality_order(const onng_vectors *base, const int32_t *pivots,

@@ -458,11 +458,31 @@ static onng_status order_launch(const onng_query_stats *st, int64_t n, int32_t *
 
 // ------------------------------------------------------ locality order ---
 
-__global__ void nearest_key_kernel(const int32_t *nn, int64_t n, uint32_t *key, int32_t *idx) {
+// key[i] = position of row i's nearest pivot in the ordered pivot list
+__global__ void nearest_key_kernel(const int32_t *nn, int64_t n, const int32_t *pos_of,
+                                   uint32_t *key, int32_t *idx) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    key[i] = (uint32_t)nn[i];
+    key[i] = (uint32_t)pos_of[nn[i]];
     idx[i] = (int32_t)i;
+}
+
+// pos_of[ids[j]] = j
+__global__ void position_kernel(const int32_t *ids, int64_t m, int32_t *pos_of) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m) pos_of[ids[j]] = (int32_t)j;
+}
+
+// dst[j] = src[j * stride]
+__global__ void strided_kernel(const int32_t *src, int64_t m, int stride, int32_t *dst) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m) dst[j] = src[j * stride];
+}
+
+// dst[j] = src[idx[j]]
+__global__ void permute_kernel(const int32_t *src, const int32_t *idx, int64_t m, int32_t *dst) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m) dst[j] = src[idx[j]];
 }
 
 __global__ void gather_bytes_kernel(const uint8_t *src, int64_t pitch, const int32_t *ids,
@@ -483,15 +503,46 @@ static size_t locality_sort_bytes(int64_t n) {
     return bytes;
 }
 
+// Pivot levels of the locality order: level 0 is the given pivots, level
+// i + 1 every LOC_STRIDE-th pivot of level i, up to the first level with at
+// most LOC_TOP pivots.
+constexpr int LOC_STRIDE = 10, LOC_TOP = 16;
+
+static std::vector<int64_t> locality_levels(int64_t n_pivots) {
+    std::vector<int64_t> sz{n_pivots};
+    while (sz.back() > LOC_TOP) sz.push_back((sz.back() + LOC_STRIDE - 1) / LOC_STRIDE);
+    return sz;
+}
+
+// top-k workspace of the largest pass: the rows against level 0, level i
+// against level i + 1
+static size_t locality_topk_ws(const onng_vectors *base, const std::vector<int64_t> &sz) {
+    size_t w = topk_ws_size(base, base, sz[0], 1);
+    for (size_t i = 1; i < sz.size(); i++) {
+        onng_vectors q = *base;
+        q.n = sz[i - 1];
+        w = std::max(w, topk_ws_size(&q, base, sz[i], 1));
+    }
+    return w;
+}
+
 static size_t locality_ws(const onng_vectors *base, int64_t n_pivots) {
+    const std::vector<int64_t> sz = locality_levels(n_pivots);
+    int64_t lv = 0;
+    for (int64_t m : sz) lv += m;
     Carver c(nullptr);
     c.take<int32_t>(base->n);                 // nearest pivot
     c.take<float>(base->n);                   // its distance (unused)
     c.take<uint32_t>(base->n);
     c.take<uint32_t>(base->n);
     c.take<int32_t>(base->n);
-    c.take<char>(locality_sort_bytes(base->n));
-    c.take<char>(topk_ws_size(base, base, n_pivots, 1));
+    c.take<int32_t>(base->n);                 // position of an id in an ordered level
+    c.take<int32_t>(base->n);                 // sorted index
+    c.take<int32_t>(lv);                      // the levels, as given
+    c.take<int32_t>(lv);                      // the levels, ordered
+    c.take<uint8_t>((size_t)n_pivots * base->pitch_bytes);   // rows of one level
+    c.take<char>(locality_sort_bytes(std::max(base->n, n_pivots)));
+    c.take<char>(locality_topk_ws(base, sz));
     return c.size() + 256;
 }
 
@@ -709,7 +760,7 @@ onng_status onng_locality_order(const onng_vectors *base, const int32_t *pivots,
                                 void *stream) {
     set_error("");
     ONNG_TRY(check_vectors(base, "base"));
-    ONNG_CHECK_ARG(pivots && perm && n_pivots >= 1, "bad arguments");
+    ONNG_CHECK_ARG(pivots && perm && n_pivots >= 1 && n_pivots <= base->n, "bad arguments");
     ONNG_CHECK_ARG(base->dtype == ONNG_U8 || base->dtype == ONNG_F32, "base must be u8 or f32");
     ONNG_CHECK_ARG(base->n < (int64_t)INT32_MAX, "too many rows");
     if (!ws || ws_bytes < locality_ws(base, n_pivots)) {
@@ -719,22 +770,63 @@ onng_status onng_locality_order(const onng_vectors *base, const int32_t *pivots,
     const int64_t n = base->n;
     if (n == 0) return ONNG_OK;
     hipStream_t st = as_stream(stream);
+    const std::vector<int64_t> sz = locality_levels(n_pivots);
+    const int top = (int)sz.size() - 1;
+    int64_t lv = 0;
+    for (int64_t m : sz) lv += m;
     Carver c(ws);
     int32_t *nn = c.take<int32_t>(n);
     float *nd = c.take<float>(n);
     uint32_t *key = c.take<uint32_t>(n);
     uint32_t *key_sorted = c.take<uint32_t>(n);
     int32_t *idx = c.take<int32_t>(n);
-    size_t tb = locality_sort_bytes(n);
+    int32_t *pos_of = c.take<int32_t>(n);
+    int32_t *sidx = c.take<int32_t>(n);
+    int32_t *given = c.take<int32_t>(lv);
+    int32_t *ordered = c.take<int32_t>(lv);
+    uint8_t *rows = c.take<uint8_t>((size_t)n_pivots * base->pitch_bytes);
+    size_t tb = locality_sort_bytes(std::max(n, n_pivots));
     void *tmp = c.take<char>(tb);
-    size_t tkb = topk_ws_size(base, base, n_pivots, 1);
+    size_t tkb = locality_topk_ws(base, sz);
     void *tk = c.take<char>(tkb);
-    ONNG_TRY(launch_topk(base, base, pivots, n_pivots, 1, 0, nn, nd, tk, tkb, st));
-    hipLaunchKernelGGL(nearest_key_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, nn,
-                       n, key, idx);
-    // radix sort is stable: rows stay ascending within a pivot's group
-    ONNG_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, key, key_sorted, idx, perm, (int)n, 0,
-                                                32, st));
+    auto blocks = [](int64_t m) { return dim3((unsigned)((m + 255) / 256)); };
+    std::vector<int64_t> at(sz.size(), 0);    // offset of each level in given/ordered
+    for (size_t i = 1; i < sz.size(); i++) at[i] = at[i - 1] + sz[i - 1];
+    ONNG_HIP(hipMemcpyAsync(given, pivots, sizeof(int32_t) * n_pivots, hipMemcpyDeviceToDevice,
+                            st));
+    for (int i = 1; i <= top; i++)
+        hipLaunchKernelGGL(strided_kernel, blocks(sz[i]), dim3(256), 0, st, given + at[i - 1],
+                           sz[i], LOC_STRIDE, given + at[i]);
+    ONNG_HIP(hipMemcpyAsync(ordered + at[top], given + at[top], sizeof(int32_t) * sz[top],
+                            hipMemcpyDeviceToDevice, st));
+    // Order level i: its pivots by (position of their nearest pivot of the
+    // ordered level i + 1, position in level i); then the rows the same way
+    // against the ordered level 0.  Stable radix sorts keep the second key.
+    for (int i = top; i >= 0; i--) {
+        const int32_t *cand = ordered + at[i];
+        const int64_t m = sz[i];
+        hipLaunchKernelGGL(position_kernel, blocks(m), dim3(256), 0, st, cand, m, pos_of);
+        const bool rows_pass = i == 0;
+        const int64_t nq = rows_pass ? n : sz[i - 1];
+        onng_vectors Q = *base;
+        if (!rows_pass) {
+            hipLaunchKernelGGL(gather_bytes_kernel, dim3((unsigned)nq), dim3(64), 0, st,
+                               static_cast<const uint8_t *>(base->data), base->pitch_bytes,
+                               given + at[i - 1], nq, rows);
+            Q.data = rows;
+            Q.n = nq;
+            Q.scale = nullptr;
+        }
+        ONNG_TRY(launch_topk(&Q, base, cand, m, 1, 0, nn, nd, tk, tkb, st));
+        hipLaunchKernelGGL(nearest_key_kernel, blocks(nq), dim3(256), 0, st, nn, nq, pos_of, key,
+                           idx);
+        int32_t *out = rows_pass ? perm : sidx;
+        ONNG_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, key, key_sorted, idx, out, (int)nq, 0,
+                                                    32, st));
+        if (!rows_pass)
+            hipLaunchKernelGGL(permute_kernel, blocks(nq), dim3(256), 0, st, given + at[i - 1],
+                               sidx, nq, ordered + at[i - 1]);
+    }
     ONNG_HIP(hipGetLastError());
     return ONNG_OK;
 }

@@ -272,18 +272,44 @@ def test_search_mixed_k_eps_ep_per_query():
     assert np.array_equal(host(r.hops), ref["hops"])
 
 
+def _locality_order_reference(bv, pivots):
+    """The hierarchical locality order written out with the oracle's top-1:
+    levels of every 10th pivot up to at most 16; each level (and finally the
+    rows) sorted by (position of the nearest pivot of the ordered level above,
+    own position)."""
+    levels = [np.asarray(pivots, dtype=np.int32)]
+    while len(levels[-1]) > 16:
+        levels.append(levels[-1][::10])
+    ordered = levels[-1]
+    for lv in reversed(levels[:-1]):
+        nn, _ = orc.topk(bv, bv, 1, q_rows=lv, cand=ordered)
+        pos = {int(v): j for j, v in enumerate(ordered)}
+        key = np.array([pos[int(v)] for v in nn[:, 0]])
+        ordered = lv[np.lexsort((np.arange(len(lv)), key))]
+    nn, _ = orc.topk(bv, bv, 1, cand=ordered)
+    pos = {int(v): j for j, v in enumerate(ordered)}
+    key = np.array([pos[int(v)] for v in nn[:, 0]])
+    return np.lexsort((np.arange(len(key)), key)).astype(np.int32)
+
+
 def test_locality_order_gather_and_id_map():
-    """The locality order sorts rows by (nearest pivot, row) with the nearest
-    pivot by (distance, id) as the oracle's top-1; rows gather exactly; an id
-    map rewrites only the output ids."""
+    """The locality order against its definition (the oracle's top-1 by
+    (distance, id) at every level); rows gather exactly; an id map rewrites
+    only the output ids."""
     P = c1_problem()
     A, Lb = api(), L()
     say("locality order")
     B = gpu_vectors(P["x"], orc.L2SQ)
     perm = host(A.locality_order(B, to_dev(P["piv"])))
-    nn, _ = orc.topk(P["bv"], P["bv"], 1, cand=P["piv"])
-    want = np.lexsort((np.arange(len(perm)), nn[:, 0]))
-    assert np.array_equal(perm, want)
+    assert len(P["piv"]) > 160            # three levels
+    assert np.array_equal(perm, _locality_order_reference(P["bv"], P["piv"]))
+    # fewer than 17 pivots: one level, rows by (nearest pivot's position, row)
+    few = P["piv"][:12][::-1].copy()
+    perm12 = host(A.locality_order(B, to_dev(few)))
+    nn, _ = orc.topk(P["bv"], P["bv"], 1, cand=few)
+    pos = {int(v): j for j, v in enumerate(few)}
+    want = np.lexsort((np.arange(len(perm12)), [pos[int(v)] for v in nn[:, 0]]))
+    assert np.array_equal(perm12, want)
     xg = host(A.gather_rows(to_dev(P["x"]), to_dev(perm)))
     assert np.array_equal(xg, P["x"][perm])
     po, pn, _ = P["pa"]
