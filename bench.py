@@ -380,7 +380,7 @@ def main():
         for fused in (False, True):
             pt = best_over_budgets(make_learned_b(tgt, fused), tgt, 2.0, 9.0,
                                    f"learned{'-fused' if fused else ''}@{tgt}",
-                                   factors=(0.0, 2.0, 4.0))
+                                   factors=(0.0, 1.25, 1.5, 2.0, 4.0))
             if pt is not None:
                 pt["single_pass"] = fused
                 if best is None or pt["qps"] > best["qps"]:
