@@ -71,8 +71,8 @@ def measured_traffic():
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c5"],
                     help="c3: the headline (learned + low precision vs plain f32); c5: one "
                          "persistent launch of queries with mixed k and target recall")
@@ -146,7 +146,8 @@ def main():
     K = 10
     NS = 8
     # label grid of the learned range: fine where recall climbs, coarse above
-    grid = ([round(0.01 * i, 2) for i in range(0, 21)] + [0.225, 0.25, 0.3, 0.4, 0.6, 1.0])
+    grid = sorted(set([round(0.005 * i, 3) for i in range(0, 10)] +
+                      [round(0.01 * i, 2) for i in range(0, 21)] + [0.225, 0.25, 0.3, 0.4, 0.6, 1.0]))
     targets = (0.9, 0.95, 0.99)
 
     # ------------------------------------------------------------ inputs --
@@ -286,8 +287,16 @@ def main():
     # each query then takes the candidate with the best recall minus
     # lambda * cost, with one lambda calibrated per target recall.
     PROBE = args.probe_hops
-    cand = {0.95: [0.05, 0.07, 0.09, 0.10, 0.11, 0.12, 0.14, 0.17],
-            0.99: [0.10, 0.13, 0.15, 0.17, 0.19, 0.20, 0.25, 0.30]}
+    # candidate ranges per target: around the plain method's range for that
+    # target (multiples of it, snapped to the label grid)
+    cand = {}
+    for tgt, dflt in ((0.95, 0.11), (0.99, 0.18)):
+        pt = result["plain"][str(tgt)]
+        e0 = pt["knob"] if pt is not None and pt["knob"] > 0 else dflt
+        ga = np.array(grid)
+        cand[tgt] = [float(ga[int(np.argmin(np.abs(ga - e0 * m)))])
+                     for m in (0.45, 0.63, 0.8, 0.9, 1.0, 1.1, 1.3, 1.6)]
+    log(f"candidate ranges of the learned range: {cand}")
     EPF = LR.dynamic_ep(0.11)
     search_rows = lp_rows if lp_rows is not None else base
     rr = dict(rerank_base=base, pool_factor=4) if lp_rows is not None else {}
@@ -342,7 +351,7 @@ def main():
     # Distance-computation budgets bound the rare very long queries, which
     # otherwise set the batch time.  Each variant gets the budget (a multiple
     # of the plain operating point's mean count, or none) that serves it best.
-    def best_over_budgets(make_b, tgt, lo, hi, name, factors=(0.0,)):
+    def best_over_budgets(make_b, tgt, lo, hi, name, factors=(0.0,), collect=None):
         base_pt = result["plain"][str(tgt)]
         mults = [0, 1.5, 2.0, 3.0, 4.0] if factors == (0.0,) else [0, 1.5, 2.0, 3.0]
         best = None
@@ -354,6 +363,8 @@ def main():
                 if pt is not None:
                     pt["max_dc"] = b
                     pt["max_dc_factor"] = fac
+                    if collect is not None:
+                        collect.append(pt)
                     if best is None or pt["qps"] > best["qps"]:
                         best = pt
         return best
@@ -375,26 +386,37 @@ def main():
             return req
         return make
 
+    # every budget setting of both forms (three steps / fused), each at its
+    # own lambda for the target; the best by search time for now
+    learned_var = {}
     for tgt in (0.95, 0.99):
         best = None
+        learned_var[tgt] = []
         for fused in (False, True):
+            got = []
             pt = best_over_budgets(make_learned_b(tgt, fused), tgt, 2.0, 9.0,
                                    f"learned{'-fused' if fused else ''}@{tgt}",
-                                   factors=(0.0, 1.25, 1.5, 2.0, 4.0))
-            if pt is not None:
-                pt["single_pass"] = fused
-                if best is None or pt["qps"] > best["qps"]:
-                    best = pt
+                                   factors=(0.0, 1.25, 1.5, 2.0, 4.0), collect=got)
+            for p_ in got:
+                p_["single_pass"] = fused
+            learned_var[tgt] += got
+            if pt is not None and (best is None or pt["qps"] > best["qps"]):
+                best = pt
         learned_pts[str(tgt)] = best
     result["learned"] = learned_pts
-    knobs = {t: (learned_pts[str(t)]["knob"] if learned_pts[str(t)] else 9.0)
-             for t in (0.95, 0.99)}
-    budgets = {t: (learned_pts[str(t)]["max_dc"] if learned_pts[str(t)] else 0)
-               for t in (0.95, 0.99)}
-    bfactors = {t: (learned_pts[str(t)]["max_dc_factor"] if learned_pts[str(t)] else 0.0)
-                for t in (0.95, 0.99)}
-    single = {t: bool(learned_pts[str(t)]["single_pass"]) if learned_pts[str(t)] else False
-              for t in (0.95, 0.99)}
+
+    def learned_params():
+        knobs = {t: (learned_pts[str(t)]["knob"] if learned_pts[str(t)] else 9.0)
+                 for t in (0.95, 0.99)}
+        budgets = {t: (learned_pts[str(t)]["max_dc"] if learned_pts[str(t)] else 0)
+                   for t in (0.95, 0.99)}
+        bfactors = {t: (learned_pts[str(t)]["max_dc_factor"] if learned_pts[str(t)] else 0.0)
+                    for t in (0.95, 0.99)}
+        single = {t: bool(learned_pts[str(t)]["single_pass"]) if learned_pts[str(t)] else False
+                  for t in (0.95, 0.99)}
+        return knobs, budgets, bfactors, single
+
+    knobs, budgets, bfactors, single = learned_params()
     # the same budgets without the learned range, for comparison
     if lp_rows is not None:
         make_lp_b = lambda e, b, fac=0.0: A.SearchRequest(lp_rows, graph, queries, seeds, k=K, eps=e, **idm,
@@ -420,8 +442,11 @@ def main():
         def shape(c):
             return dict(waves_per_block=c.waves_per_block, lanes_per_row=c.lanes_per_row,
                         s_capacity=c.s_capacity, visited_log2=c.visited_log2)
-        if single[0.95]:
-            treq = make_learned_b(0.95, True)(knobs[0.95], budgets[0.95], bfactors[0.95])
+        fv = max((p_ for p_ in learned_var[0.95] if p_["single_pass"]), key=lambda p_: p_["qps"],
+                 default=None)
+        if fv is not None:
+            # both forms of the learned pipeline look this shape up
+            treq = make_learned_b(0.95, True)(fv["knob"], fv["max_dc"], fv["max_dc_factor"])
             tuned["learned"] = shape(treq.autotune())
         p95 = result["plain"]["0.95"]
         if p95 is not None:
@@ -431,20 +456,7 @@ def main():
         log(f"tuned launch shapes: {tuned}")
 
     # ----------------------------------------------- timed region (graph) --
-    pred95 = learned_pred(0.95, knobs[0.95])
     NF = max(1, args.inflight)
-    # one pipeline (own outputs and workspace) and one stream per batch in flight
-    pipes = [A.Pipeline(search_rows, graph, queries, piv, NS, k=K, eps=0.0, ep=L.EP_INF, **idm,
-                        two_phase=True, ep_first=EPF, probe_hops=PROBE, predictor=pred95,
-                        max_dc=budgets[0.95], max_dc_factor=bfactors[0.95],
-                        single_pass=single[0.95], **rr)
-             for _ in range(NF)]
-    pipe = pipes[0]
-    plain95 = result["plain"]["0.95"]
-    pipes_plain = []
-    if plain95 is not None:
-        pipes_plain = [A.Pipeline(base, graph, queries, piv, NS, k=K, eps=plain95["knob"], **idm,
-                                  ep=LR.dynamic_ep(plain95["knob"])) for _ in range(NF)]
     streams = [torch.cuda.Stream(device=dev) for _ in range(NF)]
 
     def run_steps(pl, n):
@@ -460,6 +472,53 @@ def main():
             cur.wait_stream(s_)
         return last
 
+    def learned_pipes(tgt, pt):
+        pred = learned_pred(tgt, pt["knob"])
+        return [A.Pipeline(search_rows, graph, queries, piv, NS, k=K, eps=0.0, ep=L.EP_INF, **idm,
+                           two_phase=True, ep_first=EPF, probe_hops=PROBE, predictor=pred,
+                           max_dc=pt["max_dc"], max_dc_factor=pt["max_dc_factor"],
+                           single_pass=pt["single_pass"], **rr) for _ in range(NF)]
+
+    # The learned pipeline's setting (form and budget) is chosen by a short
+    # pipelined run of every setting: the batches in flight hide tails that
+    # the single-batch search time counts, so its ranking is not the
+    # pipeline's.
+    sel_steps = max(5, args.steps // 4)
+    for tgt in (0.95, 0.99):
+        forms = sorted(learned_var[tgt], key=lambda p_: -p_["qps"])
+        if len(forms) < 2:
+            continue
+        rates = []
+        for pt in forms:
+            pl = learned_pipes(tgt, pt)
+            run_steps(pl, args.warmup)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            run_steps(pl, sel_steps)
+            torch.cuda.synchronize()
+            rates.append(queries.n / ((time.time() - t0) / sel_steps))
+            for p_ in pl:
+                p_.close()
+            pt["selection_pipeline_qps"] = round(rates[-1], 1)
+        learned_pts[str(tgt)] = forms[int(np.argmax(rates))]
+        log(f"learned settings at {tgt} (pipelined q/s): " + ", ".join(
+            f"{'fused' if pt['single_pass'] else '3-step'} b={pt['max_dc']} "
+            f"f={pt['max_dc_factor']:g} dc={pt['dc']:.0f} {r:.0f}" for pt, r in zip(forms, rates)))
+    knobs, budgets, bfactors, single = learned_params()
+
+    pred95 = learned_pred(0.95, knobs[0.95])
+    # one pipeline (own outputs and workspace) and one stream per batch in flight
+    pipes = [A.Pipeline(search_rows, graph, queries, piv, NS, k=K, eps=0.0, ep=L.EP_INF, **idm,
+                        two_phase=True, ep_first=EPF, probe_hops=PROBE, predictor=pred95,
+                        max_dc=budgets[0.95], max_dc_factor=bfactors[0.95],
+                        single_pass=single[0.95], **rr)
+             for _ in range(NF)]
+    pipe = pipes[0]
+    plain95 = result["plain"]["0.95"]
+    pipes_plain = []
+    if plain95 is not None:
+        pipes_plain = [A.Pipeline(base, graph, queries, piv, NS, k=K, eps=plain95["knob"], **idm,
+                                  ep=LR.dynamic_ep(plain95["knob"])) for _ in range(NF)]
     if args.search_only:
         req = make_learned_b(0.95, single[0.95])(knobs[0.95], budgets[0.95], bfactors[0.95])
         for _ in range(args.warmup + args.steps):
@@ -574,9 +633,10 @@ def main():
             done += m
             n = min(4 * n, 4096)
         cpu = dict(value=round(done / spent, 1), unit="queries/s", cores=thr, kind="oracle",
-                   sample=f"first {done} queries of the workload, plain f32 search at "
-                          f"eps={eps0} (the f32 operating point for recall 0.95), fp64 "
-                          f"distances, {thr} threads")
+                   sample=f"first {done} queries of the workload, plain "
+                          f"{'u8' if is_u8 else 'f32'} search at eps={eps0} (its operating "
+                          f"point for recall 0.95), "
+                          f"{'exact int' if is_u8 else 'fp64'} distances, {thr} threads")
         log(f"cpu oracle: {done} queries in {spent:.1f} s on {thr} threads")
 
     def qps_of(pt):
