@@ -30,7 +30,12 @@ typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BN = 64;        // base rows per tile
-constexpr int CB = 128;       // candidate slots per query row
+// Per-row list capacity (k rounded up to 8 keys) and candidate slots: a
+// tile adds at most BN candidates to a row, whose buffer is merged once it
+// holds more than cb - BN.  Small k takes 80 slots (merges after 16
+// candidates), which halves the buffer's LDS.
+__host__ __device__ inline int topk_kcap(int k) { return (k + 7) / 8 * 8; }
+__host__ __device__ inline int topk_cb(int k) { return k <= 16 ? 80 : 128; }
 
 // A staged row is NCH * 64 bytes: u8, NCH k-steps of 64 components (a lane
 // feeds 16 of them per step); f32, 4 k-groups of KQ = 4 * NCH components,
@@ -61,7 +66,8 @@ struct TopkArgs {
     const void *bn;           // base norms
     int32_t dim;
     int32_t k;
-    int32_t kcap;             // list capacity per row (>= k, multiple of 64)
+    int32_t kcap;             // list capacity per row (topk_kcap)
+    int32_t cb;               // candidate slots per row (topk_cb)
     int32_t bm;               // query rows per block (16 per wave)
     int32_t exclude_self;
     int32_t lds_pitch;        // bytes per staged base row
@@ -137,14 +143,14 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
     const int nwaves = a.bm / 16;
     const int64_t row0 = (int64_t)blockIdx.x * a.bm;
 
-    // LDS: [B tile][lists bm*kcap][cands bm*CB][tau bm][cnt bm][nlist bm][stage nwaves*64]
+    // LDS: [B tile][lists bm*kcap][cands bm*cb][tau bm][cnt bm][nlist bm][stage nwaves*64]
     char *p = smem;
     uint8_t *btile = reinterpret_cast<uint8_t *>(p);
     p += (size_t)BN * a.lds_pitch;
     uint64_t *lists = reinterpret_cast<uint64_t *>(p);
     p += (size_t)a.bm * a.kcap * 8;
     uint64_t *cands = reinterpret_cast<uint64_t *>(p);
-    p += (size_t)a.bm * CB * 8;
+    p += (size_t)a.bm * a.cb * 8;
     uint64_t *tau = reinterpret_cast<uint64_t *>(p);
     p += (size_t)a.bm * 8;
     int32_t *cnt = reinterpret_cast<int32_t *>(p);
@@ -205,7 +211,7 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
         uint64_t *lst = lists + (size_t)lr * a.kcap;
         int nl = uni(nlist[lr]);
         for (int c0 = 0; c0 < n; c0 += WAVE) {
-            uint64_t key = c0 + lane < n ? cands[(size_t)lr * CB + c0 + lane] : KEY_MAX;
+            uint64_t key = c0 + lane < n ? cands[(size_t)lr * a.cb + c0 + lane] : KEY_MAX;
             int nb = min(WAVE, n - c0);
             key = wave_sort(key, pow2_at_least(nb));
             int total = merge_sorted(lst, 0, nl, key, nb, a.k, stage, NoSpill());
@@ -421,7 +427,7 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
                 if (cok && key < thr[r] && !(a.exclude_self && (int64_t)gid == crow[r])) {
                     int lr = wv * 16 + 4 * kg + r;
                     int slot = atomicAdd(&cnt[lr], 1);
-                    cands[(size_t)lr * CB + slot] = key;
+                    cands[(size_t)lr * a.cb + slot] = key;
                 }
             }
         }
@@ -431,7 +437,7 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
         // list then starts from the best k of the first tiles)
         const int cr = cnt[wv * 16 + (lane & 15)];
         const int nr = nlist[wv * 16 + (lane & 15)];
-        uint64_t over = ballot(lane < 16 && (cr > CB - BN || (nr == 0 && cr >= a.k)));
+        uint64_t over = ballot(lane < 16 && (cr > a.cb - BN || (nr == 0 && cr >= a.k)));
         while (over) {
             const int r = __builtin_ctzll(over);
             over &= over - 1;
@@ -553,9 +559,9 @@ const void *topk_fn_for(int nch) {
     }
 }
 
-size_t topk_lds_bytes(int bm, int kcap, int lds_pitch, int side_words = 0) {
+size_t topk_lds_bytes(int bm, int kcap, int cb, int lds_pitch, int side_words = 0) {
     int nwaves = bm / 16;
-    return (size_t)BN * lds_pitch + (size_t)bm * kcap * 8 + (size_t)bm * CB * 8 + (size_t)bm * 16 +
+    return (size_t)BN * lds_pitch + (size_t)bm * kcap * 8 + (size_t)bm * cb * 8 + (size_t)bm * 16 +
            (size_t)nwaves * WAVE * 8 + (size_t)side_words * BN * 4;
 }
 
@@ -566,9 +572,10 @@ int topk_side_words(int dtype, int metric, bool cand) {
 }
 
 int topk_bm(int32_t k, int dtype, int32_t dim, int side_words) {
-    const int kcap = (k + 63) / 64 * 64;
+    const int kcap = topk_kcap(k);
     const int lp = lds_pitch_for(dtype, dim);
-    return kcap <= 128 && topk_lds_bytes(64, kcap, lp, side_words) <= 160 * 1024 ? 64 : 32;
+    return kcap <= 128 && topk_lds_bytes(64, kcap, topk_cb(k), lp, side_words) <= 160 * 1024 ? 64
+                                                                                            : 32;
 }
 
 }  // namespace
@@ -650,7 +657,8 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     a.bn = bn;
     a.dim = Q->dim;
     a.k = k;
-    a.kcap = (k + 63) / 64 * 64;
+    a.kcap = topk_kcap(k);
+    a.cb = topk_cb(k);
     const int side_words = topk_side_words(Q->dtype, Q->metric, cand != nullptr);
     a.side_norms = Q->dtype == ONNG_U8 || Q->metric == ONNG_L2SQ;
     a.bm = topk_bm(k, Q->dtype, Q->dim, side_words);
@@ -659,7 +667,7 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     a.lds_pitch = lds_pitch_for(Q->dtype, B->dim);
     a.out_ids = ids;
     a.out_d = dists;
-    size_t lds = topk_lds_bytes(a.bm, a.kcap, a.lds_pitch, side_words);
+    size_t lds = topk_lds_bytes(a.bm, a.kcap, a.cb, a.lds_pitch, side_words);
     if (lds > 160 * 1024) {
         set_error("onng_topk: k or dim too large for the on-chip tile");
         return ONNG_ERR_UNSUPPORTED;
