@@ -483,7 +483,7 @@ def main():
     # pipelined run of every setting: the batches in flight hide tails that
     # the single-batch search time counts, so its ranking is not the
     # pipeline's.
-    sel_steps = max(5, args.steps // 4)
+    sel_steps = max(5, args.steps // 2)
     for tgt in (0.95, 0.99):
         forms = sorted(learned_var[tgt], key=lambda p_: -p_["qps"])
         if len(forms) < 2:
