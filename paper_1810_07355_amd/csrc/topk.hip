@@ -3,13 +3,15 @@
 // The distance matrix is |x|^2 + |y|^2 - 2<x, y>; the dot products are the
 // dense contraction and run on MFMA: int8 x int8 -> int32 (16x16x64) for u8
 // data, after shifting every component by -128 (the shift cancels in x - y,
-// and |<x', y'>| <= 128^3 keeps int32 exact), f32 x f32 -> f32 (16x16x4)
+// and |<x', y'>| <= dim * 128^2 keeps int32 exact for dim <= 512), f32 x f32
+// -> f32 (16x16x4)
 // for float data.  Cosine distance on unit vectors is 1 - <x, y>.
 //
 // A block owns BM query rows (16 per wave) and sweeps the base rows in tiles
 // of 64 staged in LDS.  Each row keeps its current k best keys sorted in LDS
 // and a buffer of candidates that beat its k-th key; the buffer is sorted and
-// merged into the list when it could overflow on the next tile and at the end.
+// merged into the list when it could overflow on the next tile, as soon as it
+// holds k keys while the list is empty, and at the end.
 // When the query rows alone give too few blocks to fill the chip (e.g. seed
 // selection for one query batch), the base tiles are split among several
 // blocks per row block, each writes its k best keys, and a second kernel
