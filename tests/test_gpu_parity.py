@@ -64,6 +64,29 @@ def test_topk_seeds_from_pivots_c1():
     assert np.array_equal(host(ids), P["seeds"])
 
 
+@pytest.mark.parametrize("k", [1, 8, 16, 17, 64, 100])
+def test_topk_u8_list_and_buffer_sizes(k):
+    """Top-k across the list and candidate-buffer size steps (lists of k
+    rounded to 8 keys; 80 candidate slots up to k = 16, 128 above), with few
+    query rows (so the candidate tiles are split over several blocks and
+    merged), heavy distance ties, a ragged last tile and a candidate list."""
+    say("topk sizes", k)
+    A = api()
+    x = dg.random_tie_u8(3001, 48, 5)
+    q = dg.random_tie_u8(37, 48, 6)
+    bv, qv = orc.Vectors.from_array(x, orc.L2SQ), orc.Vectors.from_array(q, orc.L2SQ)
+    B, Q = gpu_vectors(x, orc.L2SQ), gpu_vectors(q, orc.L2SQ)
+    rid, rd = orc.topk(qv, bv, k)
+    ids, d = A.topk(Q, B, k)
+    assert np.array_equal(host(ids), rid)
+    assert np.array_equal(host(d), rd.astype(np.int32))
+    cand = np.random.default_rng(k).choice(3001, 1111, replace=False).astype(np.int32)
+    rid, rd = orc.topk(qv, bv, k, cand=cand)
+    ids, d = A.topk(Q, B, k, cand=to_dev(cand))
+    assert np.array_equal(host(ids), rid)
+    assert np.array_equal(host(d), rd.astype(np.int32))
+
+
 def test_topk_f32_cosine_and_l2():
     for kind, metric in [("f32cos", orc.COS), ("f32l2", orc.L2SQ)]:
         say("topk float", kind)
