@@ -200,7 +200,9 @@ typedef struct {
     int32_t waves_per_block;   /* 1..8 */
     int32_t lanes_per_row;     /* 4, 8, 16 or 32: lanes that share one vector */
     int32_t s_capacity;        /* candidate-set entries held on chip per query */
-    int32_t visited_log2;      /* on-chip visited table has 2^visited_log2 slots */
+    int32_t visited_log2;      /* on-chip visited bits: 2^visited_log2 words covering a
+                                  window of 32 * 2^visited_log2 ids around the first
+                                  seed (other ids: a global bitset); negative = none */
     int32_t pool_capacity;     /* rerank pool entries held on chip per query */
     int32_t blocks;            /* persistent grid size; 0 = one wave per query */
 } onng_launch_config;

@@ -698,7 +698,7 @@ onng_status onng_autotune_search(const onng_vectors *base, const onng_graph *gra
     const int n16 = row_pieces(base);
     for (int L : {4, 8, 16, 32})
         for (int s_cap : {128, 256, 512})
-            for (int vl : {10, 11, 12, -1})
+            for (int vl : {10, 11, 12, 13, -1})
                 for (int wpb : {2, 4}) {
                     if ((n16 + L - 1) / L > ppl_for(base->dtype)) continue;
                     onng_launch_config c{};

@@ -11,9 +11,11 @@
 //          d <= r(1+eps) are cut from its tail (they can never be expanded).
 //          Keys that do not fit spill to a per-slot global array and come back
 //          when the on-chip part runs below their minimum, so S is exact.
-//   vis    the visited set C: an open-addressing hash table of node ids.  When
-//          it gets half full the query moves to a per-slot global bitset
-//          (atomic OR), which is cleared after the query.
+//   vis    the visited set C, on chip for a window of consecutive ids around
+//          the first seed (one bit per id; the rows are in locality order, so
+//          much of a query's neighbourhood falls in it), and a per-slot
+//          global bitset (atomic OR) for the other ids, whose set words are
+//          cleared after the query.
 //
 // One expansion (pop of s, scan of its first e_p edges) is processed as one
 // batch: the unvisited neighbours are marked, their distances computed by the
@@ -38,10 +40,7 @@ namespace onng {
 
 namespace {
 
-constexpr uint32_t VIS_EMPTY = 0xffffffffu;
 constexpr float F_INF = __builtin_inff();
-
-__device__ __forceinline__ uint32_t hash_id(uint32_t id) { return id * 2654435761u; }
 
 // (1+eps)^2 for squared L2, 1+eps for cosine, rounded to f32; +inf stays +inf.
 __device__ __forceinline__ float range_factor(float eps, int metric) {
@@ -202,14 +201,18 @@ search_kernel(SearchKArgs a) {
     uint32_t *gbits = a.gbits + (size_t)slot * a.gbits_words;
     int32_t *vlog = a.vlog + (size_t)slot * a.vlog_cap;
     uint64_t *spill0 = a.spill + (size_t)slot * 2 * a.spill_cap;
-    bool gbits_clean = false;   // this slot's bitset is known to be all zero
+    // this slot's bitset is all zero at the start of every query once it has
+    // been cleared in this launch (each query clears the words it set)
+    bool gready = false;
 
     const int L = a.lanes_per_row;
     const int p = lane & (L - 1);
     const int grp = lane / L;
     const int rpp = WAVE / L;   // rows per pass
-    const uint32_t vmask = a.vis_log2 > 0 ? (1u << a.vis_log2) - 1u : 0u;
-    const int vis_max = a.vis_log2 > 0 ? (1 << (a.vis_log2 - 1)) : 0;   // load 1/2
+    // on-chip visited bits: 2^vis_log2 words, one bit per id of a window of
+    // W consecutive ids (the rows are in locality order, so a query's
+    // neighbourhood has nearby ids); other ids use the global bitset
+    const uint32_t W = a.vis_log2 > 0 ? (32u << a.vis_log2) : 0u;
 
     for (;;) {
         int ticket = 0;
@@ -255,8 +258,7 @@ search_kernel(SearchKArgs a) {
         int head = 0, size = 0;
         int spill_n = 0, spill_sel = 0;
         uint64_t spill_min = KEY_MAX;
-        int vis_n = 0;
-        bool gmode = a.vis_log2 == 0;
+        bool qglobal = false;   // this query set bits of the global bitset
         int log_n = 0;
         int dc = 0, hops = 0;
         int scanned = 0;   // adjacency entries read (sum of min(deg, e_p) over expansions)
@@ -270,12 +272,15 @@ search_kernel(SearchKArgs a) {
         uint32_t spec_nb = 0, spec_nb1 = 0;
         bool spec_vis = false, spec_bit = false, spec_bit1 = false;
 
-        // clear the on-chip visited table
-        for (int i = lane; i <= (int)vmask && a.vis_log2 > 0; i += WAVE) lds.vis[i] = VIS_EMPTY;
-        if (gmode && !gbits_clean) {
-            for (int64_t i = lane; i < a.gbits_words; i += WAVE) gbits[i] = 0u;
-            __threadfence_block();
-            gbits_clean = true;
+        // the on-chip window: W ids around the first seed, within [0, n)
+        uint32_t w0 = 0;
+        if (W) {
+            const int32_t s0 = a.n_seeds > 0 ? a.seeds[(size_t)qi * a.n_seeds] : -1;
+            int64_t c = (s0 >= 0 && (int64_t)s0 < a.n_base) ? (int64_t)s0 - (int64_t)(W / 2) : 0;
+            const int64_t hi = a.n_base > (int64_t)W ? a.n_base - (int64_t)W : 0;
+            c = c < 0 ? 0 : (c > hi ? hi : c);
+            w0 = (uint32_t)uni((int)(c & ~31LL));
+            for (int i = lane; i < (1 << a.vis_log2); i += WAVE) lds.vis[i] = 0u;
         }
         wave_sync();
 
@@ -284,55 +289,38 @@ search_kernel(SearchKArgs a) {
         // known_ok: in global mode the caller already read the bit (known_bit)
         auto visit = [&](bool valid, uint32_t id, bool known_ok = false,
                          bool known_bit = false) -> bool {
+            const uint32_t off = id - w0;   // wraps below the window
+            const bool inw = valid && off < W;
+            const bool outw = valid && !inw;
+            if (!gready && ballot(outw)) {
+                // first global mark of this slot in this launch
+                for (int64_t i = lane; i < a.gbits_words; i += WAVE) gbits[i] = 0u;
+                __threadfence_block();
+                gready = true;
+                wave_sync();
+            }
             bool isnew = false;
-            if (!gmode) {
-                if (valid) {
-                    uint32_t h = hash_id(id) >> (32 - a.vis_log2);
-                    for (int probe = 0; probe <= (int)vmask; probe++) {
-                        uint32_t old = atomicCAS(&lds.vis[h], VIS_EMPTY, id);
-                        if (old == VIS_EMPTY) { isnew = true; break; }
-                        if (old == id) break;
-                        h = (h + 1) & vmask;
-                    }
-                }
-                vis_n += __popcll(ballot(isnew));
-                if (vis_n > vis_max) {
-                    // move to the global bitset: copy the table, log the ids
-                    wave_sync();
-                    if (!gbits_clean) {
-                        for (int64_t i = lane; i < a.gbits_words; i += WAVE) gbits[i] = 0u;
-                        __threadfence_block();
-                        gbits_clean = true;
-                    }
-                    for (int i = lane; i <= (int)vmask; i += WAVE) {
-                        uint32_t v = lds.vis[i];
-                        bool has = v != VIS_EMPTY;
-                        if (has) atomicOr(&gbits[v >> 5], 1u << (v & 31));
-                        uint64_t m = ballot(has);
-                        if (has && log_n + mbcnt(m) < a.vlog_cap) vlog[log_n + mbcnt(m)] = (int32_t)v;
-                        log_n += __popcll(m);
-                    }
-                    gmode = true;
-                    gbits_clean = false;
-                }
-            } else {
+            if (inw) {
+                const uint32_t bit = 1u << (off & 31);
+                isnew = (atomicOr(&lds.vis[off >> 5], bit) & bit) == 0u;
+            } else if (outw) {
+                const uint32_t bit = 1u << (id & 31);
                 if (known_ok) {
                     // ids of one adjacency list are distinct, so the bits read
                     // before this expansion decide; the marks need no reply
-                    isnew = valid && !known_bit;
+                    isnew = !known_bit;
                     if (isnew)
-                        __hip_atomic_fetch_or(&gbits[id >> 5], 1u << (id & 31), __ATOMIC_RELAXED,
+                        __hip_atomic_fetch_or(&gbits[id >> 5], bit, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
-                } else if (valid) {
-                    uint32_t bit = 1u << (id & 31);
-                    uint32_t old = atomicOr(&gbits[id >> 5], bit);
-                    isnew = (old & bit) == 0;
+                } else {
+                    isnew = (atomicOr(&gbits[id >> 5], bit) & bit) == 0u;
                 }
-                uint64_t m = ballot(isnew);
-                if (isnew && log_n + mbcnt(m) < a.vlog_cap) vlog[log_n + mbcnt(m)] = (int32_t)id;
-                log_n += __popcll(m);
-                gbits_clean = false;
             }
+            const bool logged = isnew && outw;
+            const uint64_t m = ballot(logged);
+            if (logged && log_n + mbcnt(m) < a.vlog_cap) vlog[log_n + mbcnt(m)] = (int32_t)id;
+            log_n += __popcll(m);
+            if (m) qglobal = true;
             return isnew;
         };
 
@@ -655,19 +643,20 @@ search_kernel(SearchKArgs a) {
                     spec_nb1 = lane < nl1 ? (uint32_t)a.nbrs[spec_e0 + WAVE + lane] : 0u;
                 }
                 if (na > 0) absorb_s(k0, na, true);
-                spec_vis = go && gmode;
+                spec_vis = go && gready;
                 if (spec_vis) {
                     // the marks of this expansion are complete before the
-                    // visited bits of the guess are read
+                    // visited bits of the guess are read (those outside the
+                    // window: the others are on chip)
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                     spec_bit = false;
                     spec_bit1 = false;
-                    if (lane < nl0 && (int64_t)spec_nb < a.n_base) {
+                    if (lane < nl0 && (int64_t)spec_nb < a.n_base && spec_nb - w0 >= W) {
                         uint32_t wd = __hip_atomic_load(&gbits[spec_nb >> 5], __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT);
                         spec_bit = (wd >> (spec_nb & 31)) & 1u;
                     }
-                    if (lane < nl1 && (int64_t)spec_nb1 < a.n_base) {
+                    if (lane < nl1 && (int64_t)spec_nb1 < a.n_base && spec_nb1 - w0 >= W) {
                         uint32_t wd = __hip_atomic_load(&gbits[spec_nb1 >> 5], __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT);
                         spec_bit1 = (wd >> (spec_nb1 & 31)) & 1u;
@@ -800,7 +789,7 @@ search_kernel(SearchKArgs a) {
         }
 
         // leave the global visited bitset clean for the next query
-        if (gmode) {
+        if (qglobal) {
             __threadfence_block();   // the log was written by other lanes
             if (log_n <= a.vlog_cap) {
                 for (int i = lane; i < log_n; i += WAVE) gbits[(uint32_t)vlog[i] >> 5] = 0u;
@@ -808,7 +797,6 @@ search_kernel(SearchKArgs a) {
                 for (int64_t i = lane; i < a.gbits_words; i += WAVE) gbits[i] = 0u;
             }
             __threadfence_block();
-            gbits_clean = true;
         }
         wave_sync();
     }
