@@ -139,10 +139,16 @@ __global__ void __launch_bounds__(256) segment_rank_sort_kernel(const int64_t *o
 
 constexpr int8_t ST_UNDECIDED = 0, ST_KEPT = 1, ST_REMOVED = 2;
 
+// Witness test of the start-of-round graph: c in N(G_p, n) is a witness
+// when c's edge to nd exists, was kept in an earlier round (its rank in c's
+// list is below j) and is shorter than L.  The edge is found by binary
+// search in c's edges sorted by id (sid_nb, with their edge index sid_e),
+// instead of scanning c's kept edges by length.
 template <typename LenT>
 __global__ void pa_jacobi_kernel(const int64_t *off, const int32_t *nbrs, const LenT *lens,
                                  const int32_t *active, int64_t n_active, int j,
-                                 const int32_t *gp_nb, const LenT *gp_len, const int32_t *gp_cnt,
+                                 const int32_t *gp_nb, const int32_t *gp_cnt,
+                                 const int32_t *sid_nb, const int32_t *sid_e, const int8_t *kept,
                                  int8_t *status) {
     int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     int lane = lane_id();
@@ -156,17 +162,28 @@ __global__ void pa_jacobi_kernel(const int64_t *off, const int32_t *nbrs, const 
     for (int c0 = 0; c0 < cn && !found; c0 += WAVE) {
         bool hit = false;
         if (c0 + lane < cn) {
-            int32_t c = gp_nb[off[v] + c0 + lane];
-            int64_t cb = off[c];
-            int cc = gp_cnt[c];
-            for (int t = 0; t < cc; t++) {
-                if (!(gp_len[cb + t] < L)) break;
-                if (gp_nb[cb + t] == nd) { hit = true; break; }
+            const int32_t c = gp_nb[off[v] + c0 + lane];
+            const int64_t cb = off[c], ce = off[c + 1];
+            int64_t lo = cb, hi = ce;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (sid_nb[mid] < nd) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < ce && sid_nb[lo] == nd) {
+                const int64_t ec = sid_e[lo];
+                hit = ec - cb < j && kept[ec] && lens[ec] < L;
             }
         }
         found = ballot(hit) != 0;
     }
     if (lane == 0) status[v] = found ? ST_REMOVED : ST_UNDECIDED;
+}
+
+// edge index of every edge (the values sorted along with the ids)
+__global__ void iota_kernel(int64_t n, int32_t *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (int32_t)i;
 }
 
 template <typename LenT>
@@ -203,12 +220,13 @@ template <typename LenT>
 __global__ void pa_apply_kernel(const int64_t *off, const int32_t *nbrs, const LenT *lens,
                                 const int32_t *active, int64_t n_active, int j,
                                 int32_t *gp_nb, LenT *gp_len, int32_t *gp_cnt,
-                                const int8_t *status) {
+                                const int8_t *status, int8_t *kept) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_active) return;
     int32_t v = active[i];
     if (status[v] != ST_KEPT) return;
     int64_t e = off[v] + j;
+    kept[e] = 1;
     int c = gp_cnt[v];
     gp_nb[off[v] + c] = nbrs[e];
     gp_len[off[v] + c] = lens[e];
@@ -255,6 +273,14 @@ __global__ void cnt_to_i64_kernel(const int32_t *c, int64_t n, int64_t *o) {
 }
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+size_t segsort_temp_bytes(int64_t nnz, int64_t n) {
+    size_t bytes = 0;
+    (void)hipcub::DeviceSegmentedRadixSort::SortPairs(
+        nullptr, bytes, (const int32_t *)nullptr, (int32_t *)nullptr, (const int32_t *)nullptr,
+        (int32_t *)nullptr, (int)nnz, (int)n, (const int64_t *)nullptr, (const int64_t *)nullptr);
+    return bytes;
+}
 
 size_t scan_temp_bytes(int64_t n) {
     size_t bytes = 0;
@@ -337,6 +363,11 @@ size_t adjust_path_ws(int64_t n, int64_t nnz) {
     c.take<int32_t>(1 << 20);      // cursor per degree
     c.take<int64_t>(n + 1);        // out counts
     c.take<char>(scan_temp_bytes(n + 1));
+    c.take<int32_t>(nnz);          // edge index
+    c.take<int32_t>(nnz);          // ids sorted per node
+    c.take<int32_t>(nnz);          // their edge index
+    c.take<int8_t>(nnz);           // kept flag per edge
+    c.take<char>(segsort_temp_bytes(nnz, n));
     return c.size() + 256;
 }
 
@@ -360,6 +391,20 @@ static onng_status adjust_path_impl(const onng_graph *g, int64_t *out_off, int32
     int64_t *ocnt = c.take<int64_t>(n + 1);
     size_t tb = scan_temp_bytes(n + 1);
     void *tmp = c.take<char>(tb);
+    int32_t *eidx = c.take<int32_t>(nnz);
+    int32_t *sid_nb = c.take<int32_t>(nnz);
+    int32_t *sid_e = c.take<int32_t>(nnz);
+    int8_t *kept = c.take<int8_t>(nnz);
+    size_t sb = segsort_temp_bytes(nnz, n);
+    void *stmp = c.take<char>(sb);
+    // every node's edges sorted by id, for the witness lookups
+    ONNG_HIP(hipMemsetAsync(kept, 0, (size_t)nnz, st));
+    if (nnz > 0) {
+        hipLaunchKernelGGL(iota_kernel, dim3(blocks_for(nnz, 256)), dim3(256), 0, st, nnz, eidx);
+        ONNG_HIP(hipcub::DeviceSegmentedRadixSort::SortPairs(
+            stmp, sb, g->nbrs, sid_nb, eidx, sid_e, (int)nnz, (int)n, g->offsets, g->offsets + 1,
+            0, 32, st));
+    }
 
     ONNG_HIP(hipMemsetAsync(gp_cnt, 0, sizeof(int32_t) * n, st));
     ONNG_HIP(hipMemsetAsync(hist, 0, sizeof(unsigned long long) * MAXD, st));
@@ -393,7 +438,7 @@ static onng_status adjust_path_impl(const onng_graph *g, int64_t *out_off, int32
         if (n_act == 0) break;
         hipLaunchKernelGGL((pa_jacobi_kernel<LenT>), dim3(blocks_for(n_act * WAVE, 256)),
                            dim3(256), 0, st, g->offsets, g->nbrs, lens, order, n_act, j, gp_nb,
-                           gp_len, gp_cnt, status);
+                           gp_cnt, sid_nb, sid_e, kept, status);
         for (int it = 0;; it++) {
             ONNG_HIP(hipMemsetAsync(undecided, 0, sizeof(int32_t), st));
             hipLaunchKernelGGL((pa_settle_kernel<LenT>), dim3(blocks_for(n_act, 256)), dim3(256),
@@ -410,7 +455,7 @@ static onng_status adjust_path_impl(const onng_graph *g, int64_t *out_off, int32
         }
         hipLaunchKernelGGL((pa_apply_kernel<LenT>), dim3(blocks_for(n_act, 256)), dim3(256), 0, st,
                            g->offsets, g->nbrs, lens, order, n_act, j, gp_nb, gp_len, gp_cnt,
-                           status);
+                           status, kept);
     }
     hipLaunchKernelGGL(cnt_to_i64_kernel, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st, gp_cnt,
                        n, ocnt);
