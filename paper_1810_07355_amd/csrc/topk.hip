@@ -72,6 +72,7 @@ struct TopkArgs {
     int32_t cb;               // candidate slots per row (topk_cb)
     int32_t bm;               // query rows per block (16 per wave)
     int32_t exclude_self;
+    int32_t rotate;           // rows and candidates are the same rows: start at the own tile
     int32_t lds_pitch;        // bytes per staged base row
     int32_t *out_ids;
     void *out_d;
@@ -324,9 +325,16 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
         const int r = i / CPR, c = i - r * CPR;
         put_chunk_at((uint32_t)r * (uint32_t)a.lds_pitch + (uint32_t)c * 16u, c, v);
     };
-    if (piped && t_beg < t_end) fetch_tile(t_beg);
+    // For a kNN graph of rows in locality order the sweep starts at the row
+    // block's own tile and wraps around: the nearest rows come first, so the
+    // lists' thresholds are tight from the start and few later candidates
+    // pass them.  The result does not depend on the order.
+    const int rot0 = a.rotate ? (int)((row0 / BN) % ntiles) : 0;
+    auto tile_at = [&](int i) { const int x = i + rot0; return x >= ntiles ? x - ntiles : x; };
+    if (piped && t_beg < t_end) fetch_tile(tile_at(t_beg));
     for (int t = t_beg; t < t_end; t++) {
-        const int64_t col0 = (int64_t)t * BN;
+        const int tt = tile_at(t);
+        const int64_t col0 = (int64_t)tt * BN;
         __syncthreads();
         // stage 64 base rows
         if (piped) {
@@ -337,14 +345,14 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
             }
             put_side();
         } else {
-            fetch_side(t);
+            fetch_side(tt);
             put_side();
-            const uint8_t *tb = tile_ptr(t);
-            const int rows = tile_rows(t);
+            const uint8_t *tb = tile_ptr(tt);
+            const int rows = tile_rows(tt);
             for (int i = threadIdx.x; i < total; i += blockDim.x) put_chunk(i, load_chunk(tb, rows, i));
         }
         __syncthreads();
-        if (piped && t + 1 < t_end) fetch_tile(t + 1);
+        if (piped && t + 1 < t_end) fetch_tile(tile_at(t + 1));
         if (row0 + wv * 16 >= a.nq) continue;
 
         // ---- 16 query rows x 64 tile columns: four 16x16 blocks, their
@@ -665,6 +673,7 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     a.side_norms = Q->dtype == ONNG_U8 || Q->metric == ONNG_L2SQ;
     a.bm = topk_bm(k, Q->dtype, Q->dim, side_words);
     a.exclude_self = exclude_self;
+    a.rotate = 0;   // set below once the split count is known
     // the staged tile holds a row's components (zero-extended), not its padding
     a.lds_pitch = lds_pitch_for(Q->dtype, B->dim);
     a.out_ids = ids;
@@ -682,6 +691,7 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     ONNG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int ntiles = (int)((nb + BN - 1) / BN);
     a.splits = sp;
+    a.rotate = (!cand && sp == 1 && Q->data == B->data && Q->n == B->n) ? 1 : 0;
     a.tiles_per_split = (ntiles + sp - 1) / sp;
     a.part = part;
     dim3 grid((unsigned)((Q->n + a.bm - 1) / a.bm), (unsigned)sp),
