@@ -170,7 +170,8 @@ __global__ void pa_jacobi_kernel(const int64_t *off, const int32_t *nbrs, const 
                 if (sid_nb[mid] < nd) lo = mid + 1;
                 else hi = mid;
             }
-            if (lo < ce && sid_nb[lo] == nd) {
+            // (a list may hold nd more than once: every copy is a candidate)
+            for (; lo < ce && sid_nb[lo] == nd && !hit; lo++) {
                 const int64_t ec = sid_e[lo];
                 hit = ec - cb < j && kept[ec] && lens[ec] < L;
             }
