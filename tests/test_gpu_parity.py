@@ -167,6 +167,34 @@ def test_adjust_path_ties(seed):
     assert np.array_equal(host(g.nbrs), pn)
 
 
+def test_adjust_path_arbitrary_lists_with_repeats():
+    """Path adjustment on lists that are not the degree adjustment's: random
+    lengths with many ties, degrees from 1 to 300 (past the 64-lane chunks and
+    long witness lists) and repeated neighbour ids, each list sorted by
+    (length, id); bit-exact against the oracle."""
+    say("adjust_path arbitrary")
+    A, Lb = api(), L()
+    g = np.random.default_rng(17)
+    n = 400
+    offs, nbs, lns = [0], [], []
+    for v in range(n):
+        deg = int(g.integers(1, 301)) if v % 37 == 0 else int(g.integers(1, 25))
+        nb = g.integers(0, n, size=deg)
+        nb[nb == v] = (v + 1) % n
+        ln = g.integers(1, 12, size=deg)
+        o = np.lexsort((nb, ln))
+        nbs.append(nb[o]); lns.append(ln[o]); offs.append(offs[-1] + deg)
+    off = np.array(offs, dtype=np.int64)
+    nb = np.concatenate(nbs).astype(np.int32)
+    ln = np.concatenate(lns).astype(np.int32)
+    assert any(len(set(x.tolist())) < len(x) for x in nbs)
+    po, pn, pl = orc.adjust_path(off, nb, ln)
+    gg = A.adjust_path(gpu_graph(off, nb, ln), Lb.U8, Lb.L2SQ)
+    assert np.array_equal(host(gg.offsets), po)
+    assert np.array_equal(host(gg.nbrs), pn)
+    assert np.array_equal(host(gg.lens), pl)
+
+
 def test_graph_chain_on_gpu_equals_oracle_c1():
     P = c1_problem()
     say("kNN -> SA -> PA chain on GPU")
