@@ -7,6 +7,8 @@ same code serves exact integer and fp64 data.  Ties are broken by node id
 
 * knn_search:            Algorithm 1 (KnnSearch), C a plain Python set.
 * adjusted_graph:        Algorithm 2 (ConstructAdjustedGraph).
+* adjusted_graph_with_constraint: Algorithm 3, with M a set and the argmin
+                         over (|N(G_t, x)|, x) taken afresh every step (R10).
 * adjust_path/has_path:  Algorithms 4 and 5 (AdjustPath, HasPath).
 * paper_visited:         Algorithms 6 and 7 (Set, IsSet) as a class.
 """
@@ -97,6 +99,35 @@ def adjusted_graph(knn, knn_d, e_o, e_i):
             if p <= e_i and o not in Ge[nn]:
                 Ge[nn][o] = d
             p += 1
+    return [sorted((l, i) for i, l in Ge[o].items()) for o in range(n)]
+
+
+def adjusted_graph_with_constraint(knn, knn_d, e_o, e_i):
+    """Algorithm 3.  Same input as adjusted_graph.  G_i is a list of sets;
+    every argmin is taken over the remaining members.  Returns per-node lists
+    of (len, id) sorted ascending."""
+    n = len(knn)
+    Gt = [dict((i, l) for l, i in lst) for lst in adjusted_graph(knn, knn_d, 0, e_i)]
+    Ge = [dict() for _ in range(n)]
+    Gi = [set() for _ in range(n)]
+    M = set(range(n))
+    while M:
+        o = min(M, key=lambda x: (len(Gt[x]), x))
+        M.remove(o)
+        S = dict(Gt[o])
+        while S:
+            nn = min(S, key=lambda x: (S[x], x))
+            d = S.pop(nn)
+            if not Gi[nn] or (len(Gi[nn]) < e_i and len(Ge[o]) < e_o):
+                Ge[o][nn] = d
+                Gi[nn].add(o)
+    for o in range(n):
+        S = {knn[o][t]: knn_d[o][t] for t in range(len(knn[o])) if knn[o][t] >= 0}
+        while S and len(Ge[o]) < e_o:
+            nn = min(S, key=lambda x: (S[x], x))
+            d = S.pop(nn)
+            if nn not in Ge[o]:
+                Ge[o][nn] = d
     return [sorted((l, i) for i, l in Ge[o].items()) for o in range(n)]
 
 

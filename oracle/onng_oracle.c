@@ -16,6 +16,8 @@
  *       On u8 data the product is an fp32 multiply.
  *   R6  e_p is an integer chosen by the caller; UINT32_MAX means unlimited.
  *       p advances on every scanned edge, visited or not.
+ *   R10 Algorithm 3 takes nodes in ascending (|N(G_t, x)|, x); its guard
+ *       "N(G_e, o) < e_o" compares the list's size.
  *   R11 AdjustPath visits nodes in ascending id and sees its own additions
  *       immediately.
  *   R12 HasPath keeps the strict "<" on the edge lengths.
@@ -440,6 +442,84 @@ int or_adjust_degree(const int32_t *knn_ids, const double *knn_d, int64_t n,
     int64_t total = write_csr(G, n, offsets, nbrs, lens, nnz_cap);
     for (int64_t o = 0; o < n; o++) { free(G[o].id); free(G[o].len); }
     free(G);
+    *nnz_out = total < 0 ? -total : total;
+    return total < 0 ? -3 : 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Algorithm 3: ConstructAdjustedGraphWithConstraint                          */
+/* ------------------------------------------------------------------------- */
+
+static int elist_has(const elist *l, int32_t id)
+{
+    for (int32_t t = 0; t < l->n; t++)
+        if (l->id[t] == id) return 1;
+    return 0;
+}
+
+typedef struct { int64_t cnt, id; } mkey_t;
+
+static int mkey_cmp(const void *a, const void *b)
+{
+    const mkey_t *x = (const mkey_t *)a, *y = (const mkey_t *)b;
+    if (x->cnt != y->cnt) return x->cnt < y->cnt ? -1 : 1;
+    return x->id < y->id ? -1 : (x->id > y->id);
+}
+
+int or_adjust_degree_constrained(const int32_t *knn_ids, const double *knn_d, int64_t n,
+                                 int32_t k, int32_t e_o, int32_t e_i,
+                                 int64_t *offsets, int32_t *nbrs, double *lens,
+                                 int64_t nnz_cap, int64_t *nnz_out)
+{
+    if (!knn_ids || !knn_d || n < 0 || k < 0 || e_o < 0 || e_i < 0 || !nnz_out)
+        return -1;
+    if (nbrs && (!offsets || !lens))
+        return -1;
+    /* G_t <- ConstructAdjustedGraph(G, 0, e_i): the reverse edges only */
+    int64_t tn = 0;
+    if (or_adjust_degree(knn_ids, knn_d, n, k, 0, e_i, NULL, NULL, NULL, 0, &tn) != 0)
+        return -1;
+    int64_t *t_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int32_t *t_nb = (int32_t *)malloc(sizeof(int32_t) * (size_t)(tn ? tn : 1));
+    double *t_len = (double *)malloc(sizeof(double) * (size_t)(tn ? tn : 1));
+    elist *Ge = (elist *)calloc((size_t)(n ? n : 1), sizeof(elist));
+    /* G_i is kept only through its in-degrees: o joins N(G_i, n) at most once,
+     * since o considers each member of N(G_t, o) once. */
+    int64_t *indeg = (int64_t *)calloc((size_t)(n ? n : 1), sizeof(int64_t));
+    mkey_t *M = (mkey_t *)malloc(sizeof(mkey_t) * (size_t)(n ? n : 1));
+    int rc = or_adjust_degree(knn_ids, knn_d, n, k, 0, e_i, t_off, t_nb, t_len, tn, &tn);
+    if (rc != 0) n = 0;
+    /* M in the order the repeated argmin takes it: |N(G_t, x)| does not change
+     * while M shrinks, so that order is ascending (|N(G_t, x)|, x) (R10). */
+    for (int64_t x = 0; x < n; x++) { M[x].cnt = t_off[x + 1] - t_off[x]; M[x].id = x; }
+    qsort(M, (size_t)n, sizeof(mkey_t), mkey_cmp);
+    for (int64_t a = 0; a < n; a++) {
+        int64_t o = M[a].id;
+        /* S <- N(G_t, o).  Algorithm 2's lists come out in ascending (len, id)
+         * order, so the repeated argmin over S walks the list from the front. */
+        for (int64_t t = t_off[o]; t < t_off[o + 1]; t++) {
+            int32_t nn = t_nb[t];
+            if (indeg[nn] == 0 || (indeg[nn] < e_i && Ge[o].n < e_o)) {
+                elist_push(&Ge[o], nn, t_len[t]);
+                indeg[nn]++;
+            }
+        }
+    }
+    /* Fill every node up to e_o from its own k-NN row, which is S in ascending
+     * (d, id) order; members already in N(G_e, o) are skipped. */
+    for (int64_t o = 0; o < n; o++) {
+        const int32_t *row = knn_ids + o * k;
+        const double *rd = knn_d + o * k;
+        for (int32_t t = 0; t < k && row[t] >= 0 && Ge[o].n < e_o; t++)
+            if (!elist_has(&Ge[o], row[t]))
+                elist_push(&Ge[o], row[t], rd[t]);
+    }
+    for (int64_t o = 0; o < n; o++) sort_list(&Ge[o]);   /* emitted in (len, id) order */
+    int64_t total = write_csr(Ge, n, offsets, nbrs, lens, nnz_cap);
+    for (int64_t o = 0; o < n; o++) { free(Ge[o].id); free(Ge[o].len); }
+    free(Ge); free(indeg); free(M);
+    free(t_off); free(t_nb); free(t_len);
+    if (rc != 0) return -1;
     *nnz_out = total < 0 ? -total : total;
     return total < 0 ? -3 : 0;
 }

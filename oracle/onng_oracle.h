@@ -67,6 +67,17 @@ int or_adjust_degree(const int32_t *knn_ids, const double *knn_d, int64_t n,
                      int64_t *offsets, int32_t *nbrs, double *lens,
                      int64_t nnz_cap, int64_t *nnz_out);
 
+/* ---- Algorithm 3 (ConstructAdjustedGraphWithConstraint) ---- */
+/* Same table and two-call protocol as or_adjust_degree.  G_t is Algorithm 2
+ * with (0, e_i); nodes are taken in ascending (|N(G_t, x)|, x) (R10); the
+ * inner loops take members in ascending (d, id).  Lists come out sorted by
+ * (len, id).  Phase-1 lengths are G_t's (the row the reverse edge came from);
+ * phase-2 lengths are the node's own row's. */
+int or_adjust_degree_constrained(const int32_t *knn_ids, const double *knn_d, int64_t n,
+                                 int32_t k, int32_t e_o, int32_t e_i,
+                                 int64_t *offsets, int32_t *nbrs, double *lens,
+                                 int64_t nnz_cap, int64_t *nnz_out);
+
 /* ---- Algorithms 4 and 5 (AdjustPath, HasPath) ---- */
 int or_adjust_path(const int64_t *in_off, const int32_t *in_nbrs,
                    const double *in_lens, int64_t n,

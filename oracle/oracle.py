@@ -51,6 +51,8 @@ def lib():
                                  C.c_int32]
         _lib.or_adjust_degree.argtypes = [P, P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, P,
                                           P, P, C.c_int64, P]
+        _lib.or_adjust_degree_constrained.argtypes = [P, P, C.c_int64, C.c_int32, C.c_int32,
+                                                      C.c_int32, P, P, P, C.c_int64, P]
         _lib.or_adjust_path.argtypes = [P, P, P, C.c_int64, P, P, P, P]
         _lib.or_search.argtypes = [P, P, P, C.c_int64, P, C.c_int64, P, C.c_int32, P, P, P, P,
                                    P, C.c_int32, P, C.c_int32, P, P, P, P, P, P, C.c_int32]
@@ -168,6 +170,27 @@ def adjust_degree(knn_ids, knn_d, e_o: int, e_i: int):
     rc = lib().or_adjust_degree(knn_ids.ctypes.data, knn_d.ctypes.data, n, k, e_o, e_i,
                                 off.ctypes.data, nb.ctypes.data, ln.ctypes.data, nnz.value,
                                 C.byref(nnz))
+    assert rc == 0
+    return off, nb[:nnz.value], ln[:nnz.value]
+
+
+def adjust_degree_constrained(knn_ids, knn_d, e_o: int, e_i: int):
+    """Algorithm 3 (static degree adjustment with constraints) on a k-NN table
+    whose rows are sorted by (d, id).  Returns CSR (offsets, nbrs, lens), each
+    list in (len, id) order."""
+    knn_ids = np.ascontiguousarray(knn_ids, dtype=np.int32)
+    knn_d = np.ascontiguousarray(knn_d, dtype=np.float64)
+    n, k = knn_ids.shape
+    nnz = C.c_int64(0)
+    rc = lib().or_adjust_degree_constrained(knn_ids.ctypes.data, knn_d.ctypes.data, n, k, e_o,
+                                            e_i, None, None, None, 0, C.byref(nnz))
+    assert rc == 0
+    off = np.empty(n + 1, dtype=np.int64)
+    nb = np.empty(max(1, nnz.value), dtype=np.int32)
+    ln = np.empty(max(1, nnz.value), dtype=np.float64)
+    rc = lib().or_adjust_degree_constrained(knn_ids.ctypes.data, knn_d.ctypes.data, n, k, e_o,
+                                            e_i, off.ctypes.data, nb.ctypes.data,
+                                            ln.ctypes.data, nnz.value, C.byref(nnz))
     assert rc == 0
     return off, nb[:nnz.value], ln[:nnz.value]
 

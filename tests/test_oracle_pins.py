@@ -202,6 +202,105 @@ def test_adjust_degree_hand_example():
     assert ln[off[2]:off[3]].tolist() == [3.0, 4.0, 5.0]
 
 
+# ------------------------------------------------------- Algorithm 3 (SAC)
+
+def _csr_lists(off, nb, ln):
+    return [[(float(l), int(i)) for i, l in zip(nb[off[o]:off[o + 1]], ln[off[o]:off[o + 1]])]
+            for o in range(len(off) - 1)]
+
+
+def test_sac_hand_example():
+    g = _gold("sac_line5.json")
+    knn = np.array(g["knn"], np.int32)
+    kd = np.array(g["knn_d"], np.float64)
+    for case in g["cases"]:
+        off, nb, ln = orc.adjust_degree_constrained(knn, kd, case["e_o"], case["e_i"])
+        got = [[(i, l) for l, i in lst] for lst in _csr_lists(off, nb, ln)]
+        want = [[tuple(e) for e in case["expect"][str(o)]] for o in range(5)]
+        # expected lists are in the order derived; the oracle emits (len, id) order
+        assert got == [sorted(w, key=lambda e: (e[1], e[0])) for w in want], case
+        lit = literal.adjusted_graph_with_constraint(knn.tolist(), kd.tolist(), case["e_o"],
+                                                     case["e_i"])
+        assert [[(i, l) for l, i in lst] for lst in lit] == got
+
+
+def _sac_first_source(knn, e_o, e_i):
+    """The first loop of Algorithm 3 without its sequence: only the first e_i
+    nodes of row n can add an edge into n, each considers n once, so the
+    in-degree bound never binds; o keeps o -> n when n is among the first e_o
+    members of N(G_t, o) by (d, id), or when o comes first, by
+    (|N(G_t, x)|, x), among the nodes of row n's first e_i (that one always
+    meets n with in-degree 0).  The fill loop then tops nodes with
+    |N(G_t, o)| < e_o up from their own rows."""
+    n, k = knn.shape
+    ei = min(e_i, k)
+    src = knn[:, :ei]
+    cnt = np.bincount(src[src >= 0].ravel(), minlength=n)
+    first = np.full(n, -1, np.int64)
+    for m in range(n):
+        s = [o for o in src[m].tolist() if o >= 0]
+        if s:
+            first[m] = min(s, key=lambda o: (cnt[o], o))
+    return cnt, first
+
+
+@pytest.mark.parametrize("e_o,e_i", [(3, 5), (5, 3), (0, 4), (4, 0), (8, 8), (2, 20), (1, 1)])
+def test_sac_first_source_reading_and_literal(e_o, e_i):
+    x = dg.random_tie_u8(120, 5, 7)
+    v = orc.Vectors.from_array(x, orc.L2SQ)
+    knn, kd = orc.knn_graph(v, 8)
+    off, nb, ln = orc.adjust_degree_constrained(knn, kd, e_o, e_i)
+    lists = _csr_lists(off, nb, ln)
+    assert lists == [[(float(l), int(i)) for l, i in lst] for lst in
+                     literal.adjusted_graph_with_constraint(knn.tolist(), kd.tolist(), e_o, e_i)]
+    D = ((x[:, None, :].astype(np.int64) - x[None, :, :].astype(np.int64)) ** 2).sum(-1)
+    cnt, first = _sac_first_source(knn, e_o, e_i)
+    ei = min(e_i, 8)
+    for o in range(120):
+        S = sorted((D[o, m], m) for m in range(120) if o in knn[m, :ei].tolist())
+        want = {m for p, (_, m) in enumerate(S) if p < e_o or first[m] == o}
+        if len(S) < e_o:
+            for m in knn[o].tolist():
+                if len(want) >= e_o:
+                    break
+                want.add(m)
+        ids = [i for _, i in lists[o]]
+        assert set(ids) == want and len(ids) == len(want)
+        assert [l for l, _ in lists[o]] == D[o, ids].tolist()
+
+
+def test_sac_special_cases():
+    x = dg.random_tie_u8(150, 6, 9)
+    v = orc.Vectors.from_array(x, orc.L2SQ)
+    k = 10
+    knn, kd = orc.knn_graph(v, k)
+    # e_i = 0: G_t is empty and the fill loop gives the first e_o of each row
+    off, nb, ln = orc.adjust_degree_constrained(knn, kd, 4, 0)
+    for o in range(150):
+        assert nb[off[o]:off[o + 1]].tolist() == knn[o, :4].tolist()
+    # e_o beyond every possible out-degree: the first loop keeps all of
+    # N(G_t, o) and the fill loop adds the whole row, which is Algorithm 2
+    # with (k, e_i) as sets of ids
+    for e_i in (1, 3, 10):
+        off, nb, ln = orc.adjust_degree_constrained(knn, kd, 10**6, e_i)
+        so, sn, sl = orc.adjust_degree(knn, kd, k, e_i)
+        for o in range(150):
+            assert sorted(nb[off[o]:off[o + 1]].tolist()) == sorted(sn[so[o]:so[o + 1]].tolist())
+    # invariants at a mid setting: every node gets an incoming edge, every node
+    # reaches min(e_o, available) out-edges, no duplicates or self loops
+    e_o, e_i = 3, 5
+    off, nb, ln = orc.adjust_degree_constrained(knn, kd, e_o, e_i)
+    assert np.bincount(nb, minlength=150).min() >= 1
+    for o in range(150):
+        lst = nb[off[o]:off[o + 1]].tolist()
+        avail = set(knn[o].tolist()) | {m for m in range(150) if o in knn[m, :e_i].tolist()}
+        assert len(lst) >= min(e_o, len(avail))
+        assert len(set(lst)) == len(lst) and o not in lst
+    # constrained out-degrees sit closer to e_o than Algorithm 2's (the method's purpose)
+    so, sn, sl = orc.adjust_degree(knn, kd, e_o, e_i)
+    assert np.abs(np.diff(off) - e_o).mean() < np.abs(np.diff(so) - e_o).mean()
+
+
 # ---------------------------------------------------- Algorithms 4/5 (PA)
 
 def _csr_from_adj(adj, n):
