@@ -11,8 +11,8 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    Calls enqueue their kernels on it and return after argument validation;
  *    results are valid once the stream is synchronised.  Calls that return a
- *    count to a host pointer (onng_adjust_degree, onng_adjust_path)
- *    synchronise the stream themselves.
+ *    count to a host pointer (onng_adjust_degree, onng_adjust_degree_constrained,
+ *    onng_adjust_path) synchronise the stream themselves.
  *  - Scratch memory comes from the caller: `ws`/`ws_bytes`, sized by the
  *    matching *_workspace_size function.  The library allocates no device
  *    memory of its own (the tuning cache is host memory).
@@ -135,6 +135,31 @@ onng_status onng_adjust_degree(const int32_t *knn_ids, const void *knn_dists, in
                                int64_t *offsets, int32_t *nbrs, void *lens, int64_t nnz_capacity,
                                int64_t *nnz_out, void *ws, size_t ws_bytes, void *stream);
 size_t onng_adjust_degree_workspace_size(int64_t n, int32_t k, int32_t e_o, int32_t e_i);
+
+/* ------------------------------------------------------------------------ */
+/* Static degree adjustment with constraints — Algorithm 3                  */
+/* (ConstructAdjustedGraphWithConstraint)                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Same inputs, outputs, errors and capacity rule as onng_adjust_degree.
+ * G_t is Algorithm 2 with (0, e_i): N(G_t, o) = the nodes m that have o among
+ * the first min(e_i, k) of their row, each edge with row m's length.  Nodes
+ * are taken in ascending (|N(G_t, x)|, x); each takes the members of
+ * N(G_t, o) in ascending (length, id) and keeps o -> n while its out-degree
+ * is below e_o, or whenever n has no incoming edge yet.  Then every node
+ * below e_o edges appends the members of its own row it lacks, nearest
+ * first, up to e_o.  Each list is sorted by (length, id); the result equals a
+ * sequential run of Algorithm 3 on the same table.  e_o may exceed k (no
+ * clamp); e_i is clamped to k.  n * (min(e_o,k) + min(e_i,k)) always
+ * suffices for nnz_capacity. */
+onng_status onng_adjust_degree_constrained(const int32_t *knn_ids, const void *knn_dists,
+                                           int64_t n, int32_t k, int32_t data_dtype,
+                                           int32_t metric, int32_t e_o, int32_t e_i,
+                                           int64_t *offsets, int32_t *nbrs, void *lens,
+                                           int64_t nnz_capacity, int64_t *nnz_out, void *ws,
+                                           size_t ws_bytes, void *stream);
+size_t onng_adjust_degree_constrained_workspace_size(int64_t n, int32_t k, int32_t e_o,
+                                                      int32_t e_i);
 
 /* ------------------------------------------------------------------------ */
 /* Path adjustment — Algorithms 4 (AdjustPath) and 5 (HasPath)              */

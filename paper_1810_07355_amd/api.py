@@ -136,6 +136,22 @@ def adjust_degree(knn_ids: torch.Tensor, knn_d: torch.Tensor, dtype: int, metric
     return Graph(off, nb[:nnz.value].clone(), ln[:nnz.value].clone())
 
 
+def adjust_degree_constrained(knn_ids: torch.Tensor, knn_d: torch.Tensor, dtype: int,
+                              metric: int, e_o: int, e_i: int) -> Graph:
+    n, k = knn_ids.shape
+    dev = knn_ids.device
+    cap = n * (min(e_o, k) + min(e_i, k))
+    off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    nb = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    ln = torch.empty(max(cap, 1), dtype=knn_d.dtype, device=dev)
+    ws = _workspace(L.load().onng_adjust_degree_constrained_workspace_size(n, k, e_o, e_i), dev)
+    nnz = C.c_int64(0)
+    L.call("onng_adjust_degree_constrained", knn_ids.data_ptr(), knn_d.data_ptr(), n, k, dtype,
+           metric, e_o, e_i, off.data_ptr(), nb.data_ptr(), ln.data_ptr(), cap, C.byref(nnz),
+           ws.data_ptr(), ws.numel(), _stream())
+    return Graph(off, nb[:nnz.value].clone(), ln[:nnz.value].clone())
+
+
 def adjust_path(g: Graph, dtype: int, metric: int) -> Graph:
     dev = g.offsets.device
     off = torch.empty_like(g.offsets)

@@ -1,6 +1,7 @@
 // Graph adjustment on the GPU:
-//   static degree adjustment, ConstructAdjustedGraph (Algorithm 2), and
-//   path adjustment, AdjustPath with HasPath (Algorithms 4 and 5).
+//   static degree adjustment, ConstructAdjustedGraph (Algorithm 2),
+//   the same with constraints, ConstructAdjustedGraphWithConstraint
+//   (Algorithm 3), and path adjustment, AdjustPath with HasPath (Algorithms 4 and 5).
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -123,6 +124,99 @@ __global__ void __launch_bounds__(256) segment_rank_sort_kernel(const int64_t *o
         if constexpr (std::is_integral<LenT>::value) lens[b + rank] = (LenT)lo;
         else lens[b + rank] = unord_f32(lo);
     }
+}
+
+// ------------------------------------------------------------ Algorithm 3 --
+// G_t = ConstructAdjustedGraph(G, 0, e_i): N(G_t, o) = {m : o among the first
+// e_i of row m}, each edge with row m's length.  The first loop's in-degree
+// bound never binds: only the (at most e_i) nodes of row n's head can add an
+// edge into n, each of them considers n once, so whenever one does, fewer
+// than e_i have added it before.  What remains decides every edge on its own:
+// the first of row n's head in processing order (ascending (|N(G_t, x)|, x))
+// meets n with in-degree 0 and adds it; any later one adds it only while its
+// own out-degree is below e_o, i.e. for the first e_o members of N(G_t, o) in
+// (length, id) order, all of which the loop keeps.  So o -> n is kept iff n is
+// among those first e_o or o is n's first source.  The fill loop matters only
+// for nodes with |N(G_t, o)| < e_o, whose first loop kept all of N(G_t, o): it
+// appends the members of row o not already present, nearest first, up to e_o.
+
+__global__ void sac_rcount_kernel(const int32_t *knn, int64_t n, int k, int ei, int64_t *cnt) {
+    int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const int32_t *row = knn + m * k;
+    int lim = min(ei, row_len(row, k));
+    for (int t = 0; t < lim; t++) {
+        int32_t o = row[t];
+        if (o < n) atomicAdd((unsigned long long *)&cnt[o], 1ull);
+    }
+}
+
+// reverse keys of G_t into each node's segment, and every node's first source
+template <typename LenT>
+__global__ void sac_scatter_kernel(const int32_t *knn, const LenT *kd, int64_t n, int k, int ei,
+                                   const int64_t *rev_off, int32_t *cursor, uint64_t *keys,
+                                   int32_t *first_src) {
+    int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const int32_t *row = knn + m * k;
+    int lim = min(ei, row_len(row, k));
+    int32_t best = -1;
+    int64_t bestc = 0;
+    for (int t = 0; t < lim; t++) {
+        int32_t o = row[t];
+        if (o >= n) continue;
+        int slot = atomicAdd(&cursor[o], 1);
+        keys[rev_off[o] + slot] = make_key(len_ord(kd[m * k + t]), (uint32_t)m);
+        int64_t c = rev_off[o + 1] - rev_off[o];
+        if (best < 0 || c < bestc || (c == bestc && o < best)) {
+            best = o;
+            bestc = c;
+        }
+    }
+    first_src[m] = best;
+}
+
+// One wave per node o over its sorted N(G_t, o) (rv_nb/rv_len at rev_off):
+// counts the kept edges (WRITE false) or writes their keys at out_off[o].
+template <typename LenT, bool WRITE>
+__global__ void __launch_bounds__(256) sac_select_kernel(
+    const int64_t *rev_off, const int32_t *rv_nb, const LenT *rv_len, const int32_t *first_src,
+    const int32_t *knn, const LenT *kd, int64_t n, int k, int eo, int64_t *out_cnt,
+    const int64_t *out_off, uint64_t *keys) {
+    const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int lane = lane_id();
+    if (o >= n) return;
+    const int64_t b = rev_off[o];
+    const int m = (int)(rev_off[o + 1] - b);
+    const int head = min(m, eo);
+    const int64_t w = WRITE ? out_off[o] : 0;
+    if (WRITE)
+        for (int p = lane; p < head; p += WAVE)
+            keys[w + p] = make_key(len_ord(rv_len[b + p]), (uint32_t)rv_nb[b + p]);
+    int c = head;
+    for (int p0 = head; p0 < m; p0 += WAVE) {
+        const int p = p0 + lane;
+        const bool keep = p < m && first_src[rv_nb[b + p]] == (int32_t)o;
+        const uint64_t bal = ballot(keep);
+        if (WRITE && keep)
+            keys[w + c + mbcnt(bal)] = make_key(len_ord(rv_len[b + p]), (uint32_t)rv_nb[b + p]);
+        c += __popcll(bal);
+    }
+    if (m < eo) {
+        const int32_t *row = knn + o * k;
+        const LenT *rd = kd + o * k;
+        for (int t0 = 0; t0 < k && c < eo; t0 += WAVE) {
+            const int t = t0 + lane;
+            const int32_t id = t < k ? row[t] : -1;
+            bool add = id >= 0;
+            for (int p = 0; add && p < m; p++) add = rv_nb[b + p] != id;
+            const uint64_t bal = ballot(add);
+            const int r = c + mbcnt(bal);
+            if (WRITE && add && r < eo) keys[w + r] = make_key(len_ord(rd[t]), (uint32_t)id);
+            c = min(eo, c + __popcll(bal));
+        }
+    }
+    if (!WRITE && lane == 0) out_cnt[o] = c;
 }
 
 // --------------------------------------------------------- Algorithms 4/5 --
@@ -348,6 +442,98 @@ onng_status adjust_degree_launch(const int32_t *knn, const void *kd, int64_t n, 
                                            nnz_out, ws, st);
     return adjust_degree_impl<float>(knn, static_cast<const float *>(kd), n, k, e_o, e_i, offsets,
                                      nbrs, static_cast<float *>(lens), nnz_cap, nnz_out, ws, st);
+}
+
+size_t adjust_degree_constrained_ws(int64_t n, int32_t k, int32_t e_o, int32_t e_i) {
+    const int64_t nrev = n * (int64_t)std::min(e_i, k);
+    const int64_t cap = nrev + n * (int64_t)std::min(e_o, k);
+    Carver c(nullptr);
+    c.take<int64_t>(n + 1);            // |N(G_t, o)|
+    c.take<int64_t>(n + 1);            // G_t offsets
+    c.take<int32_t>(n);                // cursors
+    c.take<int32_t>(n);                // first source per node
+    c.take<uint64_t>(nrev);            // G_t keys
+    c.take<int32_t>(nrev);             // G_t ids, sorted per node
+    c.take<int32_t>(nrev);             // G_t lengths (4 bytes)
+    c.take<int64_t>(n + 1);            // kept counts
+    c.take<uint64_t>(cap);             // kept keys
+    c.take<char>(scan_temp_bytes(n + 1));
+    return c.size() + 256;
+}
+
+template <typename LenT>
+static onng_status adjust_degree_constrained_impl(const int32_t *knn, const LenT *kd, int64_t n,
+                                                  int32_t k, int32_t e_o, int32_t e_i,
+                                                  int64_t *offsets, int32_t *nbrs, LenT *lens,
+                                                  int64_t nnz_cap, int64_t *nnz_out, void *ws,
+                                                  hipStream_t st) {
+    const int ei = std::min(e_i, k);
+    const int eo = e_o;
+    const int64_t nrev = n * (int64_t)ei;
+    const int64_t cap = nrev + n * (int64_t)std::min(e_o, k);
+    Carver c(ws);
+    int64_t *cnt = c.take<int64_t>(n + 1);
+    int64_t *rev_off = c.take<int64_t>(n + 1);
+    int32_t *cursor = c.take<int32_t>(n);
+    int32_t *first_src = c.take<int32_t>(n);
+    uint64_t *rkeys = c.take<uint64_t>(nrev);
+    int32_t *rv_nb = c.take<int32_t>(nrev);
+    LenT *rv_len = reinterpret_cast<LenT *>(c.take<int32_t>(nrev));
+    int64_t *ocnt = c.take<int64_t>(n + 1);
+    uint64_t *okeys = c.take<uint64_t>(cap);
+    size_t tb = scan_temp_bytes(n + 1);
+    void *tmp = c.take<char>(tb);
+    ONNG_HIP(hipMemsetAsync(cnt, 0, sizeof(int64_t) * (n + 1), st));
+    ONNG_HIP(hipMemsetAsync(ocnt, 0, sizeof(int64_t) * (n + 1), st));
+    ONNG_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * n, st));
+    if (n > 0) {
+        hipLaunchKernelGGL(sac_rcount_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, knn, n,
+                           k, ei, cnt);
+        ONNG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt, rev_off, (int)(n + 1), st));
+        hipLaunchKernelGGL((sac_scatter_kernel<LenT>), dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                           knn, kd, n, k, ei, rev_off, cursor, rkeys, first_src);
+        hipLaunchKernelGGL((segment_rank_sort_kernel<LenT>), dim3((unsigned)n), dim3(256),
+                           4096 * sizeof(uint64_t), st, rev_off, n, rkeys, rv_nb, rv_len);
+        hipLaunchKernelGGL((sac_select_kernel<LenT, false>), dim3(blocks_for(n * WAVE, 256)),
+                           dim3(256), 0, st, rev_off, rv_nb, rv_len, first_src, knn, kd, n, k, eo,
+                           ocnt, nullptr, nullptr);
+        ONNG_HIP(hipGetLastError());
+    }
+    ONNG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, ocnt, offsets, (int)(n + 1), st));
+    ONNG_HIP(hipMemcpyAsync(nnz_out, offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    ONNG_HIP(hipStreamSynchronize(st));
+    if (*nnz_out > nnz_cap) {
+        set_error("onng_adjust_degree_constrained: nnz_capacity too small");
+        return ONNG_ERR_CAPACITY;
+    }
+    if (*nnz_out > cap) {
+        set_error("onng_adjust_degree_constrained: more edges than the workspace bound");
+        return ONNG_ERR_CAPACITY;
+    }
+    if (n > 0) {
+        hipLaunchKernelGGL((sac_select_kernel<LenT, true>), dim3(blocks_for(n * WAVE, 256)),
+                           dim3(256), 0, st, rev_off, rv_nb, rv_len, first_src, knn, kd, n, k, eo,
+                           nullptr, offsets, okeys);
+        hipLaunchKernelGGL((segment_rank_sort_kernel<LenT>), dim3((unsigned)n), dim3(256),
+                           4096 * sizeof(uint64_t), st, offsets, n, okeys, nbrs, lens);
+    }
+    ONNG_HIP(hipGetLastError());
+    ONNG_HIP(hipStreamSynchronize(st));
+    return ONNG_OK;
+}
+
+onng_status adjust_degree_constrained_launch(const int32_t *knn, const void *kd, int64_t n,
+                                             int32_t k, bool int_len, int32_t e_o, int32_t e_i,
+                                             int64_t *offsets, int32_t *nbrs, void *lens,
+                                             int64_t nnz_cap, int64_t *nnz_out, void *ws,
+                                             hipStream_t st) {
+    if (int_len)
+        return adjust_degree_constrained_impl<int32_t>(
+            knn, static_cast<const int32_t *>(kd), n, k, e_o, e_i, offsets, nbrs,
+            static_cast<int32_t *>(lens), nnz_cap, nnz_out, ws, st);
+    return adjust_degree_constrained_impl<float>(knn, static_cast<const float *>(kd), n, k, e_o,
+                                                 e_i, offsets, nbrs, static_cast<float *>(lens),
+                                                 nnz_cap, nnz_out, ws, st);
 }
 
 size_t adjust_path_ws(int64_t n, int64_t nnz) {

@@ -25,6 +25,12 @@ onng_status adjust_degree_launch(const int32_t *knn, const void *kd, int64_t n, 
                                  int32_t *nbrs, void *lens, int64_t nnz_cap, int64_t *nnz_out,
                                  void *ws, hipStream_t st);
 size_t adjust_degree_ws(int64_t n, int32_t k, int32_t e_o, int32_t e_i);
+onng_status adjust_degree_constrained_launch(const int32_t *knn, const void *kd, int64_t n,
+                                             int32_t k, bool int_len, int32_t e_o, int32_t e_i,
+                                             int64_t *offsets, int32_t *nbrs, void *lens,
+                                             int64_t nnz_cap, int64_t *nnz_out, void *ws,
+                                             hipStream_t st);
+size_t adjust_degree_constrained_ws(int64_t n, int32_t k, int32_t e_o, int32_t e_i);
 onng_status adjust_path_launch(const onng_graph *g, bool int_len, int64_t *offsets,
                                int32_t *nbrs, void *lens, int64_t *nnz_out, void *ws,
                                hipStream_t st);
@@ -626,6 +632,34 @@ onng_status onng_adjust_degree(const int32_t *knn_ids, const void *knn_dists, in
     }
     return adjust_degree_launch(knn_ids, knn_dists, n, k, int_dist(data_dtype, metric), e_o, e_i,
                                 offsets, nbrs, lens, nnz_capacity, nnz_out, ws, as_stream(stream));
+}
+
+size_t onng_adjust_degree_constrained_workspace_size(int64_t n, int32_t k, int32_t e_o,
+                                                      int32_t e_i) {
+    if (n < 0 || k < 0 || e_o < 0 || e_i < 0) return 0;
+    return adjust_degree_constrained_ws(n, k, e_o, e_i);
+}
+
+onng_status onng_adjust_degree_constrained(const int32_t *knn_ids, const void *knn_dists,
+                                           int64_t n, int32_t k, int32_t data_dtype,
+                                           int32_t metric, int32_t e_o, int32_t e_i,
+                                           int64_t *offsets, int32_t *nbrs, void *lens,
+                                           int64_t nnz_capacity, int64_t *nnz_out, void *ws,
+                                           size_t ws_bytes, void *stream) {
+    set_error("");
+    ONNG_CHECK_ARG(n >= 0 && k >= 1 && e_o >= 0 && e_i >= 0, "bad sizes");
+    ONNG_CHECK_ARG(n == 0 || (knn_ids && knn_dists), "kNN table is null");
+    ONNG_CHECK_ARG(offsets && nnz_out, "outputs are null");
+    ONNG_CHECK_ARG(nnz_capacity == 0 || (nbrs && lens), "nbrs/lens are null");
+    ONNG_CHECK_ARG(data_dtype >= ONNG_U8 && data_dtype <= ONNG_FP8_E4M3, "unknown dtype");
+    ONNG_CHECK_ARG(n <= 0x7fffffffLL, "more than 2^31-1 nodes");
+    if (ws_bytes < adjust_degree_constrained_ws(n, k, e_o, e_i) || !ws) {
+        set_error("onng_adjust_degree_constrained: workspace too small");
+        return ONNG_ERR_WORKSPACE;
+    }
+    return adjust_degree_constrained_launch(knn_ids, knn_dists, n, k, int_dist(data_dtype, metric),
+                                            e_o, e_i, offsets, nbrs, lens, nnz_capacity, nnz_out,
+                                            ws, as_stream(stream));
 }
 
 size_t onng_adjust_path_workspace_size(int64_t n, int64_t nnz) {

@@ -141,6 +141,82 @@ def test_adjust_degree_float_and_ties(e_o, e_i):
     assert np.array_equal(host(gg.lens), ln.astype(np.float32))
 
 
+def _sac_gpu_vs_oracle(knn, kd, e_o, e_i, int_len):
+    A, Lb = api(), L()
+    off, nb, ln = orc.adjust_degree_constrained(knn, kd.astype(np.float64), e_o, e_i)
+    dt = np.int32 if int_len else np.float32
+    g = A.adjust_degree_constrained(to_dev(knn), to_dev(kd.astype(dt)),
+                                    Lb.U8 if int_len else Lb.F32, Lb.L2SQ, e_o, e_i)
+    assert np.array_equal(host(g.offsets), off)
+    assert np.array_equal(host(g.nbrs), nb)
+    assert np.array_equal(host(g.lens), ln.astype(dt))
+    return off
+
+
+@pytest.mark.parametrize("e_o,e_i", [(10, 30), (5, 0), (0, 5), (1, 1), (20, 10), (300, 20)])
+def test_adjust_degree_constrained_u8_c1(e_o, e_i):
+    P = c1_problem()
+    say("adjust_degree_constrained c1", e_o, e_i)
+    _sac_gpu_vs_oracle(P["knn"], P["kd"], e_o, e_i, True)
+
+
+@pytest.mark.parametrize("e_o,e_i", [(3, 7), (7, 3), (12, 12), (40, 12)])
+def test_adjust_degree_constrained_float_ties_ragged(e_o, e_i):
+    say("adjust_degree_constrained float/ties/ragged", e_o, e_i)
+    x = dg.random_tie_u8(400, 5, 9, levels=4)
+    knn, kd = orc.knn_graph(orc.Vectors.from_array(x, orc.L2SQ), 12)
+    # integer lengths with many ties
+    _sac_gpu_vs_oracle(knn, kd, e_o, e_i, True)
+    # float lengths; every 7th row cut short (padded with -1 / +inf)
+    g = np.random.default_rng(e_o * 17 + e_i)
+    kdf = np.sort((kd + g.uniform(0, 0.5, kd.shape)).astype(np.float32), axis=1)
+    knn = knn.copy()
+    for r in range(0, 400, 7):
+        cut = 1 + r % 12
+        knn[r, 12 - cut:] = -1
+        kdf[r, 12 - cut:] = np.inf
+    _sac_gpu_vs_oracle(knn, kdf, e_o, e_i, False)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 65])
+def test_adjust_degree_constrained_tiny(n):
+    say("adjust_degree_constrained tiny", n)
+    k = 3
+    knn = np.full((n, k), -1, np.int32)
+    kd = np.full((n, k), np.iinfo(np.int32).max, np.int64)
+    for m in range(n):
+        others = [j for j in range(n) if j != m][:k]
+        knn[m, :len(others)] = others
+        kd[m, :len(others)] = [abs(j - m) for j in others]
+        order = np.lexsort((knn[m, :len(others)], kd[m, :len(others)]))
+        knn[m, :len(others)] = knn[m, :len(others)][order]
+        kd[m, :len(others)] = kd[m, :len(others)][order]
+    off = _sac_gpu_vs_oracle(knn, kd, 2, 2, True)
+    assert len(off) == n + 1
+
+
+def test_adjust_degree_constrained_hub_lists():
+    """One node in every row: its N(G_t, o) holds 6000 members (longer than the
+    on-chip sort's 4096 and many wave chunks); lengths tie often."""
+    say("adjust_degree_constrained hub")
+    n, k = 6000, 4
+    g = np.random.default_rng(5)
+    knn = np.empty((n, k), np.int32)
+    kd = np.empty((n, k), np.int64)
+    for m in range(n):
+        ids = [0] if m else []
+        while len(ids) < k:
+            j = int(g.integers(1, n))
+            if j != m and j not in ids:
+                ids.append(j)
+        d = g.integers(1, 6, size=k)
+        order = np.lexsort((ids, d))
+        knn[m] = np.array(ids)[order]
+        kd[m] = d[order]
+    for e_o, e_i in [(5, 4), (2, 2), (50, 3)]:
+        _sac_gpu_vs_oracle(knn, kd, e_o, e_i, True)
+
+
 def test_adjust_path_u8_c1():
     P = c1_problem()
     say("adjust_path c1")

@@ -107,6 +107,50 @@ def test_c2_degree_adjustment_closed_form():
         assert got_l.tolist() == [l for _, l in want], o
 
 
+def test_c2_constrained_degree_adjustment_sampled():
+    """Algorithm 3 on the 1M-node graph, sampled nodes against its first-source
+    form (pinned to the oracle's sequential run on the CPU): o keeps o -> m,
+    m in N(G_t, o) in (length, id) order, when m is among the first e_o or o
+    is the first, by (|N(G_t, x)|, x), of row m's first e_i; nodes with
+    |N(G_t, o)| < e_o are filled from their own rows up to e_o."""
+    P = c2()
+    cfg = P["cfg"]
+    knn, kd = P["knn"], P["kd"]
+    A, Lb = api(), L()
+    say("c2: constrained degree adjustment on the GPU")
+    g = A.adjust_degree_constrained(to_dev(knn), to_dev(kd), Lb.U8, Lb.L2SQ, cfg.e_o, cfg.e_i)
+    off, nb, ln = host(g.offsets), host(g.nbrs), host(g.lens)
+    n = cfg.n_base
+    ei = min(cfg.e_i, cfg.knn_k)
+    head = knn[:, :ei]
+    cnt = np.bincount(head.ravel(), minlength=n)
+    assert np.bincount(nb, minlength=n).min() >= 1          # every node gets an incoming edge
+    nodes = _sample(n, N_NODES, 7)
+    tgt = head.ravel()
+    hit = np.isin(tgt, nodes)
+    src = np.nonzero(hit)[0] // ei
+    pos = np.nonzero(hit)[0] % ei
+    tg = tgt[hit]
+    order = np.argsort(tg, kind="stable")
+    src, pos, tg = src[order], pos[order], tg[order]
+    starts = np.searchsorted(tg, nodes, side="left")
+    ends = np.searchsorted(tg, nodes, side="right")
+    mem = np.unique(src)
+    ck = cnt[head[mem]].astype(np.int64) * (1 << 32) + head[mem]
+    first = dict(zip(mem.tolist(), head[mem, np.argmin(ck, axis=1)].tolist()))
+    for o, s0, s1 in zip(nodes, starts, ends):
+        S = sorted((int(kd[m, p]), int(m)) for m, p in zip(src[s0:s1], pos[s0:s1]))
+        want = {m: l for t, (l, m) in enumerate(S) if t < cfg.e_o or first[m] == o}
+        if len(S) < cfg.e_o:
+            for m, l in zip(knn[o].tolist(), kd[o].tolist()):
+                if len(want) >= cfg.e_o:
+                    break
+                want.setdefault(m, l)
+        want = sorted(want.items(), key=lambda t: (t[1], t[0]))
+        assert nb[off[o]:off[o + 1]].tolist() == [m for m, _ in want], o
+        assert ln[off[o]:off[o + 1]].tolist() == [l for _, l in want], o
+
+
 def test_c2_path_adjustment_decisions():
     """Algorithm 4 visits, in round j, every node n (ascending id) with more
     than j edges in the degree-adjusted graph G_e and keeps its j-th edge
