@@ -18,6 +18,7 @@ JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -95,6 +96,21 @@ def parse():
                     help="query batches in flight in the timed region (one stream each)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the library's default launch shape instead of a tuned one")
+    ap.add_argument("--degree-adjust", default="sa", choices=["sa", "sac"],
+                    help="static degree adjustment before path adjustment: Algorithm 2 (sa) "
+                         "or Algorithm 3, with constraints (sac)")
+    ap.add_argument("--e-o", type=int, default=None, help="override the workload's e_o")
+    ap.add_argument("--e-i", type=int, default=None, help="override the workload's e_i")
+    ap.add_argument("--da-grid", default="inf,10:20,20:20,30:20,50:20,30:10,30:30,30:40",
+                    help="--da-sweep settings: 'inf' or e_0:w_e, comma-separated")
+    ap.add_argument("--tune-degrees", action="store_true",
+                    help="instead of the headline run: minimise Equation 2's loss over "
+                         "(e_o, e_i) by hill climbing from the workload's values")
+    ap.add_argument("--tune-step", type=int, default=5, help="hill-climbing step")
+    ap.add_argument("--da-sweep", action="store_true",
+                    help="instead of the headline run: for a grid of (e_0, w_e) of Equation 1, "
+                         "and for an unlimited e_p, the plain f32 search range reaching recall "
+                         "0.95 and 0.99, with its distance computations and time")
     ap.add_argument("--search-only", action="store_true",
                     help="after the index and operating points, only loop the search kernel "
                          "(used under rocprofv3)")
@@ -141,6 +157,9 @@ def main():
         cfg = dg.scaled(cfg, cfg.n_base, cfg.n_query, n_train=args.n_train)
     if cfg.n_train == 0:     # c2 shares its data with c4, which has training queries
         cfg = dg.scaled(cfg, cfg.n_base, cfg.n_query, n_train=args.n_train or 100_000)
+    if args.e_o is not None or args.e_i is not None:
+        cfg = dataclasses.replace(cfg, e_o=args.e_o if args.e_o is not None else cfg.e_o,
+                                  e_i=args.e_i if args.e_i is not None else cfg.e_i)
     is_u8 = cfg.kind == "u8"
     metric = L.L2SQ if cfg.kind != "f32cos" else L.COSINE
     K = 10
@@ -190,16 +209,31 @@ def main():
         return perm[ids_t.long()] if perm is not None else ids_t
 
     ids, d = timed("knn_s", lambda: A.build_knn(base, cfg.knn_k))
-    sa = timed("adjust_degree_s", lambda: A.adjust_degree(ids, d, base.dtype, metric, cfg.e_o,
-                                                          cfg.e_i))
+    if args.degree_adjust == "sac":
+        sa = timed("adjust_degree_constrained_s", lambda: A.adjust_degree_constrained(
+            ids, d, base.dtype, metric, cfg.e_o, cfg.e_i))
+    else:
+        sa = timed("adjust_degree_s", lambda: A.adjust_degree(ids, d, base.dtype, metric,
+                                                              cfg.e_o, cfg.e_i))
     graph = timed("adjust_path_s", lambda: A.adjust_path(sa, base.dtype, metric))
-    del ids, d
+    if not args.tune_degrees:
+        del ids, d
     if args.row_align > 16:
         # searched rows start on cache-line boundaries, so a gathered row
         # touches the fewest lines
         base = A.Vectors.from_tensor(xt, metric,
                                      pitch=A.row_pitch(cfg.dim, base.dtype, args.row_align))
-    log(f"edges: SA {sa.nnz}, PA {graph.nnz} (mean outdegree {graph.nnz / cfg.n_base:.1f})")
+    log(f"edges: {args.degree_adjust.upper()} {sa.nnz}, PA {graph.nnz} "
+        f"(mean outdegree {graph.nnz / cfg.n_base:.1f})")
+    n_adj_edges = sa.nnz
+    # Table 4's statistics of the degree-adjusted and the path-adjusted graph
+    gstats = {}
+    for gname, gg in ((args.degree_adjust, sa), ("pa", graph)):
+        st = A.graph_stats(gg, base.dtype, metric, 0.05, 10)
+        gstats[gname] = dict(top5_outdegree=round(st[0], 2), bottom5_indegree=round(st[1], 2),
+                             indegree_distance=round(st[2], 5))
+        log(f"graph {gname}: mean top-5% outdegree {st[0]:.1f}, bottom-5% indegree {st[1]:.1f}, "
+            f"mean indegree distance {st[2]:.4f}")
     del sa
     seeds, _ = A.topk(queries, base, NS, cand=piv)
     gt_ids, _ = timed("ground_truth_s", lambda: A.ground_truth(queries, base, K))
@@ -261,6 +295,62 @@ def main():
                                            ep=LR.dynamic_ep(e))
     curve = {"plain": [measure(make_plain, e, "plain") for e in curve_eps]}
     result = {"plain": {str(t): bisect(make_plain, t, 0.0, 1.0, "plain") for t in (0.95, 0.99)}}
+
+    if args.tune_degrees:
+        # Equation 2's loss over recall [0.90, 0.98] on 10,000 training
+        # queries, minimised over (e_o, e_i) by hill climbing
+        from paper_1810_07355_amd import tune
+        tq_np = dg.train_queries(cfg)[:cfg.n_query]
+        TQ = A.Vectors.from_tensor(torch.from_numpy(tq_np).to(dev), metric)
+        tseeds, _ = A.topk(TQ, base, NS, cand=piv)
+        tgt = to_orig(A.ground_truth(TQ, base, K)[0]).cpu().numpy()
+        adjust = A.adjust_degree_constrained if args.degree_adjust == "sac" else A.adjust_degree
+        evals = []
+
+        def loss(eo, ei):
+            t0 = time.time()
+            g = A.adjust_path(adjust(ids, d, base.dtype, metric, eo, ei), base.dtype, metric)
+
+            def search(e):
+                req = A.SearchRequest(base, g, TQ, tseeds, k=K, eps=e, **idm,
+                                      ep=LR.dynamic_ep(e)).run()
+                return (float(LR.recall_by_ids(req.ids.cpu().numpy(), tgt, K).mean()),
+                        float(req.dc.float().mean()))
+            Lv, pts = tune.degree_loss(search, 0.90, 0.98)
+            evals.append(dict(e_o=eo, e_i=ei, L=Lv, mean_dc=10 ** Lv if math.isfinite(Lv) else None,
+                              pa_edges=g.nnz, samples=[[round(e, 5), round(p, 5), round(c, 1)]
+                                                       for e, p, c in pts]))
+            log(f"L({eo}, {ei}) = {Lv:.4f} (10^L = {10 ** Lv:.0f} distance computations), "
+                f"{g.nnz / cfg.n_base:.1f} edges per node, {time.time() - t0:.1f} s")
+            return Lv
+        pt, best, _ = tune.hill_climb(loss, cfg.e_o, cfg.e_i, args.tune_step)
+        print(json.dumps({"tune_degrees": {"degree_adjust": args.degree_adjust,
+                                           "start": [cfg.e_o, cfg.e_i], "step": args.tune_step,
+                                           "best": list(pt), "L": best, "mean_dc": 10 ** best,
+                                           "evaluations": evals},
+                          "workload": cfg.name, "build_s": build}), flush=True)
+        return
+
+    if args.da_sweep:
+        da = []
+        settings = [(None, None) if t == "inf" else tuple(float(v) for v in t.split(":"))
+                    for t in args.da_grid.split(",")]
+        for e0, we in settings:
+            nm = "ep=inf" if e0 is None else f"e0={e0},we={we}"
+            mk = (lambda e: A.SearchRequest(base, graph, queries, seeds, k=K, eps=e, **idm)) \
+                if e0 is None else \
+                (lambda e, e0=e0, we=we: A.SearchRequest(base, graph, queries, seeds, k=K, eps=e,
+                                                         **idm, ep=LR.dynamic_ep(e, e0, we)))
+            row = dict(e0=e0, we=we)
+            for t in (0.95, 0.99):
+                row[str(t)] = bisect(mk, t, 0.0, 1.0, nm)
+            da.append(row)
+        print(json.dumps({"da_sweep": da, "workload": cfg.name, "degree_adjust":
+                          args.degree_adjust, "e_o": cfg.e_o, "e_i": cfg.e_i,
+                          "edges": {"adjusted": n_adj_edges, "pa": graph.nnz},
+                          "graph_stats": gstats, "build_s": build}),
+              flush=True)
+        return
 
     lp_rows = None
     learned_pts = {}
@@ -659,7 +749,9 @@ def main():
         "config": {
             "workload": (f"{cfg.name}: {cfg.n_base:,} base + {cfg.n_query:,} queries, dim "
                          f"{cfg.dim}, {cfg.kind}, {cfg.n_clusters} clusters; kNN k={cfg.knn_k}, "
-                         f"e_o={cfg.e_o}/e_i={cfg.e_i}, path adjustment; k={K}, {NS} seeds "
+                         f"e_o={cfg.e_o}/e_i={cfg.e_i}"
+                         f"{' with constraints' if args.degree_adjust == 'sac' else ''}, "
+                         f"path adjustment; k={K}, {NS} seeds "
                          f"from {piv.numel()} pivots; learned eps for recall 0.95, "
                          f"{args.lp if not is_u8 else 'u8'} rows + f32 rerank of 4k"),
             "global_batch": cfg.n_query,
@@ -693,6 +785,7 @@ def main():
         "operating_points": result,
         "curve": curve,
         "build_s": build,
+        "graph_stats": gstats,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

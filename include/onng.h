@@ -11,8 +11,9 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    Calls enqueue their kernels on it and return after argument validation;
  *    results are valid once the stream is synchronised.  Calls that return a
- *    count to a host pointer (onng_adjust_degree, onng_adjust_degree_constrained,
- *    onng_adjust_path) synchronise the stream themselves.
+ *    count or result to a host pointer (onng_adjust_degree,
+ *    onng_adjust_degree_constrained, onng_adjust_path, onng_graph_stats)
+ *    synchronise the stream themselves.
  *  - Scratch memory comes from the caller: `ws`/`ws_bytes`, sized by the
  *    matching *_workspace_size function.  The library allocates no device
  *    memory of its own (the tuning cache is host memory).
@@ -175,6 +176,26 @@ onng_status onng_adjust_path(const onng_graph *in, int32_t data_dtype, int32_t m
                              int64_t *offsets, int32_t *nbrs, void *lens, int64_t *nnz_out,
                              void *ws, size_t ws_bytes, void *stream);
 size_t onng_adjust_path_workspace_size(int64_t n, int64_t nnz);
+
+/* ------------------------------------------------------------------------ */
+/* Graph statistics — Table 4                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Degree shape and incoming-edge lengths of a graph (Section 3.2, Table 4),
+ * with t = max(1, floor(frac * n)) (0 when n = 0).  out (host, [3]):
+ *   out[0]  mean out-degree of the t nodes of largest out-degree;
+ *   out[1]  mean in-degree of the t nodes of smallest in-degree;
+ *   out[2]  mean edge length after transposing the graph and keeping each
+ *           node's `keep` shortest incoming edges (all of them when it has
+ *           fewer), over all kept edges; a squared-L2 length enters as its
+ *           square root (the Euclidean distance), a cosine length as is.
+ *           0 when no edge is kept.
+ * Table 4 uses frac = 0.05 and keep = 10.  lens must be present, in the
+ * distance type of data_dtype/metric.  Sums are in double in a fixed order.
+ * Synchronises the stream. */
+onng_status onng_graph_stats(const onng_graph *g, int32_t data_dtype, int32_t metric, double frac,
+                             int32_t keep, double *out, void *ws, size_t ws_bytes, void *stream);
+size_t onng_graph_stats_workspace_size(int64_t n, int64_t nnz);
 
 /* ------------------------------------------------------------------------ */
 /* Search — Algorithm 1 (KnnSearch)                                         */

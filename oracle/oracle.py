@@ -210,6 +210,84 @@ def adjust_path(off, nbrs, lens):
     return oo, on[:nnz.value], ol[:nnz.value]
 
 
+# ------------------------------------------------------ graph statistics --
+
+def graph_stats(off, nbrs, lens, metric: int, frac: float = 0.05, keep: int = 10):
+    """Table 4's graph statistics, from their definitions in Section 3.2:
+    mean out-degree of the t nodes of largest out-degree, mean in-degree of
+    the t nodes of smallest in-degree (t = max(1, floor(frac * n))), and the
+    mean edge length of the transposed graph cut to each node's `keep`
+    shortest incoming edges.  A squared-L2 length counts as its square root
+    (the Euclidean distance the paper reports); a cosine length as is."""
+    off = np.asarray(off, dtype=np.int64)
+    nbrs = np.asarray(nbrs, dtype=np.int64)
+    lens = np.asarray(lens, dtype=np.float64)
+    n = len(off) - 1
+    if n == 0:
+        return 0.0, 0.0, 0.0
+    t = max(1, int(math.floor(frac * n)))
+    outdeg = np.diff(off)
+    indeg = np.bincount(nbrs, minlength=n)
+    top = float(np.sort(outdeg)[::-1][:t].sum()) / t
+    bottom = float(np.sort(indeg)[:t].sum()) / t
+    incoming = [[] for _ in range(n)]
+    for v in range(n):
+        for e in range(off[v], off[v + 1]):
+            incoming[nbrs[e]].append(lens[e])
+    kept = []
+    for lst in incoming:
+        kept.extend(sorted(lst)[:keep])
+    kept = np.array(kept, dtype=np.float64)
+    if metric == L2SQ:
+        kept = np.sqrt(kept)
+    return top, bottom, float(kept.mean()) if len(kept) else 0.0
+
+
+# ----------------------------------------- degree-parameter optimisation --
+
+def degree_loss(search, p_l=0.90, p_u=0.98, eps_max=1.0, iters=30, samples=10):
+    """Equation 2 measured from searches (Section 2.6): search(eps) gives
+    (mean precision, mean distance computations).  The upper range is the
+    binary-search midpoint whose precision first falls in [p_u, p_u + 0.005),
+    the lower one the first in (p_l - 0.005, p_l] searched below it (0 when
+    the smallest range already exceeds p_l); ten evenly spaced ranges between
+    them give (p, C); the trapezoidal rule integrates log10 C over their
+    precision span, divided by that span.  Returns (L, [(eps, p, C)]), L = inf
+    when p_u is not reached."""
+    def bracket_search(target, up, lo, hi):
+        if not up and search(lo)[0] > target:
+            return lo
+        if search(hi)[0] < target:
+            return None
+        for _ in range(iters):
+            mid = (lo + hi) / 2
+            p = search(mid)[0]
+            inside = (target <= p < target + 0.005) if up else (target - 0.005 < p <= target)
+            if inside:
+                return mid
+            too_low = p < target if up else p <= target - 0.005
+            if too_low:
+                lo = mid
+            else:
+                hi = mid
+        return hi if up else lo
+
+    eu = bracket_search(p_u, True, 0.0, eps_max)
+    if eu is None:
+        return math.inf, []
+    el = bracket_search(p_l, False, 0.0, eu)
+    eps = [el + (eu - el) * i / (samples - 1) for i in range(samples)]
+    pts = [(e,) + tuple(search(e)) for e in eps]
+    p = np.array([t[1] for t in pts])
+    y = np.log10(np.array([t[2] for t in pts], dtype=np.float64))
+    o = np.argsort(p, kind="stable")
+    p, y = p[o], y[o]
+    if p[-1] == p[0]:
+        return float(y.mean()), pts
+    area = float(np.sum((p[1:] - p[:-1]) * (y[1:] + y[:-1]) / 2))
+    return area / float(p[-1] - p[0]), pts
+
+
 # ---------------------------------------------------------------- search --
 
 def range_factor(eps: float, metric: int) -> np.float32:

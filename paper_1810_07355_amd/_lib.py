@@ -71,6 +71,9 @@ PROTOS = {
                                                  C.c_int64, P, P, C.c_size_t, P]),
     "onng_adjust_degree_constrained_workspace_size": (C.c_size_t, [C.c_int64, C.c_int32,
                                                                    C.c_int32, C.c_int32]),
+    "onng_graph_stats": (C.c_int, [P, C.c_int32, C.c_int32, C.c_double, C.c_int32, P, P,
+                                   C.c_size_t, P]),
+    "onng_graph_stats_workspace_size": (C.c_size_t, [C.c_int64, C.c_int64]),
     "onng_adjust_path": (C.c_int, [P, C.c_int32, C.c_int32, P, P, P, P, P, C.c_size_t, P]),
     "onng_adjust_path_workspace_size": (C.c_size_t, [C.c_int64, C.c_int64]),
     "onng_search": (C.c_int, [P, P, P, P, C.c_int32, P, P, P, P, P, C.c_size_t, P]),

@@ -152,6 +152,16 @@ def adjust_degree_constrained(knn_ids: torch.Tensor, knn_d: torch.Tensor, dtype:
     return Graph(off, nb[:nnz.value].clone(), ln[:nnz.value].clone())
 
 
+def graph_stats(g: Graph, dtype: int, metric: int, frac: float = 0.05, keep: int = 10):
+    """(mean top-frac out-degree, mean bottom-frac in-degree, mean length of
+    every node's `keep` shortest incoming edges) of a graph, as in Table 4."""
+    ws = _workspace(L.load().onng_graph_stats_workspace_size(g.n, g.nnz), g.offsets.device)
+    out = (C.c_double * 3)()
+    L.call("onng_graph_stats", C.byref(g.struct()), dtype, metric, frac, keep, out,
+           ws.data_ptr(), ws.numel(), _stream())
+    return tuple(out)
+
+
 def adjust_path(g: Graph, dtype: int, metric: int) -> Graph:
     dev = g.offsets.device
     off = torch.empty_like(g.offsets)

@@ -6,6 +6,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 #include <cstdint>
 #include <vector>
@@ -384,6 +385,73 @@ size_t scan_temp_bytes(int64_t n) {
     return bytes;
 }
 
+// ------------------------------------------------------ graph statistics --
+// Degree shape and incoming-edge lengths of a graph (Table 4).
+
+__global__ void gs_degree_kernel(const int64_t *off, const int32_t *nbrs, int64_t n,
+                                 int32_t *outdeg, int32_t *indeg) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    outdeg[v] = (int32_t)(off[v + 1] - off[v]);
+    for (int64_t e = off[v]; e < off[v + 1]; e++) atomicAdd(&indeg[nbrs[e]], 1);
+}
+
+// every edge's length key into its target's segment of the transposed graph
+template <typename LenT>
+__global__ void gs_transpose_kernel(const int64_t *off, const int32_t *nbrs, const LenT *lens,
+                                    int64_t n, const int64_t *toff, int32_t *cursor,
+                                    uint32_t *tkeys) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    for (int64_t e = off[v]; e < off[v + 1]; e++) {
+        int32_t t = nbrs[e];
+        int slot = atomicAdd(&cursor[t], 1);
+        tkeys[toff[t] + slot] = len_ord(lens[e]);
+    }
+}
+
+// per node: the sum of its `keep` shortest incoming lengths, as distances
+template <typename LenT, bool SQRT>
+__global__ void gs_keep_kernel(const int64_t *toff, const uint32_t *sorted, int64_t n, int keep,
+                               double *psum, double *pcnt) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int64_t b = toff[v];
+    int c = (int)min<int64_t>(keep, toff[v + 1] - b);
+    double s = 0.0;
+    for (int i = 0; i < c; i++) {
+        uint32_t key = sorted[b + i];
+        double x;
+        if constexpr (std::is_integral<LenT>::value) x = (double)key;
+        else x = (double)unord_f32(key);
+        s += SQRT ? sqrt(x) : x;
+    }
+    psum[v] = s;
+    pcnt[v] = (double)c;
+}
+
+// one block: out[slot] = sum of a[0 .. cnt) in double, in a fixed order
+template <typename T>
+__global__ void __launch_bounds__(1024) gs_sum_kernel(const T *a, int64_t cnt, double *out,
+                                                      int slot) {
+    __shared__ double part[1024];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) s += (double)a[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[slot] = part[0];
+}
+
+__global__ void gs_final_kernel(const double *sums, double t, double *res) {
+    res[0] = t > 0 ? sums[0] / t : 0.0;
+    res[1] = t > 0 ? sums[1] / t : 0.0;
+    res[2] = sums[3] > 0 ? sums[2] / sums[3] : 0.0;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- host side --
@@ -534,6 +602,102 @@ onng_status adjust_degree_constrained_launch(const int32_t *knn, const void *kd,
     return adjust_degree_constrained_impl<float>(knn, static_cast<const float *>(kd), n, k, e_o,
                                                  e_i, offsets, nbrs, static_cast<float *>(lens),
                                                  nnz_cap, nnz_out, ws, st);
+}
+
+static size_t gs_sort_temp_bytes(int64_t n, int64_t nnz) {
+    size_t a = 0, b = 0, d = 0;
+    (void)hipcub::DeviceRadixSort::SortKeys(nullptr, a, (const int32_t *)nullptr,
+                                            (int32_t *)nullptr, (int)n);
+    (void)hipcub::DeviceRadixSort::SortKeysDescending(nullptr, d, (const int32_t *)nullptr,
+                                                      (int32_t *)nullptr, (int)n);
+    a = std::max(a, d);
+    (void)hipcub::DeviceSegmentedRadixSort::SortKeys(
+        nullptr, b, (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)nnz, (int)n,
+        (const int64_t *)nullptr, (const int64_t *)nullptr);
+    return std::max(std::max(a, b), scan_temp_bytes(n + 1));
+}
+
+size_t graph_stats_ws(int64_t n, int64_t nnz) {
+    Carver c(nullptr);
+    c.take<int32_t>(n);          // out-degrees
+    c.take<int32_t>(n);          // in-degrees
+    c.take<int32_t>(n);          // sorted degrees
+    c.take<int32_t>(n);          // cursors
+    c.take<int64_t>(n + 1);      // in-degrees as int64
+    c.take<int64_t>(n + 1);      // transposed offsets
+    c.take<uint32_t>(nnz);       // incoming length keys
+    c.take<uint32_t>(nnz);       // the same, sorted per node
+    c.take<double>(n);           // per-node sums
+    c.take<double>(n);           // per-node counts
+    c.take<double>(8);           // sums and results
+    c.take<char>(gs_sort_temp_bytes(n, nnz));
+    return c.size() + 256;
+}
+
+template <typename LenT>
+static onng_status graph_stats_impl(const onng_graph *g, bool sqrt_len, double frac, int keep,
+                                    double *out, void *ws, hipStream_t st) {
+    const int64_t n = g->n, nnz = g->nnz;
+    Carver c(ws);
+    int32_t *outdeg = c.take<int32_t>(n);
+    int32_t *indeg = c.take<int32_t>(n);
+    int32_t *sdeg = c.take<int32_t>(n);
+    int32_t *cursor = c.take<int32_t>(n);
+    int64_t *in64 = c.take<int64_t>(n + 1);
+    int64_t *toff = c.take<int64_t>(n + 1);
+    uint32_t *tkeys = c.take<uint32_t>(nnz);
+    uint32_t *tsorted = c.take<uint32_t>(nnz);
+    double *psum = c.take<double>(n);
+    double *pcnt = c.take<double>(n);
+    double *sums = c.take<double>(8);
+    size_t tb = gs_sort_temp_bytes(n, nnz);
+    void *tmp = c.take<char>(tb);
+    const int64_t t = n > 0 ? std::max<int64_t>(1, (int64_t)std::floor(frac * (double)n)) : 0;
+    ONNG_HIP(hipMemsetAsync(indeg, 0, sizeof(int32_t) * n, st));
+    ONNG_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * n, st));
+    ONNG_HIP(hipMemsetAsync(sums, 0, sizeof(double) * 8, st));
+    if (n > 0) {
+        const unsigned nb = blocks_for(n, 256);
+        hipLaunchKernelGGL(gs_degree_kernel, dim3(nb), dim3(256), 0, st, g->offsets, g->nbrs, n,
+                           outdeg, indeg);
+        size_t b = tb;
+        ONNG_HIP(hipcub::DeviceRadixSort::SortKeysDescending(tmp, b, outdeg, sdeg, (int)n, 0, 32,
+                                                             st));
+        hipLaunchKernelGGL((gs_sum_kernel<int32_t>), dim3(1), dim3(1024), 0, st, sdeg, t, sums, 0);
+        b = tb;
+        ONNG_HIP(hipcub::DeviceRadixSort::SortKeys(tmp, b, indeg, sdeg, (int)n, 0, 32, st));
+        hipLaunchKernelGGL((gs_sum_kernel<int32_t>), dim3(1), dim3(1024), 0, st, sdeg, t, sums, 1);
+        hipLaunchKernelGGL(cnt_to_i64_kernel, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st,
+                           indeg, n, in64);
+        b = tb;
+        ONNG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, b, in64, toff, (int)(n + 1), st));
+        hipLaunchKernelGGL((gs_transpose_kernel<LenT>), dim3(nb), dim3(256), 0, st, g->offsets,
+                           g->nbrs, static_cast<const LenT *>(g->lens), n, toff, cursor, tkeys);
+        if (nnz > 0) {
+            b = tb;
+            ONNG_HIP(hipcub::DeviceSegmentedRadixSort::SortKeys(
+                tmp, b, tkeys, tsorted, (int)nnz, (int)n, toff, toff + 1, 0, 32, st));
+        }
+        if (sqrt_len)
+            hipLaunchKernelGGL((gs_keep_kernel<LenT, true>), dim3(nb), dim3(256), 0, st, toff,
+                               tsorted, n, keep, psum, pcnt);
+        else
+            hipLaunchKernelGGL((gs_keep_kernel<LenT, false>), dim3(nb), dim3(256), 0, st, toff,
+                               tsorted, n, keep, psum, pcnt);
+        hipLaunchKernelGGL((gs_sum_kernel<double>), dim3(1), dim3(1024), 0, st, psum, n, sums, 2);
+        hipLaunchKernelGGL((gs_sum_kernel<double>), dim3(1), dim3(1024), 0, st, pcnt, n, sums, 3);
+    }
+    hipLaunchKernelGGL(gs_final_kernel, dim3(1), dim3(1), 0, st, sums, (double)t, sums + 4);
+    ONNG_HIP(hipGetLastError());
+    ONNG_HIP(hipMemcpyAsync(out, sums + 4, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    ONNG_HIP(hipStreamSynchronize(st));
+    return ONNG_OK;
+}
+
+onng_status graph_stats_launch(const onng_graph *g, bool int_len, bool sqrt_len, double frac,
+                               int keep, double *out, void *ws, hipStream_t st) {
+    if (int_len) return graph_stats_impl<int32_t>(g, sqrt_len, frac, keep, out, ws, st);
+    return graph_stats_impl<float>(g, sqrt_len, frac, keep, out, ws, st);
 }
 
 size_t adjust_path_ws(int64_t n, int64_t nnz) {

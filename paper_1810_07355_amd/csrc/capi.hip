@@ -31,6 +31,9 @@ onng_status adjust_degree_constrained_launch(const int32_t *knn, const void *kd,
                                              int64_t nnz_cap, int64_t *nnz_out, void *ws,
                                              hipStream_t st);
 size_t adjust_degree_constrained_ws(int64_t n, int32_t k, int32_t e_o, int32_t e_i);
+onng_status graph_stats_launch(const onng_graph *g, bool int_len, bool sqrt_len, double frac,
+                               int keep, double *out, void *ws, hipStream_t st);
+size_t graph_stats_ws(int64_t n, int64_t nnz);
 onng_status adjust_path_launch(const onng_graph *g, bool int_len, int64_t *offsets,
                                int32_t *nbrs, void *lens, int64_t *nnz_out, void *ws,
                                hipStream_t st);
@@ -660,6 +663,29 @@ onng_status onng_adjust_degree_constrained(const int32_t *knn_ids, const void *k
     return adjust_degree_constrained_launch(knn_ids, knn_dists, n, k, int_dist(data_dtype, metric),
                                             e_o, e_i, offsets, nbrs, lens, nnz_capacity, nnz_out,
                                             ws, as_stream(stream));
+}
+
+size_t onng_graph_stats_workspace_size(int64_t n, int64_t nnz) {
+    if (n < 0 || nnz < 0) return 0;
+    return graph_stats_ws(n, nnz);
+}
+
+onng_status onng_graph_stats(const onng_graph *g, int32_t data_dtype, int32_t metric, double frac,
+                             int32_t keep, double *out, void *ws, size_t ws_bytes, void *stream) {
+    set_error("");
+    ONNG_CHECK_ARG(g && out, "null argument");
+    ONNG_CHECK_ARG(g->n >= 0 && g->nnz >= 0 && g->n <= 0x7fffffffLL && g->nnz <= 0x7fffffffLL,
+                   "bad graph sizes");
+    ONNG_CHECK_ARG(g->offsets && (g->nnz == 0 || (g->nbrs && g->lens)), "graph arrays are null");
+    ONNG_CHECK_ARG(frac > 0.0 && frac <= 1.0 && keep >= 0, "frac must be in (0, 1], keep >= 0");
+    ONNG_CHECK_ARG(data_dtype >= ONNG_U8 && data_dtype <= ONNG_FP8_E4M3, "unknown dtype");
+    ONNG_CHECK_ARG(metric == ONNG_L2SQ || metric == ONNG_COSINE, "unknown metric");
+    if (ws_bytes < graph_stats_ws(g->n, g->nnz) || !ws) {
+        set_error("onng_graph_stats: workspace too small");
+        return ONNG_ERR_WORKSPACE;
+    }
+    return graph_stats_launch(g, int_dist(data_dtype, metric), metric == ONNG_L2SQ, frac, keep,
+                              out, ws, as_stream(stream));
 }
 
 size_t onng_adjust_path_workspace_size(int64_t n, int64_t nnz) {

@@ -1,6 +1,8 @@
 """GPU parity: every kernel of the path against the CPU oracle on the same
 seeded inputs.  u8 data is compared bit for bit (ids, distances, distance
 computations, expansions); float data by the margin rule."""
+import math
+
 import numpy as np
 import pytest
 
@@ -217,6 +219,33 @@ def test_adjust_degree_constrained_hub_lists():
         _sac_gpu_vs_oracle(knn, kd, e_o, e_i, True)
 
 
+def test_graph_stats_against_oracle():
+    P = c1_problem()
+    A, Lb = api(), L()
+    say("graph_stats c1 SA / PA")
+    for off, nb, ln in (P["sa"], P["pa"]):
+        g = gpu_graph(off, nb, ln)
+        for frac, keep in ((0.05, 10), (0.01, 1), (1.0, 0), (0.3, 1000)):
+            got = A.graph_stats(g, Lb.U8, Lb.L2SQ, frac, keep)
+            want = orc.graph_stats(off, nb, ln, orc.L2SQ, frac, keep)
+            assert got[0] == want[0] and got[1] == want[1]
+            assert got[2] == pytest.approx(want[2], rel=1e-12, abs=0)
+    say("graph_stats float cosine lengths and an empty graph")
+    g = np.random.default_rng(11)
+    n = 3000
+    deg = g.integers(0, 30, size=n)
+    off = np.concatenate([[0], np.cumsum(deg)]).astype(np.int64)
+    nb = g.integers(0, n, size=off[-1]).astype(np.int32)
+    ln = g.uniform(0, 2, size=off[-1]).astype(np.float32)
+    gg = gpu_graph(off, nb, ln, int_len=False)
+    got = A.graph_stats(gg, Lb.F32, Lb.COSINE)
+    want = orc.graph_stats(off, nb, ln.astype(np.float64), orc.COS)
+    assert got[0] == want[0] and got[1] == want[1]
+    assert got[2] == pytest.approx(want[2], rel=1e-12, abs=0)
+    e = gpu_graph(np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert A.graph_stats(e, Lb.U8, Lb.L2SQ) == (0.0, 0.0, 0.0)
+
+
 def test_adjust_path_u8_c1():
     P = c1_problem()
     say("adjust_path c1")
@@ -317,6 +346,33 @@ def test_search_u8_c1_eps_sweep(k):
             ref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], k, eps, ep)
             r = _run_search_u8(P, G, k, eps, ep)
             _assert_exact(r, ref, k)
+
+
+def test_degree_loss_gpu_equals_oracle_c1():
+    """Equation 2 on c1's path-adjusted graph: the GPU searches and the
+    oracle's searches give the same precision and distance counts at every
+    range the binary searches visit, hence the same loss."""
+    from paper_1810_07355_amd import tune
+    P = c1_problem()
+    po, pn, _ = P["pa"]
+    G = gpu_graph(po, pn)
+    gt_ids, gt_d = orc.topk(P["qv"], P["bv"], 10)
+
+    def gpu_search(e):
+        r = _run_search_u8(P, G, 10, e, orc.dynamic_ep(e))
+        return (float(orc.recall_at_k(host(r.ids), host(r.dists), gt_d, 10).mean()),
+                float(host(r.dc).astype(np.float64).mean()))
+
+    def oracle_search(e):
+        r = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, e, orc.dynamic_ep(e))
+        return float(orc.recall_at_k(r["ids"], r["dists"], gt_d, 10).mean()), float(r["dc"].mean())
+
+    say("degree loss c1: GPU searches")
+    Lg, pg = tune.degree_loss(gpu_search, 0.90, 0.98)
+    say("degree loss c1: oracle searches")
+    Lo, po_ = orc.degree_loss(oracle_search, 0.90, 0.98)
+    assert [t[0] for t in pg] == [t[0] for t in po_]
+    assert Lg == pytest.approx(Lo, rel=1e-12) and math.isfinite(Lg)
 
 
 @pytest.mark.parametrize("shape", [dict(s_capacity=64, visited_log2=8),

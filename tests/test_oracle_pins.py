@@ -301,6 +301,111 @@ def test_sac_special_cases():
     assert np.abs(np.diff(off) - e_o).mean() < np.abs(np.diff(so) - e_o).mean()
 
 
+# --------------------------------------------------- graph statistics
+
+def test_graph_stats_star():
+    """A star: 0 -> j and j -> 0 for j = 1..39, both of squared length j^2.
+    t = floor(0.05 * 40) = 2.  Out-degrees 39, 1, 1, ... -> top two (39 + 1)/2 = 20;
+    in-degrees likewise -> bottom two 1.  Incoming, transposed and cut to 10:
+    node j keeps 0 -> j (distance j), node 0 keeps j = 1..10 (distances 1..10);
+    mean (sum 1..39 + sum 1..10) / (39 + 10) = (780 + 55) / 49."""
+    n = 40
+    adj = {0: [(j, j * j) for j in range(1, n)]}
+    for j in range(1, n):
+        adj[j] = [(0, j * j)]
+    off, nb, ln = [0], [], []
+    for v in range(n):
+        for t, l in adj[v]:
+            nb.append(t)
+            ln.append(l)
+        off.append(len(nb))
+    top, bottom, mean_in = orc.graph_stats(off, nb, ln, orc.L2SQ)
+    assert top == 20.0 and bottom == 1.0
+    assert mean_in == pytest.approx(835 / 49, rel=1e-15)
+    # the same lengths read as cosine distances are not square-rooted
+    _, _, m2 = orc.graph_stats(off, nb, ln, orc.COS, keep=1)
+    # keep = 1: node j keeps j^2, node 0 keeps 1 -> (sum j^2 + 1) / 40
+    assert m2 == pytest.approx((sum(j * j for j in range(1, n)) + 1) / 40, rel=1e-15)
+
+
+def test_graph_stats_regular_graph_and_brute_force():
+    # a directed circulant graph: every node has out- and in-degree 6
+    n = 50
+    off = np.arange(n + 1) * 6
+    nb = np.array([(v + d) % n for v in range(n) for d in (1, 2, 3, 5, 8, 13)])
+    ln = np.array([float(d) for v in range(n) for d in (1, 2, 3, 5, 8, 13)])
+    top, bottom, mean_in = orc.graph_stats(off, nb, ln, orc.COS, keep=4)
+    assert top == 6.0 and bottom == 6.0
+    assert mean_in == pytest.approx((1 + 2 + 3 + 5) / 4, rel=1e-15)
+    # random graph: top/bottom against an explicit ranking, all t
+    g = np.random.default_rng(3)
+    n = 200
+    deg = g.integers(0, 9, size=n)
+    off = np.concatenate([[0], np.cumsum(deg)])
+    nb = g.integers(0, n, size=off[-1])
+    ln = g.uniform(0, 4, size=off[-1])
+    for frac in (0.01, 0.05, 0.5, 1.0):
+        top, bottom, _ = orc.graph_stats(off, nb, ln, orc.L2SQ, frac=frac)
+        t = max(1, int(frac * n))
+        indeg = [int((nb == v).sum()) for v in range(n)]
+        assert top == pytest.approx(sum(sorted(deg.tolist(), reverse=True)[:t]) / t, rel=1e-15)
+        assert bottom == pytest.approx(sum(sorted(indeg)[:t]) / t, rel=1e-15)
+
+
+# ------------------------------------------------- Equation 2 (loss L)
+
+def _synthetic_search(a, b, scale=1.0):
+    """precision p(eps) = min(1, scale * eps); C = 10^(a + b p)."""
+    def f(e):
+        p = min(1.0, scale * e)
+        return p, 10.0 ** (a + b * p)
+    return f
+
+
+def test_degree_loss_linear_log_cost_is_exact():
+    # log10 C linear in p: the trapezoidal rule is exact, and the mean over
+    # the sampled span [p0, p9] is a + b (p0 + p9) / 2
+    for a, b, scale in ((2.0, 3.0, 1.0), (1.0, 10.0, 1.7), (3.0, 0.0, 1.3)):
+        L, pts = orc.degree_loss(_synthetic_search(a, b, scale))
+        p = [t[1] for t in pts]
+        assert len(pts) == 10
+        assert 0.895 < p[0] <= 0.90 and 0.98 <= p[-1] < 0.985      # the brackets of Section 2.6
+        assert L == pytest.approx(a + b * (p[0] + p[-1]) / 2, rel=1e-12)
+        es = [t[0] for t in pts]
+        assert np.allclose(np.diff(es), (es[-1] - es[0]) / 9)        # ten evenly spaced ranges
+
+
+def test_degree_loss_against_library_trapezoid_and_edge_cases():
+    from scipy.integrate import trapezoid
+    f = lambda e: (1 - math.exp(-12 * e), 50.0 * math.exp(30 * e))
+    L, pts = orc.degree_loss(f)
+    p = np.array([t[1] for t in pts])
+    y = np.log10([t[2] for t in pts])
+    assert L == pytest.approx(trapezoid(y, p) / (p[-1] - p[0]), rel=1e-12)
+    # constant cost: L = log10 C
+    L2, _ = orc.degree_loss(lambda e: (min(1.0, e), 123.0))
+    assert L2 == pytest.approx(math.log10(123.0), rel=1e-14)
+    # unreachable upper target
+    assert orc.degree_loss(lambda e: (0.5 * min(1.0, e), 10.0))[0] == math.inf
+    # already above p_l at eps = 0: the lower end is 0
+    L3, pts3 = orc.degree_loss(lambda e: (min(1.0, 0.95 + e), 10.0 ** (1 + e)))
+    assert pts3[0][0] == 0.0 and pts3[0][1] == pytest.approx(0.95)
+
+
+def test_package_tuner_matches_oracle_and_climbs():
+    from paper_1810_07355_amd import tune
+    for f in (_synthetic_search(2.0, 3.0), _synthetic_search(1.0, 10.0, 1.7),
+              lambda e: (1 - math.exp(-12 * e), 50.0 * math.exp(30 * e))):
+        La, pa = tune.degree_loss(f)
+        Lb, pb = orc.degree_loss(f)
+        assert La == pytest.approx(Lb, rel=1e-12) and [t[0] for t in pa] == [t[0] for t in pb]
+    # hill climbing on a convex bowl reaches the lattice point nearest its minimum
+    loss = lambda eo, ei: (eo - 42) ** 2 + 2 * (ei - 71) ** 2
+    pt, best, seen = tune.hill_climb(loss, 20, 60)
+    assert pt == (40, 70) and best == loss(40, 70)
+    assert all(v >= best for v in seen.values())
+
+
 # ---------------------------------------------------- Algorithms 4/5 (PA)
 
 def _csr_from_adj(adj, n):
