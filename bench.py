@@ -51,15 +51,19 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(workload: str):
     """HBM bytes per launch of the timed search kernel from the committed
     counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's
-    reading), or None when that summary was taken on other kernel sources."""
+    reading), or None when that summary was taken on other kernel sources or
+    on another workload."""
     try:
         with open(COUNTERS) as fh:
-            kv = dict(l.split(":", 1) for l in fh if ":" in l and not l.startswith(" "))
+            text = fh.read()
     except OSError:
         return None
+    if workload not in text:
+        return None
+    kv = dict(l.split(":", 1) for l in text.splitlines() if ":" in l and not l.startswith(" "))
     kv = {k.strip(): v.strip() for k, v in kv.items()}
     if kv.get("kernel_source_sha256") != kernel_source_hash():
         return None
@@ -690,8 +694,15 @@ def main():
                  + (4 * dim) * pool + 8 * K + 32)
     bytes_launch = float(per_query.sum())
     achieved = bytes_launch / (ms_search / 1e3) / 1e9
+    workload_str = (f"{cfg.name}: {cfg.n_base:,} base + {cfg.n_query:,} queries, dim "
+                    f"{cfg.dim}, {cfg.kind}, {cfg.n_clusters} clusters; kNN k={cfg.knn_k}, "
+                    f"e_o={cfg.e_o}/e_i={cfg.e_i}"
+                    f"{' with constraints' if args.degree_adjust == 'sac' else ''}, "
+                    f"path adjustment; k={K}, {NS} seeds "
+                    f"from {piv.numel()} pivots; learned eps for recall 0.95, "
+                    f"{args.lp if not is_u8 else 'u8'} rows + f32 rerank of 4k")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=8000.0, unit="GB/s",
-                    frac=round(achieved / 8000.0, 4), traffic=measured_traffic(),
+                    frac=round(achieved / 8000.0, 4), traffic=measured_traffic(workload_str),
                     kernel="search_kernel", bytes_per_launch=bytes_launch,
                     ms_per_launch=round(ms_search, 4),
                     bytes_per_query_mean=round(float(per_query.mean()), 1))
@@ -747,13 +758,7 @@ def main():
         "storage": "u8" if is_u8 else args.lp,
         "data": "synthetic",
         "config": {
-            "workload": (f"{cfg.name}: {cfg.n_base:,} base + {cfg.n_query:,} queries, dim "
-                         f"{cfg.dim}, {cfg.kind}, {cfg.n_clusters} clusters; kNN k={cfg.knn_k}, "
-                         f"e_o={cfg.e_o}/e_i={cfg.e_i}"
-                         f"{' with constraints' if args.degree_adjust == 'sac' else ''}, "
-                         f"path adjustment; k={K}, {NS} seeds "
-                         f"from {piv.numel()} pivots; learned eps for recall 0.95, "
-                         f"{args.lp if not is_u8 else 'u8'} rows + f32 rerank of 4k"),
+            "workload": workload_str,
             "global_batch": cfg.n_query,
             "batches_in_flight": NF,
             "max_dc": {str(t): budgets[t] for t in (0.95, 0.99)},
