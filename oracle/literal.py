@@ -11,6 +11,9 @@ same code serves exact integer and fp64 data.  Ties are broken by node id
                          over (|N(G_t, x)|, x) taken afresh every step (R10).
 * adjust_path/has_path:  Algorithms 4 and 5 (AdjustPath, HasPath).
 * paper_visited:         Algorithms 6 and 7 (Set, IsSet) as a class.
+* vptree:                the 4-way vantage-point tree of the seeds (Section
+                         3.2, Table 5), built depth first and renumbered
+                         breadth first afterwards.
 """
 from __future__ import annotations
 
@@ -129,6 +132,41 @@ def adjusted_graph_with_constraint(knn, knn_d, e_o, e_i):
             if nn not in Ge[o]:
                 Ge[o][nn] = d
     return [sorted((l, i) for i, l in Ge[o].items()) for o in range(n)]
+
+
+def vptree(ids, dist, prio, leaf_size, n_seeds):
+    """Recursive build over the row ids `ids` with dist(a, b) and priorities
+    prio[x].  Returns (vp, child, mu, seeds) lists in breadth-first numbering,
+    child[v] = first of four children or -1 - leaf."""
+    def build(members):
+        v = min(members, key=lambda x: (prio[x], x))
+        if len(members) <= leaf_size:
+            near = sorted(members, key=lambda x: (dist(v, x), x))[:n_seeds]
+            return {"vp": v, "seeds": near + [-1] * (n_seeds - len(near))}
+        rest = sorted((x for x in members if x != v), key=lambda x: (dist(v, x), x))
+        m1 = len(rest)
+        cuts = [c * m1 // 4 for c in range(5)]
+        return {"vp": v, "mu": [dist(v, rest[cuts[c]]) for c in (1, 2, 3)],
+                "kids": [build(rest[cuts[c]:cuts[c + 1]]) for c in range(4)]}
+
+    root = build(list(ids))
+    order, q = [], [root]
+    while q:                       # breadth-first numbering
+        node = q.pop(0)
+        order.append(node)
+        q.extend(node.get("kids", []))
+    index = {id(nd): i for i, nd in enumerate(order)}
+    vp, child, mu, seeds = [], [], [], []
+    for nd in order:
+        vp.append(nd["vp"])
+        if "kids" in nd:
+            child.append(index[id(nd["kids"][0])])
+            mu.append(nd["mu"])
+        else:
+            child.append(-1 - len(seeds))
+            mu.append([0.0, 0.0, 0.0])
+            seeds.append(nd["seeds"])
+    return vp, child, mu, seeds
 
 
 def has_path(Gp, ns, nd, d_ns_nd):

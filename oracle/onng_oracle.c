@@ -525,6 +525,127 @@ int or_adjust_degree_constrained(const int32_t *knn_ids, const double *knn_d, in
 }
 
 /* ------------------------------------------------------------------------- */
+/* Tree-based seeds: a 4-way vantage-point tree (Section 3.2, Table 5)        */
+/* ------------------------------------------------------------------------- */
+
+/* Distances inside the tree: exact integers on u8 (squared L2); on f32 rows
+ * fp32 arithmetic in coordinate order, each product and sum rounded on its
+ * own (squared L2, or 1 - dot for cosine).  These values decide branches,
+ * so they are fixed to one precision and order (the tree is defined in it). */
+static double vp_dist(const or_vecs *a, int64_t i, const or_vecs *b, int64_t j)
+{
+    if (a->dtype == OR_U8)
+        return or_dist(a, i, b, j);
+    const float *x = (const float *)((const uint8_t *)a->data + i * a->pitch);
+    const float *y = (const float *)((const uint8_t *)b->data + j * b->pitch);
+    float s = 0.0f;
+    if (a->metric == OR_L2SQ) {
+        for (int32_t t = 0; t < a->dim; t++) {
+            float df = x[t] - y[t];
+            float sq = df * df;
+            s = s + sq;
+        }
+        return (double)s;
+    }
+    for (int32_t t = 0; t < a->dim; t++) {
+        float pr = x[t] * y[t];
+        s = s + pr;
+    }
+    return (double)(1.0f - s);
+}
+
+typedef struct { double d; int32_t id; } did_t;
+
+static int did_cmp(const void *a, const void *b)
+{
+    const did_t *x = (const did_t *)a, *y = (const did_t *)b;
+    if (x->d != y->d) return x->d < y->d ? -1 : 1;
+    return (x->id > y->id) - (x->id < y->id);
+}
+
+static int32_t min_priority(const int32_t *ids, int64_t m, const uint32_t *prio)
+{
+    int32_t best = ids[0];
+    for (int64_t t = 1; t < m; t++) {
+        int32_t x = ids[t];
+        if (prio[x] < prio[best] || (prio[x] == prio[best] && x < best)) best = x;
+    }
+    return best;
+}
+
+int or_vptree_build(const or_vecs *B, const uint32_t *prio, int32_t leaf_size, int32_t n_seeds,
+                    int32_t *node_vp, int32_t *node_child, double *node_mu,
+                    int32_t *leaf_seeds, int64_t *n_nodes, int64_t *n_leaves)
+{
+    int64_t n = B->n;
+    if (n < 1 || leaf_size < 4 || n_seeds < 1) return -1;
+    int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *qb = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);   /* FIFO of segments */
+    int64_t *qm = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *qn = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    did_t *tmp = (did_t *)malloc(sizeof(did_t) * (size_t)n);
+    for (int64_t t = 0; t < n; t++) perm[t] = (int32_t)t;
+    int64_t head = 0, tail = 0, next = 1, leaves = 0;
+    qb[tail] = 0; qm[tail] = n; qn[tail] = 0; tail++;
+    while (head < tail) {                       /* breadth first: nodes numbered by level */
+        int64_t b = qb[head], m = qm[head], node = qn[head];
+        head++;
+        int32_t *seg = perm + b;
+        int32_t vp = min_priority(seg, m, prio);
+        node_vp[node] = vp;
+        if (m <= leaf_size) {
+            /* leaf: its seeds are the n_seeds members nearest its vantage point */
+            for (int64_t t = 0; t < m; t++) { tmp[t].id = seg[t]; tmp[t].d = vp_dist(B, vp, B, seg[t]); }
+            qsort(tmp, (size_t)m, sizeof(did_t), did_cmp);
+            for (int32_t r = 0; r < n_seeds; r++)
+                leaf_seeds[leaves * n_seeds + r] = r < m ? tmp[r].id : -1;
+            node_child[node] = (int32_t)(-1 - leaves);
+            leaves++;
+            continue;
+        }
+        /* the others in ascending (d(vp, x), x), cut into four runs of equal size */
+        int64_t m1 = 0;
+        for (int64_t t = 0; t < m; t++)
+            if (seg[t] != vp) { tmp[m1].id = seg[t]; tmp[m1].d = vp_dist(B, vp, B, seg[t]); m1++; }
+        qsort(tmp, (size_t)m1, sizeof(did_t), did_cmp);
+        seg[0] = vp;
+        for (int64_t t = 0; t < m1; t++) seg[1 + t] = tmp[t].id;
+        node_child[node] = (int32_t)next;
+        for (int32_t c = 0; c < 4; c++) {
+            int64_t r0 = c * m1 / 4, r1 = (c + 1) * m1 / 4;
+            if (c > 0) node_mu[3 * node + c - 1] = tmp[r0].d;
+            qb[tail] = b + 1 + r0; qm[tail] = r1 - r0; qn[tail] = next + c; tail++;
+        }
+        next += 4;
+    }
+    *n_nodes = next;
+    *n_leaves = leaves;
+    free(perm); free(qb); free(qm); free(qn); free(tmp);
+    return 0;
+}
+
+int or_vptree_seeds(const or_vecs *B, const or_vecs *Q, int64_t nq, const int32_t *node_vp,
+                    const int32_t *node_child, const double *node_mu,
+                    const int32_t *leaf_seeds, int32_t n_seeds, int32_t *seeds, int32_t *dc)
+{
+    for (int64_t q = 0; q < nq; q++) {
+        int64_t node = 0;
+        int32_t cnt = 0;
+        while (node_child[node] >= 0) {
+            double d = vp_dist(Q, q, B, node_vp[node]);
+            cnt++;
+            int c = (d >= node_mu[3 * node]) + (d >= node_mu[3 * node + 1]) +
+                    (d >= node_mu[3 * node + 2]);
+            node = node_child[node] + c;
+        }
+        int64_t leaf = -1 - (int64_t)node_child[node];
+        for (int32_t r = 0; r < n_seeds; r++) seeds[q * n_seeds + r] = leaf_seeds[leaf * n_seeds + r];
+        dc[q] = cnt;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Algorithms 4 and 5: AdjustPath / HasPath                                   */
 /* ------------------------------------------------------------------------- */
 

@@ -78,6 +78,23 @@ int or_adjust_degree_constrained(const int32_t *knn_ids, const double *knn_d, in
                                  int64_t *offsets, int32_t *nbrs, double *lens,
                                  int64_t nnz_cap, int64_t *nnz_out);
 
+/* ---- Tree-based seeds: 4-way vantage-point tree (Section 3.2, Table 5) ----
+ * A node holding m > leaf_size rows takes its lowest-priority row (ties by
+ * id) as vantage point; the other m-1 rows sorted by (d(vp, x), x) are cut
+ * at floor(c (m-1) / 4), c = 0..4, into four children, and mu[c-1] is the
+ * distance of child c's first row.  A node of at most leaf_size rows is a
+ * leaf; its seeds are its n_seeds rows nearest its own vantage point (padded
+ * with -1).  Nodes are numbered breadth first; node_child holds the first of
+ * four consecutive children or -1 - leaf.  A query takes child
+ * #{c : d(q, vp) >= mu[c]} at every inner node (one distance computation
+ * each).  f32 distances are fp32 in coordinate order; u8 exact. */
+int or_vptree_build(const or_vecs *B, const uint32_t *prio, int32_t leaf_size, int32_t n_seeds,
+                    int32_t *node_vp, int32_t *node_child, double *node_mu,
+                    int32_t *leaf_seeds, int64_t *n_nodes, int64_t *n_leaves);
+int or_vptree_seeds(const or_vecs *B, const or_vecs *Q, int64_t nq, const int32_t *node_vp,
+                    const int32_t *node_child, const double *node_mu,
+                    const int32_t *leaf_seeds, int32_t n_seeds, int32_t *seeds, int32_t *dc);
+
 /* ---- Algorithms 4 and 5 (AdjustPath, HasPath) ---- */
 int or_adjust_path(const int64_t *in_off, const int32_t *in_nbrs,
                    const double *in_lens, int64_t n,

@@ -54,6 +54,8 @@ def lib():
         _lib.or_adjust_degree_constrained.argtypes = [P, P, C.c_int64, C.c_int32, C.c_int32,
                                                       C.c_int32, P, P, P, C.c_int64, P]
         _lib.or_adjust_path.argtypes = [P, P, P, C.c_int64, P, P, P, P]
+        _lib.or_vptree_build.argtypes = [P, P, C.c_int32, C.c_int32, P, P, P, P, P, P]
+        _lib.or_vptree_seeds.argtypes = [P, P, C.c_int64, P, P, P, P, C.c_int32, P, P]
         _lib.or_search.argtypes = [P, P, P, C.c_int64, P, C.c_int64, P, C.c_int32, P, P, P, P,
                                    P, C.c_int32, P, C.c_int32, P, P, P, P, P, P, C.c_int32]
         _lib.or_hash_size.restype = C.c_int64
@@ -286,6 +288,42 @@ def degree_loss(search, p_l=0.90, p_u=0.98, eps_max=1.0, iters=30, samples=10):
         return float(y.mean()), pts
     area = float(np.sum((p[1:] - p[:-1]) * (y[1:] + y[:-1]) / 2))
     return area / float(p[-1] - p[0]), pts
+
+
+# ------------------------------------------------- tree-based seeds ------
+
+def vptree_build(B: Vectors, prio, leaf_size: int = 100, n_seeds: int = 10):
+    """The 4-way vantage-point tree of the base rows (Section 3.2, Table 5);
+    see or_vptree_build.  Returns a dict of numpy arrays."""
+    n = B.n
+    prio = np.ascontiguousarray(prio, dtype=np.uint32)
+    vp = np.empty(n, np.int32)
+    child = np.empty(n, np.int32)
+    mu = np.zeros(3 * n, np.float64)
+    seeds = np.empty(n * n_seeds, np.int32)
+    nn, nl = C.c_int64(0), C.c_int64(0)
+    rc = lib().or_vptree_build(B.ref, prio.ctypes.data, leaf_size, n_seeds, vp.ctypes.data,
+                               child.ctypes.data, mu.ctypes.data, seeds.ctypes.data, C.byref(nn),
+                               C.byref(nl))
+    assert rc == 0
+    m, l = nn.value, nl.value
+    return dict(vp=vp[:m], child=child[:m], mu=mu[:3 * m].reshape(m, 3),
+                seeds=seeds[:l * n_seeds].reshape(l, n_seeds), n_seeds=n_seeds)
+
+
+def vptree_seeds(B: Vectors, Q: Vectors, tree):
+    """Descent of every query: (seeds [nq][n_seeds], distance computations [nq])."""
+    ns = tree["n_seeds"]
+    out = np.empty((Q.n, ns), np.int32)
+    dc = np.empty(Q.n, np.int32)
+    vp = np.ascontiguousarray(tree["vp"])
+    child = np.ascontiguousarray(tree["child"])
+    mu = np.ascontiguousarray(tree["mu"], dtype=np.float64)
+    sd = np.ascontiguousarray(tree["seeds"])
+    rc = lib().or_vptree_seeds(B.ref, Q.ref, Q.n, vp.ctypes.data, child.ctypes.data,
+                               mu.ctypes.data, sd.ctypes.data, ns, out.ctypes.data, dc.ctypes.data)
+    assert rc == 0
+    return out, dc
 
 
 # ---------------------------------------------------------------- search --

@@ -169,6 +169,14 @@ def pivots(cfg: Preset, n_pivots: int | None = None) -> np.ndarray:
     return np.sort(ids).astype(np.int32)
 
 
+def vp_priority(n: int, seed: int = 0) -> np.ndarray:
+    """Seeded random ranks 0..n-1 (a permutation), one per base row: the
+    vantage-point tree takes a node's lowest-ranked row as its vantage point,
+    which makes that choice uniformly random."""
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence(ROOT_SEED, spawn_key=(97, seed))))
+    return g.permutation(n).astype(np.uint32)
+
+
 def random_seeds(cfg: Preset, n_query: int, n_seeds: int, stream_offset: int = 0) -> np.ndarray:
     """Uniformly random seed ids per query (the paper's "rand" seeding)."""
     g = rng(cfg.config_id, 6 + stream_offset)

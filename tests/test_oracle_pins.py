@@ -406,6 +406,56 @@ def test_package_tuner_matches_oracle_and_climbs():
     assert all(v >= best for v in seen.values())
 
 
+# ------------------------------------------- tree-based seeds (Table 5)
+
+def test_vptree_literal_on_tied_u8():
+    x = dg.random_tie_u8(700, 6, 13, levels=3)
+    v = orc.Vectors.from_array(x, orc.L2SQ)
+    prio = dg.vp_priority(700, 1)
+    t = orc.vptree_build(v, prio, leaf_size=20, n_seeds=5)
+    D = ((x[:, None, :].astype(np.int64) - x[None, :, :].astype(np.int64)) ** 2).sum(-1)
+    vp, child, mu, seeds = literal.vptree(range(700), lambda a, b: int(D[a, b]), prio, 20, 5)
+    assert t["vp"].tolist() == vp and t["child"].tolist() == child
+    inner = t["child"] >= 0
+    assert np.array_equal(t["mu"][inner], np.array(mu, dtype=np.float64)[inner])
+    assert t["seeds"].tolist() == seeds
+
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_vptree_partition_and_self_descent(metric):
+    """With leaf_size = n_seeds a leaf's seed list is all its rows, so the
+    partition is visible: every row is an inner vantage point or in exactly
+    one leaf, and a row used as a query descends to its own leaf (the
+    defining property of a vantage-point tree, with no tied distances)."""
+    g = np.random.default_rng(4 + metric)
+    x = g.standard_normal((3000, 16)).astype(np.float32)
+    if metric == 1:
+        x /= np.linalg.norm(x, axis=1, keepdims=True)
+    v = orc.Vectors.from_array(x, orc.L2SQ if metric == 0 else orc.COS)
+    t = orc.vptree_build(v, dg.vp_priority(3000, 2), leaf_size=8, n_seeds=8)
+    inner = t["child"] >= 0
+    ivp = t["vp"][inner]
+    members = t["seeds"][t["seeds"] >= 0]
+    allr = np.concatenate([ivp, members])
+    assert len(allr) == 3000 and len(np.unique(allr)) == 3000
+    n_in, n_leaf = int(inner.sum()), len(t["seeds"])
+    assert len(t["vp"]) == 4 * n_in + 1 and n_leaf == 3 * n_in + 1
+    seeds, dc = orc.vptree_seeds(v, v, t)
+    leaf_of = {}
+    for l, row in enumerate(t["seeds"]):
+        for r in row[row >= 0]:
+            leaf_of[int(r)] = l
+    for r in range(3000):
+        if r in leaf_of:
+            assert seeds[r].tolist() == t["seeds"][leaf_of[r]].tolist()
+    # leaf seeds are in distance order from the leaf's vantage point (first)
+    for nd in np.nonzero(~inner)[0][:50]:
+        row = t["seeds"][-1 - t["child"][nd]]
+        assert row[0] == t["vp"][nd]
+    # depth: 3000 -> 749/750 -> 187 -> 46 -> 11 -> 2/3 rows: five inner levels on every path
+    assert dc.min() == 5 and dc.max() == 5
+
+
 # ---------------------------------------------------- Algorithms 4/5 (PA)
 
 def _csr_from_adj(adj, n):
