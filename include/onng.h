@@ -198,6 +198,54 @@ onng_status onng_graph_stats(const onng_graph *g, int32_t data_dtype, int32_t me
 size_t onng_graph_stats_workspace_size(int64_t n, int64_t nnz);
 
 /* ------------------------------------------------------------------------ */
+/* Entry seeds from a tree — Section 3.2 (tree-based index), Table 5        */
+/* ------------------------------------------------------------------------ */
+
+/* A 4-way vantage-point tree over the base rows.  A node of m > leaf_size
+ * rows takes its row of lowest (priority[row], row) as vantage point v; its
+ * other m-1 rows, sorted by (d(v, x), x), are cut at floor(c (m-1) / 4),
+ * c = 0..4, into four children, and node_mu[3 node + c - 1] is the distance
+ * of child c's first row.  A node of at most leaf_size rows is a leaf; its
+ * seeds are its n_seeds rows nearest its own vantage point, in (d, id)
+ * order, padded with -1.  Nodes are numbered breadth first (root 0);
+ * node_child[v] is the first of four consecutive children, or -1 - leaf.
+ * Tree distances: exact on u8 (squared L2); on f32 rows (squared L2 or
+ * cosine) fp32 in coordinate order, no fused multiply-add.  The paper's tree
+ * has leaves of at most 100 rows and uses the 10 rows nearest a leaf's
+ * vantage point as seeds; its fan-out is not stated, 4 gives the 6-8
+ * distance computations per query of Table 5.
+ * Device arrays are caller-owned with the stated capacities; node_capacity
+ * = leaf_capacity = n always suffices. */
+typedef struct {
+    int32_t *node_vp;         /* [node_capacity] */
+    int32_t *node_child;      /* [node_capacity] */
+    void *node_mu;            /* [3 * node_capacity], distance type of the rows */
+    int32_t *leaf_seeds;      /* [leaf_capacity * n_seeds] */
+    int64_t node_capacity;
+    int64_t leaf_capacity;
+    int32_t leaf_size;        /* 4 .. 256 */
+    int32_t n_seeds;          /* 1 .. 256 */
+    int64_t n_nodes;          /* written by onng_vptree_build */
+    int64_t n_leaves;         /* written by onng_vptree_build */
+} onng_vptree;
+
+/* Builds `tree` (a host struct; its arrays and counts are written) from
+ * `base` (u8 with ONNG_L2SQ, or f32 with either metric) and one priority per
+ * row (device [n]; a random permutation makes every vantage point a uniform
+ * draw).  ONNG_ERR_CAPACITY when a capacity is too small.  Synchronises the
+ * stream. */
+onng_status onng_vptree_build(const onng_vectors *base, const uint32_t *priority,
+                              onng_vptree *tree, void *ws, size_t ws_bytes, void *stream);
+size_t onng_vptree_build_workspace_size(int64_t n);
+
+/* Descends the tree for every query (same dtype, dim and metric as the
+ * base): seeds [nq][n_seeds] (device) get the leaf's seeds, dc [nq] (device)
+ * the distance computations spent (one per inner node). */
+onng_status onng_vptree_seeds(const onng_vectors *base, const onng_vptree *tree,
+                              const onng_vectors *queries, int32_t *seeds, int32_t *dc,
+                              void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Search — Algorithm 1 (KnnSearch)                                         */
 /* ------------------------------------------------------------------------ */
 

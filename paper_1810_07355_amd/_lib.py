@@ -31,6 +31,13 @@ class Graph_t(C.Structure):
     _fields_ = [("offsets", P), ("nbrs", P), ("lens", P), ("n", C.c_int64), ("nnz", C.c_int64)]
 
 
+class VPTree_t(C.Structure):
+    _fields_ = [("node_vp", P), ("node_child", P), ("node_mu", P), ("leaf_seeds", P),
+                ("node_capacity", C.c_int64), ("leaf_capacity", C.c_int64),
+                ("leaf_size", C.c_int32), ("n_seeds", C.c_int32), ("n_nodes", C.c_int64),
+                ("n_leaves", C.c_int64)]
+
+
 class Predictor_t(C.Structure):
     _fields_ = [("w1_bf16", P), ("b1", P), ("w2_bf16", P), ("b2", P), ("feat_mean", P),
                 ("feat_std", P), ("shift", P), ("head_per_query", P), ("head", C.c_int32),
@@ -74,6 +81,9 @@ PROTOS = {
     "onng_graph_stats": (C.c_int, [P, C.c_int32, C.c_int32, C.c_double, C.c_int32, P, P,
                                    C.c_size_t, P]),
     "onng_graph_stats_workspace_size": (C.c_size_t, [C.c_int64, C.c_int64]),
+    "onng_vptree_build": (C.c_int, [P, P, P, P, C.c_size_t, P]),
+    "onng_vptree_build_workspace_size": (C.c_size_t, [C.c_int64]),
+    "onng_vptree_seeds": (C.c_int, [P, P, P, P, P, P]),
     "onng_adjust_path": (C.c_int, [P, C.c_int32, C.c_int32, P, P, P, P, P, C.c_size_t, P]),
     "onng_adjust_path_workspace_size": (C.c_size_t, [C.c_int64, C.c_int64]),
     "onng_search": (C.c_int, [P, P, P, P, C.c_int32, P, P, P, P, P, C.c_size_t, P]),

@@ -162,6 +162,53 @@ def graph_stats(g: Graph, dtype: int, metric: int, frac: float = 0.05, keep: int
     return tuple(out)
 
 
+class VPTree:
+    """A 4-way vantage-point tree for entry seeds (Section 3.2, Table 5);
+    built by vptree_build, its arrays live on the device."""
+
+    def __init__(self, n: int, device, int_dist: bool, leaf_size: int, n_seeds: int):
+        self.node_vp = torch.empty(n, dtype=torch.int32, device=device)
+        self.node_child = torch.empty(n, dtype=torch.int32, device=device)
+        self.node_mu = torch.empty(3 * n, dtype=torch.int32 if int_dist else torch.float32,
+                                   device=device)
+        self.leaf_seeds = torch.empty(n * n_seeds, dtype=torch.int32, device=device)
+        self.t = L.VPTree_t(self.node_vp.data_ptr(), self.node_child.data_ptr(),
+                            self.node_mu.data_ptr(), self.leaf_seeds.data_ptr(), n, n,
+                            leaf_size, n_seeds, 0, 0)
+
+    @property
+    def n_nodes(self):
+        return self.t.n_nodes
+
+    @property
+    def n_leaves(self):
+        return self.t.n_leaves
+
+    @property
+    def n_seeds(self):
+        return self.t.n_seeds
+
+
+def vptree_build(base: Vectors, priority: torch.Tensor, leaf_size: int = 100,
+                 n_seeds: int = 10) -> VPTree:
+    dev = priority.device
+    tree = VPTree(base.n, dev, base.dtype == L.U8, leaf_size, n_seeds)
+    ws = _workspace(L.load().onng_vptree_build_workspace_size(base.n), dev)
+    L.call("onng_vptree_build", base.ref, priority.data_ptr(), C.byref(tree.t),
+           ws.data_ptr(), ws.numel(), _stream())
+    return tree
+
+
+def vptree_seeds(base: Vectors, tree: VPTree, queries: Vectors):
+    """(seeds [nq][n_seeds] int32, distance computations [nq] int32)."""
+    dev = tree.node_vp.device
+    seeds = torch.empty((queries.n, tree.n_seeds), dtype=torch.int32, device=dev)
+    dc = torch.empty(queries.n, dtype=torch.int32, device=dev)
+    L.call("onng_vptree_seeds", base.ref, C.byref(tree.t), queries.ref,
+           seeds.data_ptr(), dc.data_ptr(), _stream())
+    return seeds, dc
+
+
 def adjust_path(g: Graph, dtype: int, metric: int) -> Graph:
     dev = g.offsets.device
     off = torch.empty_like(g.offsets)

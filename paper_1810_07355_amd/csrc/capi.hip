@@ -34,6 +34,12 @@ size_t adjust_degree_constrained_ws(int64_t n, int32_t k, int32_t e_o, int32_t e
 onng_status graph_stats_launch(const onng_graph *g, bool int_len, bool sqrt_len, double frac,
                                int keep, double *out, void *ws, hipStream_t st);
 size_t graph_stats_ws(int64_t n, int64_t nnz);
+onng_status vptree_build_launch(const onng_vectors *base, const uint32_t *prio, onng_vptree *t,
+                                void *ws, hipStream_t st);
+onng_status vptree_seeds_launch(const onng_vectors *base, const onng_vptree *t,
+                                const onng_vectors *q, int32_t *seeds, int32_t *dc,
+                                hipStream_t st);
+size_t vptree_ws(int64_t n);
 onng_status adjust_path_launch(const onng_graph *g, bool int_len, int64_t *offsets,
                                int32_t *nbrs, void *lens, int64_t *nnz_out, void *ws,
                                hipStream_t st);
@@ -686,6 +692,54 @@ onng_status onng_graph_stats(const onng_graph *g, int32_t data_dtype, int32_t me
     }
     return graph_stats_launch(g, int_dist(data_dtype, metric), metric == ONNG_L2SQ, frac, keep,
                               out, ws, as_stream(stream));
+}
+
+// ------------------------------------------------------- tree-based seeds --
+
+static onng_status check_vptree_rows(const onng_vectors *v, const char *what) {
+    ONNG_TRY(check_vectors(v, what));
+    ONNG_CHECK_ARG((v->dtype == ONNG_U8 && v->metric == ONNG_L2SQ) || v->dtype == ONNG_F32,
+                   "tree rows must be u8 (squared L2) or f32");
+    return ONNG_OK;
+}
+
+size_t onng_vptree_build_workspace_size(int64_t n) {
+    if (n < 0) return 0;
+    return vptree_ws(n);
+}
+
+onng_status onng_vptree_build(const onng_vectors *base, const uint32_t *priority,
+                              onng_vptree *tree, void *ws, size_t ws_bytes, void *stream) {
+    set_error("");
+    ONNG_TRY(check_vptree_rows(base, "base"));
+    ONNG_CHECK_ARG(base->n >= 1 && base->n <= 0x7fffffffLL, "base must hold 1 .. 2^31-1 rows");
+    ONNG_CHECK_ARG(priority && tree, "null argument");
+    ONNG_CHECK_ARG(tree->node_vp && tree->node_child && tree->node_mu && tree->leaf_seeds,
+                   "tree arrays are null");
+    ONNG_CHECK_ARG(tree->leaf_size >= 4 && tree->leaf_size <= 256, "leaf_size must be in [4, 256]");
+    ONNG_CHECK_ARG(tree->n_seeds >= 1 && tree->n_seeds <= 256, "n_seeds must be in [1, 256]");
+    ONNG_CHECK_ARG(tree->node_capacity >= 1 && tree->leaf_capacity >= 1, "capacities must be >= 1");
+    if (ws_bytes < vptree_ws(base->n) || !ws) {
+        set_error("onng_vptree_build: workspace too small");
+        return ONNG_ERR_WORKSPACE;
+    }
+    return vptree_build_launch(base, priority, tree, ws, as_stream(stream));
+}
+
+onng_status onng_vptree_seeds(const onng_vectors *base, const onng_vptree *tree,
+                              const onng_vectors *queries, int32_t *seeds, int32_t *dc,
+                              void *stream) {
+    set_error("");
+    ONNG_TRY(check_vptree_rows(base, "base"));
+    ONNG_TRY(check_vptree_rows(queries, "queries"));
+    ONNG_CHECK_ARG(queries->dtype == base->dtype && queries->dim == base->dim &&
+                   queries->metric == base->metric, "queries must match the base rows");
+    ONNG_CHECK_ARG(tree && tree->n_nodes >= 1 && tree->n_leaves >= 1 && tree->node_vp &&
+                   tree->node_child && tree->node_mu && tree->leaf_seeds,
+                   "tree is not built");
+    ONNG_CHECK_ARG(tree->n_seeds >= 1 && tree->n_seeds <= 256, "n_seeds must be in [1, 256]");
+    ONNG_CHECK_ARG(queries->n == 0 || (seeds && dc), "outputs are null");
+    return vptree_seeds_launch(base, tree, queries, seeds, dc, as_stream(stream));
 }
 
 size_t onng_adjust_path_workspace_size(int64_t n, int64_t nnz) {

@@ -246,6 +246,55 @@ def test_graph_stats_against_oracle():
     assert A.graph_stats(e, Lb.U8, Lb.L2SQ) == (0.0, 0.0, 0.0)
 
 
+def _vptree_vs_oracle(x, q, metric, leaf_size, n_seeds, seed=0):
+    A = api()
+    n = len(x)
+    prio = dg.vp_priority(n, seed)
+    bv, qv = orc.Vectors.from_array(x, metric), orc.Vectors.from_array(q, metric)
+    ref = orc.vptree_build(bv, prio, leaf_size, n_seeds)
+    B, Q = gpu_vectors(x, metric), gpu_vectors(q, metric)
+    t = A.vptree_build(B, to_dev(prio.view(np.int32)), leaf_size, n_seeds)
+    m, l = t.n_nodes, t.n_leaves
+    assert (m, l) == (len(ref["vp"]), len(ref["seeds"]))
+    assert np.array_equal(host(t.node_vp)[:m], ref["vp"])
+    assert np.array_equal(host(t.node_child)[:m], ref["child"])
+    inner = ref["child"] >= 0
+    mu = host(t.node_mu)[:3 * m].reshape(m, 3).astype(np.float64)
+    assert np.array_equal(mu[inner], ref["mu"][inner])
+    assert np.array_equal(host(t.leaf_seeds)[:l * n_seeds].reshape(l, n_seeds), ref["seeds"])
+    s, dc = A.vptree_seeds(B, t, Q)
+    rs, rdc = orc.vptree_seeds(bv, qv, ref)
+    assert np.array_equal(host(s), rs) and np.array_equal(host(dc), rdc)
+    return rdc
+
+
+def test_vptree_u8_c1_against_oracle():
+    P = c1_problem()
+    say("vptree c1 u8: 100 queries and the base rows as queries")
+    dc = _vptree_vs_oracle(P["x"], np.concatenate([P["q"], P["x"][:2000]]), orc.L2SQ, 100, 10)
+    assert dc.min() >= 4 and dc.max() <= 5
+
+
+@pytest.mark.parametrize("metric", [orc.L2SQ, orc.COS])
+def test_vptree_float_against_oracle(metric):
+    say("vptree f32", metric)
+    g = np.random.default_rng(21 + metric)
+    x = g.standard_normal((20000, 100)).astype(np.float32)
+    q = g.standard_normal((500, 100)).astype(np.float32)
+    if metric == orc.COS:
+        x /= np.linalg.norm(x, axis=1, keepdims=True)
+        q /= np.linalg.norm(q, axis=1, keepdims=True)
+    _vptree_vs_oracle(x, q, metric, 100, 10, seed=3)
+
+
+@pytest.mark.parametrize("n,leaf,ns", [(1, 4, 3), (4, 4, 6), (5, 4, 2), (257, 256, 1),
+                                       (1000, 7, 10), (300, 100, 100)])
+def test_vptree_small_and_padding(n, leaf, ns):
+    say("vptree small", n, leaf, ns)
+    x = dg.random_tie_u8(n, 5, 17, levels=4)
+    _vptree_vs_oracle(x, x[:50], orc.L2SQ, leaf, ns, seed=n)
+
+
 def test_adjust_path_u8_c1():
     P = c1_problem()
     say("adjust_path c1")

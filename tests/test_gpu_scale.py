@@ -151,6 +151,30 @@ def test_c2_constrained_degree_adjustment_sampled():
         assert ln[off[o]:off[o + 1]].tolist() == [l for _, l in want], o
 
 
+def test_c2_vptree_whole_tree_and_sampled_queries():
+    """The 1M-row tree equals the oracle's node for node; a query costs 6-8
+    distance computations, the range Table 5 reports at 1M-10M rows."""
+    P = c2()
+    A = api()
+    n = P["cfg"].n_base
+    prio = dg.vp_priority(n, 0)
+    say("c2: vantage-point tree on the GPU and in the oracle")
+    t = A.vptree_build(P["B"], to_dev(prio.view(np.int32)), 100, 10)
+    bv = orc.Vectors.from_array(P["x"], orc.L2SQ)
+    ref = orc.vptree_build(bv, prio, 100, 10)
+    m, l = t.n_nodes, t.n_leaves
+    assert (m, l) == (len(ref["vp"]), len(ref["seeds"]))
+    assert np.array_equal(host(t.node_vp)[:m], ref["vp"])
+    assert np.array_equal(host(t.node_child)[:m], ref["child"])
+    assert np.array_equal(host(t.leaf_seeds)[:l * 10].reshape(l, 10), ref["seeds"])
+    qs = _sample(P["cfg"].n_query, 2000, 9)
+    qv = orc.Vectors.from_array(P["q"][qs], orc.L2SQ)
+    s, dc = A.vptree_seeds(P["B"], t, gpu_vectors(P["q"][qs], orc.L2SQ))
+    rs, rdc = orc.vptree_seeds(bv, qv, ref)
+    assert np.array_equal(host(s), rs) and np.array_equal(host(dc), rdc)
+    assert 6 <= rdc.min() and rdc.max() <= 8
+
+
 def test_c2_path_adjustment_decisions():
     """Algorithm 4 visits, in round j, every node n (ascending id) with more
     than j edges in the degree-adjusted graph G_e and keeps its j-th edge
