@@ -103,6 +103,9 @@ def parse():
     ap.add_argument("--degree-adjust", default="sa", choices=["sa", "sac"],
                     help="static degree adjustment before path adjustment: Algorithm 2 (sa) "
                          "or Algorithm 3, with constraints (sac)")
+    ap.add_argument("--seeds", default="pivots", choices=["pivots", "vptree", "random"],
+                    help="entry seeds of the test queries in --da-sweep: the nearest pivots "
+                         "(default), the vantage-point tree, or uniformly random rows")
     ap.add_argument("--e-o", type=int, default=None, help="override the workload's e_o")
     ap.add_argument("--e-i", type=int, default=None, help="override the workload's e_i")
     ap.add_argument("--da-grid", default="inf,10:20,20:20,30:20,50:20,30:10,30:30,30:40",
@@ -240,6 +243,27 @@ def main():
             f"mean indegree distance {st[2]:.4f}")
     del sa
     seeds, _ = A.topk(queries, base, NS, cand=piv)
+    seed_info = {"kind": "pivots", "n_seeds": NS, "pivots": int(piv.numel())}
+    if args.seeds != "pivots":
+        if not args.da_sweep:
+            raise SystemExit("--seeds other than pivots applies to --da-sweep only")
+        if args.seeds == "vptree":
+            # the paper's tree-based seeds: 10 rows nearest the vantage point
+            # of the query's leaf, leaves of at most 100 rows
+            prio = torch.from_numpy(dg.vp_priority(cfg.n_base, 0).view(np.int32)).to(dev)
+            tree = timed("vptree_s", lambda: A.vptree_build(base, prio, 100, 10))
+            A.vptree_seeds(base, tree, queries)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            seeds, sdc = A.vptree_seeds(base, tree, queries)
+            torch.cuda.synchronize()
+            seed_info = {"kind": "vptree", "n_seeds": 10, "nodes": tree.n_nodes,
+                         "leaves": tree.n_leaves, "descent_ms": round((time.time() - t0) * 1e3, 3),
+                         "mean_dc": float(sdc.float().mean())}
+        else:
+            seeds = torch.from_numpy(dg.random_seeds(cfg, cfg.n_query, 10)).to(dev)
+            seed_info = {"kind": "random", "n_seeds": 10}
+        log(f"seeds: {seed_info}")
     gt_ids, _ = timed("ground_truth_s", lambda: A.ground_truth(queries, base, K))
     gt = to_orig(gt_ids).cpu().numpy()
 
@@ -352,6 +376,7 @@ def main():
         print(json.dumps({"da_sweep": da, "workload": cfg.name, "degree_adjust":
                           args.degree_adjust, "e_o": cfg.e_o, "e_i": cfg.e_i,
                           "edges": {"adjusted": n_adj_edges, "pa": graph.nnz},
+                          "seeds": seed_info,
                           "graph_stats": gstats, "build_s": build}),
               flush=True)
         return
