@@ -11,6 +11,7 @@ same code serves exact integer and fp64 data.  Ties are broken by node id
                          over (|N(G_t, x)|, x) taken afresh every step (R10).
 * adjust_path/has_path:  Algorithms 4 and 5 (AdjustPath, HasPath).
 * paper_visited:         Algorithms 6 and 7 (Set, IsSet) as a class.
+* construct_anng:        Algorithm 9, one object at a time.
 * vptree:                the 4-way vantage-point tree of the seeds (Section
                          3.2, Table 5), built depth first and renumbered
                          breadth first afterwards.
@@ -132,6 +133,26 @@ def adjusted_graph_with_constraint(knn, knn_d, e_o, e_i):
             if nn not in Ge[o]:
                 Ge[o][nn] = d
     return [sorted((l, i) for i, l in Ge[o].items()) for o in range(n)]
+
+
+def construct_anng(order, dist, k_c, thr_fn, n_seeds, n_pivots):
+    """Algorithm 9 as printed: objects in `order` one by one; each gets the
+    KnnSearch results on the graph so far as edges, and each result gets the
+    reverse edge.  Seeds: the n_seeds objects nearest the new one among the
+    first n_pivots inserted, by (d, id).  Returns per-node lists of (len, id)
+    sorted ascending."""
+    adj = {o: [] for o in order}
+    inserted = []
+    for o in order:
+        if inserted:
+            neigh = {v: [i for _, i in sorted(adj[v])] for v in inserted}
+            piv = sorted(inserted[:n_pivots], key=lambda m: (dist(o, m), m))[:n_seeds]
+            R, _, _ = knn_search(neigh, lambda m: dist(o, m), piv, k_c, thr_fn)
+            for d, m in R:
+                adj[o].append((d, m))
+                adj[m].append((d, o))
+        inserted.append(o)
+    return {o: sorted(adj[o]) for o in order}
 
 
 def vptree(ids, dist, prio, leaf_size, n_seeds):

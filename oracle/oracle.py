@@ -290,6 +290,47 @@ def degree_loss(search, p_l=0.90, p_u=0.98, eps_max=1.0, iters=30, samples=10):
     return area / float(p[-1] - p[0]), pts
 
 
+# ------------------------------------------- ANNG construction (Alg 9) --
+
+def anng(x: np.ndarray, metric: int, order, k_c: int, eps_c: float, n_seeds: int = 8,
+         n_pivots: int = 1024, max_batch: int = 65536):
+    """Algorithm 9 with batched insertion: the first object of `order` starts
+    alone; each later batch (as large as everything inserted so far, at most
+    max_batch) runs KnnSearch(G_a, o, k_c, eps_c, inf) on the graph of the
+    earlier batches, seeded by each object's n_seeds nearest among the first
+    n_pivots inserted objects, and adds o -> n and n -> o for every result n.
+    Returns CSR lists sorted by (length, id)."""
+    n = len(x)
+    order = np.asarray(order, dtype=np.int64)
+    B = Vectors.from_array(x, metric)
+    adj = [[] for _ in range(n)]
+
+    def csr():
+        lists = [sorted(a) for a in adj]
+        off = np.zeros(n + 1, np.int64)
+        off[1:] = np.cumsum([len(a) for a in lists])
+        nb = np.array([i for a in lists for _, i in a], dtype=np.int32)
+        ln = np.array([l for a in lists for l, _ in a], dtype=np.float64)
+        return off, nb, ln
+
+    done = min(1, n)
+    while done < n:
+        b = min(done, max_batch, n - done)
+        ids = order[done:done + b]
+        off, nb, _ = csr()
+        Q = Vectors.from_array(x[ids], metric)
+        piv = order[:min(done, n_pivots)].astype(np.int32)
+        seeds, _ = topk(Q, B, n_seeds, cand=piv)
+        r = search(B, off, nb, Q, seeds, k_c, eps_c)
+        for t, o in enumerate(ids):
+            for nn, d in zip(r["ids"][t, :k_c], r["dists"][t, :k_c]):
+                if nn >= 0:
+                    adj[int(o)].append((float(d), int(nn)))
+                    adj[int(nn)].append((float(d), int(o)))
+        done += b
+    return csr()
+
+
 # ------------------------------------------------- tree-based seeds ------
 
 def vptree_build(B: Vectors, prio, leaf_size: int = 100, n_seeds: int = 10):

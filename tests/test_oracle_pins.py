@@ -456,6 +456,43 @@ def test_vptree_partition_and_self_descent(metric):
     assert dc.min() == 5 and dc.max() == 5
 
 
+# ------------------------------------------- Algorithm 9 (ANNG)
+
+@pytest.mark.parametrize("n_pivots,n_seeds", [(1, 1), (5, 2), (1000, 3)])
+def test_anng_batches_of_one_are_the_sequential_algorithm(n_pivots, n_seeds):
+    """With batches of one object the batched construction is Algorithm 9 as
+    printed."""
+    x = dg.random_tie_u8(60, 4, 23, levels=5)
+    order = dg.vp_priority(60, 7).astype(np.int64)
+    eps = 0.1
+    f = orc.range_factor(eps, orc.L2SQ)
+    D = ((x[:, None, :].astype(np.int64) - x[None, :, :].astype(np.int64)) ** 2).sum(-1)
+    thr = lambda rr: math.inf if math.isinf(rr) else float(np.float32(rr) * f)
+    for k_c in (1, 3, 6):
+        off, nb, ln = orc.anng(x, orc.L2SQ, order, k_c, eps, n_seeds=n_seeds,
+                               n_pivots=n_pivots, max_batch=1)
+        lit = literal.construct_anng(order.tolist(), lambda a, b: float(D[a, b]), k_c, thr,
+                                     n_seeds, n_pivots)
+        for o in range(60):
+            got = list(zip(ln[off[o]:off[o + 1]].tolist(), nb[off[o]:off[o + 1]].tolist()))
+            assert got == [(float(l), i) for l, i in lit[o]], (k_c, o)
+
+
+def test_anng_batched_edges_pair_up_without_repeats():
+    x = dg.random_tie_u8(300, 5, 29, levels=6)
+    order = dg.vp_priority(300, 8)
+    for mb in (1, 7, 64, 300):
+        off, nb, ln = orc.anng(x, orc.L2SQ, order, 4, 0.1, n_pivots=16, max_batch=mb)
+        pairs = {}
+        for o in range(300):
+            lst = nb[off[o]:off[o + 1]].tolist()
+            assert o not in lst and len(set(lst)) == len(lst)      # no self loop, no repeat
+            for i, l in zip(lst, ln[off[o]:off[o + 1]].tolist()):
+                pairs[(o, i)] = l
+        assert all(pairs.get((i, o)) == l for (o, i), l in pairs.items())
+        assert np.bincount(nb, minlength=300).min() >= 1           # everything linked
+
+
 # ---------------------------------------------------- Algorithms 4/5 (PA)
 
 def _csr_from_adj(adj, n):
