@@ -198,6 +198,23 @@ onng_status onng_graph_stats(const onng_graph *g, int32_t data_dtype, int32_t me
 size_t onng_graph_stats_workspace_size(int64_t n, int64_t nnz);
 
 /* ------------------------------------------------------------------------ */
+/* Edge insertion — the graph updates of ConstructANNG (Appendix, Alg 9)    */
+/* ------------------------------------------------------------------------ */
+
+/* out = in plus the edges src[e] -> dst[e] of length lens[e], e < n_edges
+ * (device arrays; an edge with an id outside [0, n) is skipped).  Each output
+ * list holds the node's old and new edges sorted by (length, id); duplicates
+ * are kept (ConstructANNG never produces one).  Same capacity rule and
+ * errors as onng_adjust_degree; in->nnz + n_edges always suffices.
+ * Synchronises the stream. */
+onng_status onng_graph_add_edges(const onng_graph *in, const int32_t *src, const int32_t *dst,
+                                 const void *lens, int64_t n_edges, int32_t data_dtype,
+                                 int32_t metric, int64_t *offsets, int32_t *nbrs, void *out_lens,
+                                 int64_t nnz_capacity, int64_t *nnz_out, void *ws,
+                                 size_t ws_bytes, void *stream);
+size_t onng_graph_add_edges_workspace_size(int64_t n, int64_t nnz, int64_t n_edges);
+
+/* ------------------------------------------------------------------------ */
 /* Entry seeds from a tree — Section 3.2 (tree-based index), Table 5        */
 /* ------------------------------------------------------------------------ */
 

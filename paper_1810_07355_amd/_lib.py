@@ -81,6 +81,9 @@ PROTOS = {
     "onng_graph_stats": (C.c_int, [P, C.c_int32, C.c_int32, C.c_double, C.c_int32, P, P,
                                    C.c_size_t, P]),
     "onng_graph_stats_workspace_size": (C.c_size_t, [C.c_int64, C.c_int64]),
+    "onng_graph_add_edges": (C.c_int, [P, P, P, P, C.c_int64, C.c_int32, C.c_int32, P, P, P,
+                                       C.c_int64, P, P, C.c_size_t, P]),
+    "onng_graph_add_edges_workspace_size": (C.c_size_t, [C.c_int64, C.c_int64, C.c_int64]),
     "onng_vptree_build": (C.c_int, [P, P, P, P, C.c_size_t, P]),
     "onng_vptree_build_workspace_size": (C.c_size_t, [C.c_int64]),
     "onng_vptree_seeds": (C.c_int, [P, P, P, P, P, P]),

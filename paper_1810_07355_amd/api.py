@@ -162,6 +162,24 @@ def graph_stats(g: Graph, dtype: int, metric: int, frac: float = 0.05, keep: int
     return tuple(out)
 
 
+def graph_add_edges(g: Graph, src: torch.Tensor, dst: torch.Tensor, lens: torch.Tensor,
+                    dtype: int, metric: int) -> Graph:
+    """g plus the edges src -> dst (ids outside [0, n) skipped), lists sorted
+    by (length, id)."""
+    dev = g.offsets.device
+    m = src.numel()
+    cap = g.nnz + m
+    off = torch.empty_like(g.offsets)
+    nb = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    ln = torch.empty(max(cap, 1), dtype=lens.dtype, device=dev)
+    ws = _workspace(L.load().onng_graph_add_edges_workspace_size(g.n, g.nnz, m), dev)
+    nnz = C.c_int64(0)
+    L.call("onng_graph_add_edges", C.byref(g.struct()), _ptr(src), _ptr(dst), _ptr(lens), m,
+           dtype, metric, off.data_ptr(), nb.data_ptr(), ln.data_ptr(), cap, C.byref(nnz),
+           ws.data_ptr(), ws.numel(), _stream())
+    return Graph(off, nb[:nnz.value].clone(), ln[:nnz.value].clone())
+
+
 class VPTree:
     """A 4-way vantage-point tree for entry seeds (Section 3.2, Table 5);
     built by vptree_build, its arrays live on the device."""

@@ -452,6 +452,43 @@ __global__ void gs_final_kernel(const double *sums, double t, double *res) {
     res[2] = sums[3] > 0 ? sums[2] / sums[3] : 0.0;
 }
 
+// ------------------------------------------------------- edge insertion --
+// Graph plus new edges (src, dst, length): per-node counts, offsets, keys of
+// the old and new edges in each node's segment, then the (length, id) sort.
+
+__global__ void ae_count_kernel(const int64_t *off, int64_t n, const int32_t *src,
+                                const int32_t *dst, int64_t m, int64_t *cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd((unsigned long long *)&cnt[i], (unsigned long long)(off[i + 1] - off[i]));
+    if (i < m && src[i] >= 0 && src[i] < n && dst[i] >= 0 && dst[i] < n)
+        atomicAdd((unsigned long long *)&cnt[src[i]], 1ull);
+}
+
+template <typename LenT>
+__global__ void ae_scatter_kernel(const int64_t *off, const int32_t *nbrs, const LenT *lens,
+                                  int64_t n, const int32_t *src, const int32_t *dst,
+                                  const LenT *len, int64_t m, const int64_t *out_off,
+                                  int32_t *cursor, uint64_t *keys) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int64_t b = off[i], e = off[i + 1];
+        const int64_t w = out_off[i];
+        for (int64_t t = b; t < e; t++) keys[w + (t - b)] = make_key(len_ord(lens[t]), (uint32_t)nbrs[t]);
+        cursor[i] = (int32_t)(e - b);
+    }
+}
+
+template <typename LenT>
+__global__ void ae_new_kernel(int64_t n, const int32_t *src, const int32_t *dst, const LenT *len,
+                              int64_t m, const int64_t *out_off, int32_t *cursor, uint64_t *keys) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int32_t s = src[i], d = dst[i];
+    if (s < 0 || s >= n || d < 0 || d >= n) return;
+    const int slot = atomicAdd(&cursor[s], 1);
+    keys[out_off[s] + slot] = make_key(len_ord(len[i]), (uint32_t)d);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- host side --
@@ -698,6 +735,67 @@ onng_status graph_stats_launch(const onng_graph *g, bool int_len, bool sqrt_len,
                                int keep, double *out, void *ws, hipStream_t st) {
     if (int_len) return graph_stats_impl<int32_t>(g, sqrt_len, frac, keep, out, ws, st);
     return graph_stats_impl<float>(g, sqrt_len, frac, keep, out, ws, st);
+}
+
+size_t add_edges_ws(int64_t n, int64_t nnz, int64_t m) {
+    Carver c(nullptr);
+    c.take<int64_t>(n + 1);
+    c.take<int32_t>(n);
+    c.take<uint64_t>(nnz + m);
+    c.take<char>(scan_temp_bytes(n + 1));
+    return c.size() + 256;
+}
+
+template <typename LenT>
+static onng_status add_edges_impl(const onng_graph *g, const int32_t *src, const int32_t *dst,
+                                  const LenT *len, int64_t m, int64_t *out_off, int32_t *out_nb,
+                                  LenT *out_len, int64_t nnz_cap, int64_t *nnz_out, void *ws,
+                                  hipStream_t st) {
+    const int64_t n = g->n, nnz = g->nnz;
+    Carver c(ws);
+    int64_t *cnt = c.take<int64_t>(n + 1);
+    int32_t *cursor = c.take<int32_t>(n);
+    uint64_t *keys = c.take<uint64_t>(nnz + m);
+    size_t tb = scan_temp_bytes(n + 1);
+    void *tmp = c.take<char>(tb);
+    ONNG_HIP(hipMemsetAsync(cnt, 0, sizeof(int64_t) * (n + 1), st));
+    ONNG_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * n, st));
+    const int64_t big = std::max(n, m);
+    if (big > 0)
+        hipLaunchKernelGGL(ae_count_kernel, dim3(blocks_for(big, 256)), dim3(256), 0, st,
+                           g->offsets, n, src, dst, m, cnt);
+    ONNG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt, out_off, (int)(n + 1), st));
+    ONNG_HIP(hipMemcpyAsync(nnz_out, out_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    ONNG_HIP(hipStreamSynchronize(st));
+    if (*nnz_out > nnz_cap) {
+        set_error("onng_graph_add_edges: nnz_capacity too small");
+        return ONNG_ERR_CAPACITY;
+    }
+    if (n > 0) {
+        hipLaunchKernelGGL((ae_scatter_kernel<LenT>), dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                           g->offsets, g->nbrs, static_cast<const LenT *>(g->lens), n, src, dst,
+                           len, m, out_off, cursor, keys);
+        if (m > 0)
+            hipLaunchKernelGGL((ae_new_kernel<LenT>), dim3(blocks_for(m, 256)), dim3(256), 0, st,
+                               n, src, dst, len, m, out_off, cursor, keys);
+        hipLaunchKernelGGL((segment_rank_sort_kernel<LenT>), dim3((unsigned)n), dim3(256),
+                           4096 * sizeof(uint64_t), st, out_off, n, keys, out_nb, out_len);
+    }
+    ONNG_HIP(hipGetLastError());
+    ONNG_HIP(hipStreamSynchronize(st));
+    return ONNG_OK;
+}
+
+onng_status add_edges_launch(const onng_graph *g, const int32_t *src, const int32_t *dst,
+                             const void *len, int64_t m, bool int_len, int64_t *out_off,
+                             int32_t *out_nb, void *out_len, int64_t nnz_cap, int64_t *nnz_out,
+                             void *ws, hipStream_t st) {
+    if (int_len)
+        return add_edges_impl<int32_t>(g, src, dst, static_cast<const int32_t *>(len), m, out_off,
+                                       out_nb, static_cast<int32_t *>(out_len), nnz_cap, nnz_out,
+                                       ws, st);
+    return add_edges_impl<float>(g, src, dst, static_cast<const float *>(len), m, out_off, out_nb,
+                                 static_cast<float *>(out_len), nnz_cap, nnz_out, ws, st);
 }
 
 size_t adjust_path_ws(int64_t n, int64_t nnz) {

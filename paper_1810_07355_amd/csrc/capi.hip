@@ -40,6 +40,11 @@ onng_status vptree_seeds_launch(const onng_vectors *base, const onng_vptree *t,
                                 const onng_vectors *q, int32_t *seeds, int32_t *dc,
                                 hipStream_t st);
 size_t vptree_ws(int64_t n);
+onng_status add_edges_launch(const onng_graph *g, const int32_t *src, const int32_t *dst,
+                             const void *len, int64_t m, bool int_len, int64_t *out_off,
+                             int32_t *out_nb, void *out_len, int64_t nnz_cap, int64_t *nnz_out,
+                             void *ws, hipStream_t st);
+size_t add_edges_ws(int64_t n, int64_t nnz, int64_t m);
 onng_status adjust_path_launch(const onng_graph *g, bool int_len, int64_t *offsets,
                                int32_t *nbrs, void *lens, int64_t *nnz_out, void *ws,
                                hipStream_t st);
@@ -692,6 +697,34 @@ onng_status onng_graph_stats(const onng_graph *g, int32_t data_dtype, int32_t me
     }
     return graph_stats_launch(g, int_dist(data_dtype, metric), metric == ONNG_L2SQ, frac, keep,
                               out, ws, as_stream(stream));
+}
+
+// ---------------------------------------------------------- edge insertion --
+
+size_t onng_graph_add_edges_workspace_size(int64_t n, int64_t nnz, int64_t n_edges) {
+    if (n < 0 || nnz < 0 || n_edges < 0) return 0;
+    return add_edges_ws(n, nnz, n_edges);
+}
+
+onng_status onng_graph_add_edges(const onng_graph *in, const int32_t *src, const int32_t *dst,
+                                 const void *lens, int64_t n_edges, int32_t data_dtype,
+                                 int32_t metric, int64_t *offsets, int32_t *nbrs, void *out_lens,
+                                 int64_t nnz_capacity, int64_t *nnz_out, void *ws,
+                                 size_t ws_bytes, void *stream) {
+    set_error("");
+    ONNG_CHECK_ARG(in && offsets && nnz_out, "null argument");
+    ONNG_CHECK_ARG(in->n >= 0 && in->nnz >= 0 && in->n <= 0x7fffffffLL && n_edges >= 0 &&
+                   in->nnz + n_edges <= 0x7fffffffLL, "bad sizes");
+    ONNG_CHECK_ARG(in->offsets && (in->nnz == 0 || (in->nbrs && in->lens)), "graph arrays are null");
+    ONNG_CHECK_ARG(n_edges == 0 || (src && dst && lens), "edge arrays are null");
+    ONNG_CHECK_ARG(nnz_capacity == 0 || (nbrs && out_lens), "outputs are null");
+    ONNG_CHECK_ARG(data_dtype >= ONNG_U8 && data_dtype <= ONNG_FP8_E4M3, "unknown dtype");
+    if (ws_bytes < add_edges_ws(in->n, in->nnz, n_edges) || !ws) {
+        set_error("onng_graph_add_edges: workspace too small");
+        return ONNG_ERR_WORKSPACE;
+    }
+    return add_edges_launch(in, src, dst, lens, n_edges, int_dist(data_dtype, metric), offsets,
+                            nbrs, out_lens, nnz_capacity, nnz_out, ws, as_stream(stream));
 }
 
 // ------------------------------------------------------- tree-based seeds --

@@ -295,6 +295,56 @@ def test_vptree_small_and_padding(n, leaf, ns):
     _vptree_vs_oracle(x, x[:50], orc.L2SQ, leaf, ns, seed=n)
 
 
+@pytest.mark.parametrize("max_batch,n_pivots", [(2048, 1024), (1, 4), (64, 1)])
+def test_anng_u8_against_oracle(max_batch, n_pivots):
+    """Algorithm 9 in batches on c1's rows (the first 300 for the
+    one-at-a-time case): the whole graph bit for bit."""
+    from paper_1810_07355_amd import anng
+    P = c1_problem()
+    A, Lb = api(), L()
+    n = 10000 if max_batch > 1 else 300
+    x = P["x"][:n]
+    order = dg.vp_priority(n, 11).astype(np.int64)
+    say("anng u8", n, max_batch, n_pivots)
+    g = anng.build_anng(to_dev(x), Lb.L2SQ, to_dev(order.astype(np.int32)), 10, 0.1,
+                        n_seeds=8, n_pivots=n_pivots, max_batch=max_batch)
+    off, nb, ln = orc.anng(x, orc.L2SQ, order, 10, 0.1, n_seeds=8, n_pivots=n_pivots,
+                           max_batch=max_batch)
+    assert np.array_equal(host(g.offsets), off)
+    assert np.array_equal(host(g.nbrs), nb)
+    assert np.array_equal(host(g.lens), ln.astype(np.int32))
+
+
+def test_graph_add_edges_against_numpy():
+    say("graph_add_edges")
+    A, Lb = api(), L()
+    g = np.random.default_rng(31)
+    n = 500
+    deg = g.integers(0, 12, size=n)
+    off = np.concatenate([[0], np.cumsum(deg)]).astype(np.int64)
+    nb = g.integers(0, n, size=off[-1]).astype(np.int32)
+    ln = g.integers(0, 50, size=off[-1]).astype(np.int32)
+    for v in range(n):                         # lists sorted by (len, id)
+        o = np.lexsort((nb[off[v]:off[v + 1]], ln[off[v]:off[v + 1]]))
+        nb[off[v]:off[v + 1]] = nb[off[v]:off[v + 1]][o]
+        ln[off[v]:off[v + 1]] = ln[off[v]:off[v + 1]][o]
+    m = 3000
+    src = g.integers(-2, n + 2, size=m).astype(np.int32)      # a few ids outside [0, n)
+    dst = g.integers(-2, n + 2, size=m).astype(np.int32)
+    el = g.integers(0, 50, size=m).astype(np.int32)
+    out = A.graph_add_edges(gpu_graph(off, nb, ln), to_dev(src), to_dev(dst), to_dev(el),
+                            Lb.U8, Lb.L2SQ)
+    lists = [list(zip(ln[off[v]:off[v + 1]].tolist(), nb[off[v]:off[v + 1]].tolist()))
+             for v in range(n)]
+    for s_, d_, l_ in zip(src.tolist(), dst.tolist(), el.tolist()):
+        if 0 <= s_ < n and 0 <= d_ < n:
+            lists[s_].append((l_, d_))
+    lists = [sorted(a) for a in lists]
+    assert host(out.offsets).tolist() == [0] + np.cumsum([len(a) for a in lists]).tolist()
+    assert host(out.nbrs).tolist() == [i for a in lists for _, i in a]
+    assert host(out.lens).tolist() == [l for a in lists for l, _ in a]
+
+
 def test_adjust_path_u8_c1():
     P = c1_problem()
     say("adjust_path c1")
