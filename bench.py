@@ -103,6 +103,10 @@ def parse():
     ap.add_argument("--degree-adjust", default="sa", choices=["sa", "sac"],
                     help="static degree adjustment before path adjustment: Algorithm 2 (sa) "
                          "or Algorithm 3, with constraints (sac)")
+    ap.add_argument("--graph", default="knn", choices=["knn", "anng"],
+                    help="--da-sweep only: the adjusted exact kNN graph (default) or the ANNG "
+                         "of Algorithm 9 searched as it is")
+    ap.add_argument("--anng-kc", type=int, default=10, help="k_c of the ANNG")
     ap.add_argument("--seeds", default="pivots", choices=["pivots", "vptree", "random"],
                     help="entry seeds of the test queries in --da-sweep: the nearest pivots "
                          "(default), the vantage-point tree, or uniformly random rows")
@@ -215,14 +219,28 @@ def main():
     def to_orig(ids_t):
         return perm[ids_t.long()] if perm is not None else ids_t
 
-    ids, d = timed("knn_s", lambda: A.build_knn(base, cfg.knn_k))
-    if args.degree_adjust == "sac":
+    if args.graph == "anng":
+        # Algorithm 9 searched directly (the paper's ANNG baseline), no kNN table
+        if not args.da_sweep:
+            raise SystemExit("--graph anng applies to --da-sweep only")
+        from paper_1810_07355_amd import anng
+        order = torch.from_numpy(dg.vp_priority(cfg.n_base, 3).view(np.int32)).to(dev)
+        graph = timed("anng_s", lambda: anng.build_anng(xt, metric, order, args.anng_kc, 0.1,
+                                                          base=base))
+        ids = d = None
+        sa = graph
+    else:
+        ids, d = timed("knn_s", lambda: A.build_knn(base, cfg.knn_k))
+    if args.graph == "anng":
+        pass
+    elif args.degree_adjust == "sac":
         sa = timed("adjust_degree_constrained_s", lambda: A.adjust_degree_constrained(
             ids, d, base.dtype, metric, cfg.e_o, cfg.e_i))
     else:
         sa = timed("adjust_degree_s", lambda: A.adjust_degree(ids, d, base.dtype, metric,
                                                               cfg.e_o, cfg.e_i))
-    graph = timed("adjust_path_s", lambda: A.adjust_path(sa, base.dtype, metric))
+    if args.graph != "anng":
+        graph = timed("adjust_path_s", lambda: A.adjust_path(sa, base.dtype, metric))
     if not args.tune_degrees:
         del ids, d
     if args.row_align > 16:
@@ -235,7 +253,8 @@ def main():
     n_adj_edges = sa.nnz
     # Table 4's statistics of the degree-adjusted and the path-adjusted graph
     gstats = {}
-    for gname, gg in ((args.degree_adjust, sa), ("pa", graph)):
+    for gname, gg in (((args.degree_adjust, sa), ("pa", graph)) if args.graph != "anng"
+                      else (("anng", graph),)):
         st = A.graph_stats(gg, base.dtype, metric, 0.05, 10)
         gstats[gname] = dict(top5_outdegree=round(st[0], 2), bottom5_indegree=round(st[1], 2),
                              indegree_distance=round(st[2], 5))
