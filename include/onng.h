@@ -190,7 +190,8 @@ size_t onng_adjust_path_workspace_size(int64_t n, int64_t nnz);
  *           fewer), over all kept edges; a squared-L2 length enters as its
  *           square root (the Euclidean distance), a cosine length as is.
  *           0 when no edge is kept.
- * Table 4 uses frac = 0.05 and keep = 10.  lens must be present, in the
+ * Table 4 uses frac = 0.05 and keep = 10.  Edges to ids outside [0, n) are
+ * left out of the in-degrees and the transposed graph.  lens must be present, in the
  * distance type of data_dtype/metric.  Sums are in double in a fixed order.
  * Synchronises the stream. */
 onng_status onng_graph_stats(const onng_graph *g, int32_t data_dtype, int32_t metric, double frac,
@@ -257,7 +258,9 @@ size_t onng_vptree_build_workspace_size(int64_t n);
 
 /* Descends the tree for every query (same dtype, dim and metric as the
  * base): seeds [nq][n_seeds] (device) get the leaf's seeds, dc [nq] (device)
- * the distance computations spent (one per inner node). */
+ * the distance computations spent (one per inner node).  A query whose
+ * descent leaves the tree's counts (a tree not made by onng_vptree_build)
+ * gets seeds -1 and dc -1. */
 onng_status onng_vptree_seeds(const onng_vectors *base, const onng_vptree *tree,
                               const onng_vectors *queries, int32_t *seeds, int32_t *dc,
                               void *stream);

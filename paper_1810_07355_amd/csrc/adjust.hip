@@ -393,7 +393,10 @@ __global__ void gs_degree_kernel(const int64_t *off, const int32_t *nbrs, int64_
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     outdeg[v] = (int32_t)(off[v + 1] - off[v]);
-    for (int64_t e = off[v]; e < off[v + 1]; e++) atomicAdd(&indeg[nbrs[e]], 1);
+    for (int64_t e = off[v]; e < off[v + 1]; e++) {
+        const int32_t t = nbrs[e];
+        if (t >= 0 && t < n) atomicAdd(&indeg[t], 1);   // ids outside the graph count nowhere
+    }
 }
 
 // every edge's length key into its target's segment of the transposed graph
@@ -404,8 +407,9 @@ __global__ void gs_transpose_kernel(const int64_t *off, const int32_t *nbrs, con
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     for (int64_t e = off[v]; e < off[v + 1]; e++) {
-        int32_t t = nbrs[e];
-        int slot = atomicAdd(&cursor[t], 1);
+        const int32_t t = nbrs[e];
+        if (t < 0 || t >= n) continue;
+        const int slot = atomicAdd(&cursor[t], 1);
         tkeys[toff[t] + slot] = len_ord(lens[e]);
     }
 }

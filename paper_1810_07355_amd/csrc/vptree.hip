@@ -192,32 +192,40 @@ __global__ void __launch_bounds__(64) vp_leaf_kernel(const int32_t *perm, const 
     }
 }
 
-// one thread per query; the depth bound keeps a malformed tree from looping
+// one thread per query
 template <bool U8, bool COS>
 __global__ void vp_descend_kernel(const uint8_t *base, int64_t bpitch, const uint8_t *qs,
                                   int64_t qpitch, int64_t nq, int dim, const int32_t *node_vp,
                                   const int32_t *node_child, const void *node_mu,
-                                  const int32_t *leaf_seeds, int n_seeds, int32_t *seeds,
-                                  int32_t *dc) {
+                                  const int32_t *leaf_seeds, int n_seeds, int64_t n_nodes,
+                                  int64_t n_leaves, int64_t n_base, int32_t *seeds, int32_t *dc) {
     using T = typename VDist<U8, COS>::T;
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nq) return;
     const T *mu = static_cast<const T *>(node_mu);
     int64_t node = 0;
     int cnt = 0;
-    while (node_child[node] >= 0 && cnt < 64) {
-        const T d = VDist<U8, COS>::d(qs + q * qpitch, base + (int64_t)node_vp[node] * bpitch, dim);
+    bool bad = false;
+    // every index is checked against the tree's counts, and the depth is
+    // bounded, so a tree not made by the build cannot fault or loop
+    while (!bad && node_child[node] >= 0 && cnt < 64) {
+        const int32_t v = node_vp[node];
+        bad = v < 0 || v >= n_base;
+        if (bad) break;
+        const T d = VDist<U8, COS>::d(qs + q * qpitch, base + (int64_t)v * bpitch, dim);
         const int c = (d >= mu[3 * node]) + (d >= mu[3 * node + 1]) + (d >= mu[3 * node + 2]);
-        node = node_child[node] + c;
+        node = (int64_t)node_child[node] + c;
+        bad = node >= n_nodes;
         cnt++;
     }
     int32_t *out = seeds + q * n_seeds;
-    if (node_child[node] >= 0) {       // deeper than any tree of 2^31 rows: not a built tree
+    const int64_t leaf = bad ? -1 : -1 - (int64_t)node_child[node];
+    if (bad || leaf < 0 || leaf >= n_leaves) {
         for (int r = 0; r < n_seeds; r++) out[r] = -1;
         dc[q] = -1;
         return;
     }
-    const int32_t *src = leaf_seeds + (int64_t)(-1 - node_child[node]) * n_seeds;
+    const int32_t *src = leaf_seeds + leaf * n_seeds;
     for (int r = 0; r < n_seeds; r++) out[r] = src[r];
     dc[q] = cnt;
 }
@@ -324,7 +332,8 @@ void vptree_seeds_impl(const onng_vectors *base, const onng_vptree *t, const onn
     hipLaunchKernelGGL((vp_descend_kernel<U8, COS>), dim3(blocks_of(q->n, 256)), dim3(256), 0, st,
                        static_cast<const uint8_t *>(base->data), base->pitch_bytes,
                        static_cast<const uint8_t *>(q->data), q->pitch_bytes, q->n, base->dim,
-                       t->node_vp, t->node_child, t->node_mu, t->leaf_seeds, t->n_seeds, seeds, dc);
+                       t->node_vp, t->node_child, t->node_mu, t->leaf_seeds, t->n_seeds,
+                       t->n_nodes, t->n_leaves, base->n, seeds, dc);
 }
 
 }  // namespace
