@@ -420,6 +420,25 @@ onng_status onng_search(const onng_vectors *base, const onng_graph *graph,
 size_t onng_search_workspace_size(const onng_vectors *base, int64_t n_queries,
                                   const onng_search_params *params);
 
+/* onng_search for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and errors as onng_search, without the workspace; it
+ * calls no hipMalloc, hipFree or allocating library routine.  Its scratch
+ * (work counter, visited bitsets, visit logs, spill buffers) is one static
+ * device array of ONNG_SEARCH_STATIC_SCRATCH_BYTES, a copy of which each
+ * device the library runs on holds until the process ends.  The persistent
+ * grid is cut to the wave slots that fit in it (results do not depend on
+ * the slot count, throughput may drop); a base so large that one block of
+ * slots does not fit returns ONNG_ERR_CAPACITY with nothing enqueued.  Every
+ * call on a device shares that device's array and leaves its contents for
+ * the next call: calls that overlap in time on one device (other streams or
+ * threads) race on it and must not be issued. */
+#define ONNG_SEARCH_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+onng_status onng_search_static(const onng_vectors *base, const onng_graph *graph,
+                               const onng_vectors *queries, const int32_t *seeds, int32_t n_seeds,
+                               const onng_search_params *params, int32_t *ids, void *dists,
+                               onng_query_stats *stats, void *stream);
+
 /* order[0..n) = query indices by descending stats[q].cost (ties: ascending
  * index), so that a persistent search starts the most expensive queries
  * first and the batch ends when the cheap ones do (longest first).

@@ -91,6 +91,7 @@ PROTOS = {
     "onng_adjust_path_workspace_size": (C.c_size_t, [C.c_int64, C.c_int64]),
     "onng_search": (C.c_int, [P, P, P, P, C.c_int32, P, P, P, P, P, C.c_size_t, P]),
     "onng_search_workspace_size": (C.c_size_t, [P, C.c_int64, P]),
+    "onng_search_static": (C.c_int, [P, P, P, P, C.c_int32, P, P, P, P, P]),
     "onng_order_by_cost": (C.c_int, [P, C.c_int64, P, P, C.c_size_t, P]),
     "onng_order_by_cost_workspace_size": (C.c_size_t, [C.c_int64]),
     "onng_locality_order": (C.c_int, [P, P, C.c_int64, P, P, C.c_size_t, P]),

@@ -291,7 +291,9 @@ class SearchRequest:
                  rerank_base: Vectors | None = None, pool_factor=4, launch=None, probe_hops=1,
                  predict_only=False, range_from: torch.Tensor | None = None,
                  order: torch.Tensor | None = None, max_dc=0, max_dc_factor=0.0,
-                 id_map: torch.Tensor | None = None, single_pass=False):
+                 id_map: torch.Tensor | None = None, single_pass=False, static_scratch=False):
+        """static_scratch: run through onng_search_static (the library's
+        static device scratch; no workspace is allocated)."""
         dev = queries.data.device
         nq = queries.n
         self.base, self.graph, self.queries = base, graph, queries
@@ -337,6 +339,10 @@ class SearchRequest:
         self.ids = torch.empty((nq, self.k_stride), dtype=torch.int32, device=dev)
         self.dists = torch.empty((nq, self.k_stride), dtype=out_dt, device=dev)
         self.stats = torch.empty((nq, 8), dtype=torch.int32, device=dev)
+        self.static_scratch = bool(static_scratch)
+        self.ws = None
+        if self.static_scratch:
+            return
         self.ws_bytes = L.load().onng_search_workspace_size(base.ref, nq, C.byref(self.params))
         if self.ws_bytes == 0:
             raise L.OnngError("onng_search_workspace_size", L.ERR_INVALID_ARG,
@@ -344,6 +350,11 @@ class SearchRequest:
         self.ws = _workspace(self.ws_bytes, dev)
 
     def run(self):
+        if self.static_scratch:
+            L.call("onng_search_static", self.base.ref, C.byref(self.gs), self.queries.ref,
+                   self.seeds.data_ptr(), self.seeds.shape[1], C.byref(self.params),
+                   self.ids.data_ptr(), self.dists.data_ptr(), self.stats.data_ptr(), _stream())
+            return self
         L.call("onng_search", self.base.ref, C.byref(self.gs), self.queries.ref,
                self.seeds.data_ptr(), self.seeds.shape[1], C.byref(self.params),
                self.ids.data_ptr(), self.dists.data_ptr(), self.stats.data_ptr(),

@@ -821,6 +821,81 @@ onng_status onng_search(const onng_vectors *base, const onng_graph *graph,
                       ws_bytes, as_stream(stream), cfg);
 }
 
+// -------------------------------------------- search without allocation ----
+
+// Scratch of onng_search_static: work counter, visited bitsets, visit logs and
+// spill buffers of the persistent waves.  Each device the library runs on
+// holds its own copy until the process ends.  Host code never uses this name
+// as a device address: the address on a device comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[ONNG_SEARCH_STATIC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void *> g_scratch_ptr;   // device ordinal -> its `scratch`
+
+// Address of `scratch` on the current device, looked up once per device.
+static onng_status scratch_on_current_device(void **out) {
+    int dev = 0;
+    ONNG_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return ONNG_OK;
+    }
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        set_error(std::string("onng_search_static: hipGetSymbolAddress failed: ") +
+                  hipGetErrorString(e));
+        return ONNG_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+    *out = p;
+    return ONNG_OK;
+}
+
+onng_status onng_search_static(const onng_vectors *base, const onng_graph *graph,
+                               const onng_vectors *queries, const int32_t *seeds, int32_t n_seeds,
+                               const onng_search_params *params, int32_t *ids, void *dists,
+                               onng_query_stats *stats, void *stream) {
+    set_error("");
+    ONNG_TRY(validate_search(base, graph, queries, seeds, n_seeds, params));
+    ONNG_CHECK_ARG(ids && dists && stats, "outputs are null");
+    if (queries->n == 0) return ONNG_OK;
+    void *ws = nullptr;
+    ONNG_TRY(scratch_on_current_device(&ws));
+    onng_launch_config tuned;
+    const onng_launch_config *cfg0 = params->launch;
+    if (!cfg0 && lookup_tuned(base, params, &tuned)) cfg0 = &tuned;
+    SearchPlan P;
+    ONNG_TRY(make_plan(base, queries->n, params, cfg0, &P));
+    // the same shape with as many persistent blocks as the scratch holds; the
+    // carve adds at most 256 bytes of alignment per region (five regions)
+    const size_t per_slot = (size_t)P.gbits_words * 4 + (size_t)P.vlog_cap * 4 +
+                            (size_t)P.spill_cap * 16;
+    const size_t fixed = 6 * 256 + 64 * 4;
+    const size_t cap = ONNG_SEARCH_STATIC_SCRATCH_BYTES;
+    const int64_t max_blocks =
+        cap > fixed ? (int64_t)((cap - fixed) / (per_slot * (size_t)P.wpb)) : 0;
+    if (max_blocks < 1) {
+        set_error("onng_search_static: a block of " + std::to_string(P.wpb) + " waves needs " +
+                  std::to_string(per_slot * P.wpb + fixed) + " bytes of scratch for " +
+                  std::to_string(base->n) + " rows; the static scratch holds " +
+                  std::to_string(cap) + " (use onng_search with a workspace)");
+        return ONNG_ERR_CAPACITY;
+    }
+    onng_launch_config c = cfg0 ? *cfg0 : onng_launch_config{};
+    c.blocks = (int32_t)std::min<int64_t>(P.blocks, max_blocks);
+    SearchPlan P2;
+    ONNG_TRY(make_plan(base, queries->n, params, &c, &P2));
+    if (P2.ws > cap) {
+        set_error("onng_search_static: internal scratch layout");
+        return ONNG_ERR_CAPACITY;
+    }
+    return run_search(base, graph, queries, seeds, n_seeds, params, ids, dists, stats, ws, cap,
+                      as_stream(stream), &c);
+}
+
 size_t onng_order_by_cost_workspace_size(int64_t n) { return n < 0 ? 0 : order_ws(n); }
 
 onng_status onng_order_by_cost(const onng_query_stats *stats, int64_t n, int32_t *order, void *ws,
