@@ -1,20 +1,32 @@
-"""Second, independent oracle for tiny inputs: pure-Python loops that follow
-the paper's algorithms in their printed order, with sets and lists only.
+"""Second, independent oracle for tiny inputs, written from what each step of
+the method computes rather than from the printed listings: pure Python over
+dicts and lists, no heaps, no shared code with the C oracle.
 
-TEST INFRASTRUCTURE ONLY.  Distances come in as a callable dist(a, b), so the
-same code serves exact integer and fp64 data.  Ties are broken by node id
-(reading R4), and the readings R1, R2, R5, R11 and R12 apply as in the C oracle.
+TEST INFRASTRUCTURE ONLY.  Distances come in as a callable, so the same code
+serves exact integer and fp64 data.  Ties are broken by node id everywhere
+(reading R4), and the readings R1, R2, R5, R11 and R12 apply as in the C
+oracle.
 
-* knn_search:            Algorithm 1 (KnnSearch), C a plain Python set.
-* adjusted_graph:        Algorithm 2 (ConstructAdjustedGraph).
-* adjusted_graph_with_constraint: Algorithm 3, with M a set and the argmin
-                         over (|N(G_t, x)|, x) taken afresh every step (R10).
-* adjust_path/has_path:  Algorithms 4 and 5 (AdjustPath, HasPath).
-* paper_visited:         Algorithms 6 and 7 (Set, IsSet) as a class.
-* construct_anng:        Algorithm 9, one object at a time.
-* vptree:                the 4-way vantage-point tree of the seeds (Section
-                         3.2, Table 5), built depth first and renumbered
-                         breadth first afterwards.
+* knn_search:  KnnSearch (Algorithm 1, Section 2) stated as: keep the set V
+               of nodes whose distance has been computed; repeatedly expand
+               the nearest node of V not expanded yet, as long as it lies
+               within r(1 + eps), r being the k-th smallest distance in V;
+               an expansion computes the distances of the first e_p entries
+               of the node's list that are not in V yet.  R is the k nearest
+               of V.  (The candidate set of the listing only ever holds
+               nodes of V; a node it rejected lies beyond every later range,
+               so "nearest unexpanded node of V" is the node it pops.)
+* adjusted_graph: ConstructAdjustedGraph (Algorithm 2, Section 2.1) as the
+               set identity N(G_e, o) = F(o) u Rv(o).
+* adjusted_graph_with_constraint: Algorithm 3 (Section 2.2) as one pass
+               over its edge decisions in their stated order.
+* adjust_path: AdjustPath / HasPath (Algorithms 4 and 5, Section 2.3) as one
+               pass over the edge decisions in their stated order, each edge
+               tested for a shorter two-hop detour among the edges kept so far.
+* PaperVisited: the visited-node table of Section 2.5 (Algorithms 6 and 7).
+* construct_anng: Algorithm 9 (Appendix), one object at a time.
+* vptree:      the 4-way vantage-point tree of the seeds (Section 3.2,
+               Table 5), built depth first and renumbered breadth first.
 """
 from __future__ import annotations
 
@@ -23,136 +35,123 @@ import math
 import numpy as np
 
 
-def _key(d, i):
-    return (d, i)
+def knn_search(neigh, dist_to_q, seeds, k, thr_fn, ep=math.inf, max_dc=0, trace=None,
+               visited=None):
+    """neigh[s]: the edge list of s in stored order (ascending length);
+    dist_to_q(n) = d(n, q); thr_fn(r) = r(1 + eps) in the reading's
+    arithmetic (R5); ep: entries scanned per expansion (Equation 1's e_p,
+    counting visited entries too).  max_dc > 0: a distance-computation
+    budget checked before each expansion (not in the paper).  Returns
+    (R as (d, id) ascending, distance computations, expansions).
+    trace (a list) receives the count after the seeds and after each
+    expansion; visited (a dict) receives id -> d for every node of V."""
+    V = {} if visited is None else visited
+    for s in seeds:                      # R2: distinct seeds, each one computation
+        if s not in V:
+            V[s] = dist_to_q(s)
+    expanded = set()
 
+    def nearest(m):
+        return sorted((d, i) for i, d in V.items())[:m]
 
-def knn_search(neigh, dist_to_q, seeds, k, thr_fn, ep=math.inf, max_dc=0, trace=None):
-    """Algorithm 1.  neigh[s] is the edge list of s sorted by length;
-    dist_to_q(n) is d(n, q); thr_fn(r) returns r(1+eps) in the reading's
-    arithmetic.  max_dc > 0 adds a distance-computation budget checked before
-    each pop (not in the paper).  Returns (R sorted by (d, id), distance
-    computations, hops).  trace, if a list, receives the distance count after
-    the seeds and after every expansion."""
-    C = set()
-    S = []                               # list of (d, id)
-    R = []                               # list of (d, id)
-    r = math.inf
-    dc = 0
-    for s in seeds:                      # R2: seeds de-duplicated, offered to R
-        if s in C:
-            continue
-        C.add(s)
-        d = dist_to_q(s)
-        dc += 1
-        S.append((d, s))
-        if d <= r:
-            R.append((d, s))
-            if len(R) > k:
-                R.remove(max(R))
-            if len(R) == k:
-                r = max(R)[0]
-    hops = 0
+    def radius():
+        best = nearest(k)
+        return best[-1][0] if len(best) == k else math.inf
+
     if trace is not None:
-        trace.append(dc)
-    while S:
-        if max_dc > 0 and dc >= max_dc:
+        trace.append(len(V))
+    scan = None if math.isinf(ep) else int(ep)
+    while not (max_dc > 0 and len(V) >= max_dc):
+        todo = [(d, i) for i, d in V.items() if i not in expanded]
+        if not todo:
             break
-        s = min(S)                       # argmin over S by (d, id)
-        S.remove(s)
-        if s[0] > thr_fn(r):
-            return sorted(R), dc, hops
-        hops += 1
-        p = 1
-        M = list(neigh[s[1]])            # already ascending by length
-        while M and p <= ep:
-            n = M.pop(0)
-            if n not in C:
-                C.add(n)
-                d = dist_to_q(n)
-                dc += 1
-                if d <= thr_fn(r):
-                    S.append((d, n))
-                if d <= r:
-                    R.append((d, n))
-                    if len(R) > k:
-                        R.remove(max(R))
-                    if len(R) == k:
-                        r = max(R)[0]
-            p += 1
+        d, s = min(todo)
+        if d > thr_fn(radius()):
+            break
+        expanded.add(s)
+        for n in list(neigh[s])[:scan]:
+            if n not in V:
+                V[n] = dist_to_q(n)
         if trace is not None:
-            trace.append(dc)
-    return sorted(R), dc, hops
+            trace.append(len(V))
+    return nearest(k), len(V), len(expanded)
 
 
 def adjusted_graph(knn, knn_d, e_o, e_i):
-    """Algorithm 2 with the loop guard read as "p <= e_o or p <= e_i" (R1).
-    knn[o] lists o's neighbours, knn_d[o] their distances.  Returns per-node
-    lists of (len, id) sorted ascending."""
+    """G_e of Algorithm 2: o keeps F(o), the first e_o entries of its own row,
+    and receives Rv(o), the nodes m whose row holds o among its first e_i
+    entries (reading R1: both bounds apply, the row ends the loop).  An edge
+    takes the length stored in the row it comes from; a pair present both
+    ways keeps the copy Algorithm 2's node order meets first (R17): the
+    reverse one when m < o.  Returns per-node lists of (len, id), ascending."""
     n = len(knn)
-    Ge = [dict() for _ in range(n)]      # id -> length, per node
+    row = [[(knn_d[o][t], knn[o][t]) for t in range(len(knn[o])) if knn[o][t] >= 0]
+           for o in range(n)]
+    fwd = [{i: d for d, i in row[o][:e_o]} for o in range(n)]
+    rev = [dict() for _ in range(n)]
+    for m in range(n):
+        for d, o in row[m][:e_i]:
+            rev[o][m] = d
+    out = []
     for o in range(n):
-        S = [(knn_d[o][t], knn[o][t]) for t in range(len(knn[o])) if knn[o][t] >= 0]
-        p = 1
-        while S and (p <= e_o or p <= e_i):
-            dn = min(S)
-            S.remove(dn)
-            d, nn = dn
-            if p <= e_o and nn not in Ge[o]:
-                Ge[o][nn] = d
-            if p <= e_i and o not in Ge[nn]:
-                Ge[nn][o] = d
-            p += 1
-    return [sorted((l, i) for i, l in Ge[o].items()) for o in range(n)]
+        edges = {}
+        for m in set(fwd[o]) | set(rev[o]):
+            if m in rev[o] and (m not in fwd[o] or m < o):
+                edges[m] = rev[o][m]
+            else:
+                edges[m] = fwd[o][m]
+        out.append(sorted((l, i) for i, l in edges.items()))
+    return out
 
 
 def adjusted_graph_with_constraint(knn, knn_d, e_o, e_i):
-    """Algorithm 3.  Same input as adjusted_graph.  G_i is a list of sets;
-    every argmin is taken over the remaining members.  Returns per-node lists
-    of (len, id) sorted ascending."""
+    """G_e of Algorithm 3.  Its first loop decides the edges o -> n of G_t
+    (Algorithm 2 with (0, e_i): each node's reverse edges) one by one, nodes
+    by ascending (|N(G_t, o)|, o) (R10) and within a node by (len, id): an
+    edge is kept when n has no incoming edge yet, or when n's in-degree is
+    below e_i and o's out-degree below e_o.  The second loop tops every node
+    with fewer than e_o edges up from its own row, in row order.  Returns
+    per-node lists of (len, id), ascending."""
     n = len(knn)
-    Gt = [dict((i, l) for l, i in lst) for lst in adjusted_graph(knn, knn_d, 0, e_i)]
-    Ge = [dict() for _ in range(n)]
-    Gi = [set() for _ in range(n)]
-    M = set(range(n))
-    while M:
-        o = min(M, key=lambda x: (len(Gt[x]), x))
-        M.remove(o)
-        S = dict(Gt[o])
-        while S:
-            nn = min(S, key=lambda x: (S[x], x))
-            d = S.pop(nn)
-            if not Gi[nn] or (len(Gi[nn]) < e_i and len(Ge[o]) < e_o):
-                Ge[o][nn] = d
-                Gi[nn].add(o)
+    Gt = adjusted_graph(knn, knn_d, 0, e_i)
+    node_order = sorted(range(n), key=lambda x: (len(Gt[x]), x))
+    decisions = [(o, l, t) for o in node_order for l, t in Gt[o]]
+    out = [[] for _ in range(n)]
+    indeg = [0] * n
+    for o, l, t in decisions:
+        if indeg[t] == 0 or (indeg[t] < e_i and len(out[o]) < e_o):
+            out[o].append((l, t))
+            indeg[t] += 1
     for o in range(n):
-        S = {knn[o][t]: knn_d[o][t] for t in range(len(knn[o])) if knn[o][t] >= 0}
-        while S and len(Ge[o]) < e_o:
-            nn = min(S, key=lambda x: (S[x], x))
-            d = S.pop(nn)
-            if nn not in Ge[o]:
-                Ge[o][nn] = d
-    return [sorted((l, i) for i, l in Ge[o].items()) for o in range(n)]
+        have = {t for _, t in out[o]}
+        for j in range(len(knn[o])):
+            if len(out[o]) >= e_o:
+                break
+            t = knn[o][j]
+            if t >= 0 and t not in have:
+                out[o].append((knn_d[o][j], t))
+                have.add(t)
+    return [sorted(lst) for lst in out]
 
 
 def construct_anng(order, dist, k_c, thr_fn, n_seeds, n_pivots):
-    """Algorithm 9 as printed: objects in `order` one by one; each gets the
-    KnnSearch results on the graph so far as edges, and each result gets the
-    reverse edge.  Seeds: the n_seeds objects nearest the new one among the
-    first n_pivots inserted, by (d, id).  Returns per-node lists of (len, id)
-    sorted ascending."""
-    adj = {o: [] for o in order}
-    inserted = []
-    for o in order:
-        if inserted:
-            neigh = {v: [i for _, i in sorted(adj[v])] for v in inserted}
-            piv = sorted(inserted[:n_pivots], key=lambda m: (dist(o, m), m))[:n_seeds]
-            R, _, _ = knn_search(neigh, lambda m: dist(o, m), piv, k_c, thr_fn)
-            for d, m in R:
-                adj[o].append((d, m))
-                adj[m].append((d, o))
-        inserted.append(o)
-    return {o: sorted(adj[o]) for o in order}
+    """Algorithm 9: objects join in `order`; a new object's edges are the
+    k_c results of KnnSearch (range eps_c, unlimited e_p) on the graph of the
+    objects before it, and each result gets the edge back.  Seeds: the
+    n_seeds objects nearest the new one among the first n_pivots inserted,
+    by (d, id).  Returns per-node lists of (len, id), ascending."""
+    graph = {o: [] for o in order}
+    for t, o in enumerate(order):
+        before = order[:t]
+        found = []
+        if before:
+            lists = {v: [i for _, i in sorted(graph[v])] for v in before}
+            seeds = sorted(before[:n_pivots], key=lambda m: (dist(o, m), m))[:n_seeds]
+            found, _, _ = knn_search(lists, lambda m: dist(o, m), seeds, k_c, thr_fn)
+        for d, m in found:
+            graph[o].append((d, m))
+            graph[m].append((d, o))
+    return {o: sorted(graph[o]) for o in order}
 
 
 def vptree(ids, dist, prio, leaf_size, n_seeds):
@@ -190,54 +189,48 @@ def vptree(ids, dist, prio, leaf_size, n_seeds):
     return vp, child, mu, seeds
 
 
-def has_path(Gp, ns, nd, d_ns_nd):
-    """Algorithm 5 with edge lengths as distances."""
-    for c, _ in Gp[ns]:
-        for m, lcm in Gp[c]:
-            if m == nd and lcm < d_ns_nd:
-                return True
-    return False
-
-
 def adjust_path(G):
-    """Algorithm 4.  G: per-node lists of (len, id).  Returns G_p as per-node
-    lists of (id, len) in insertion order."""
+    """G_p of Algorithms 4 and 5.  G: per-node lists of (len, id).  The
+    edges are decided in the order Algorithm 4 visits them: round j takes
+    the j-th shortest edge of every node that has one, nodes in ascending id
+    (R11: each decision sees every earlier one).  Edge n -> t of length l is
+    dropped when the kept edges already hold n -> c and c -> t with
+    len(c, t) < l (HasPath, strict, R12); otherwise it is kept.  Returns
+    per-node lists of (id, len) in decision order."""
     n = len(G)
-    Gt = [sorted(G[v]) for v in range(n)]
-    Gp = [[] for _ in range(n)]
-    Vt = [v for v in range(n) if Gt[v]]
-    while Vt:
-        for v in list(Vt):               # ascending id, immediate visibility (R11)
-            ln, nd = min(Gt[v])
-            if not has_path(Gp, v, nd, ln):
-                Gp[v].append((nd, ln))
-            Gt[v].remove((ln, nd))
-            if not Gt[v]:
-                Vt.remove(v)
-    return Gp
+    ranked = [sorted(G[v]) for v in range(n)]
+    decisions = sorted((j, v) for v in range(n) for j in range(len(ranked[v])))
+    kept = [[] for _ in range(n)]
+    for j, v in decisions:
+        l, t = ranked[v][j]
+        detour = any(m == t and lm < l for c, _ in kept[v] for m, lm in kept[c])
+        if not detour:
+            kept[v].append((t, l))
+    return kept
 
 
 class PaperVisited:
-    """Algorithms 6 and 7: table b of size s plus collision lists L."""
+    """The visited-node set of Section 2.5: s = 2^floor((log2 n + b) / 2)
+    slots addressed by the low bits of the id.  A slot holds the first id
+    that hashed to it; any other id of that slot goes to the slot's overflow
+    set.  Membership: the slot's id, else its overflow set."""
 
     def __init__(self, n, b=11):
         lg = int(n).bit_length() - 1
         self.s = 1 << ((lg + b) // 2)
-        self.b = [None] * self.s
-        self.L = [set() for _ in range(self.s)]
+        self.first = [None] * self.s
+        self.more = [set() for _ in range(self.s)]
 
     def set(self, i):
         h = i % self.s
-        if self.b[h] is None:
-            self.b[h] = i
-        elif self.b[h] != i:
-            self.L[h].add(i)
+        if self.first[h] is None:
+            self.first[h] = i
+        elif self.first[h] != i:
+            self.more[h].add(i)
 
     def isset(self, i):
         h = i % self.s
-        if self.b[h] == i:
-            return True
-        return i in self.L[h]
+        return self.first[h] == i or i in self.more[h]
 
 
 def brute_topk(D: np.ndarray, k: int, exclude_diag: bool = False):

@@ -887,9 +887,32 @@ typedef struct {
     double *out_d;
     int64_t *out_dc, *out_hops;
     double *out_margin, *feat;
+    int32_t pool_k;
+    int32_t *pool_ids;
+    double *pool_d, *pool_margin;
+    int32_t probe_only;
     int64_t next;
     pthread_mutex_t mu;
 } search_job;
+
+/* The candidates of a rerank: the pool_k + 1 smallest (d, id) among the
+ * distances the search computed (seeds and visited nodes), ascending. */
+typedef struct { double *d; int64_t *id; int32_t n, cap; } pool_t;
+
+static void pool_offer(pool_t *P, double d, int64_t id)
+{
+    if (P->cap == 0) return;
+    if (P->n == P->cap && !key_less(d, id, P->d[P->n - 1], P->id[P->n - 1])) return;
+    int32_t pos = P->n < P->cap ? P->n : P->cap - 1;
+    while (pos > 0 && key_less(d, id, P->d[pos - 1], P->id[pos - 1])) {
+        P->d[pos] = P->d[pos - 1];
+        P->id[pos] = P->id[pos - 1];
+        pos--;
+    }
+    P->d[pos] = d;
+    P->id[pos] = id;
+    if (P->n < P->cap) P->n++;
+}
 
 /* f of reading R5 */
 static float range_factor(float eps, int32_t metric)
@@ -925,7 +948,7 @@ static int dcmp(const void *a, const void *b)
     return (x > y) - (x < y);
 }
 
-static void search_one(search_job *J, visited_t *C, heap_t *S, rset_t *R, int64_t q)
+static void search_one(search_job *J, visited_t *C, heap_t *S, rset_t *R, pool_t *Pl, int64_t q)
 {
     const int u8 = J->base->dtype == OR_U8;
     const double mfloor = J->base->metric == OR_COS ? 1e-2 : 1e-300;
@@ -944,6 +967,7 @@ static void search_one(search_job *J, visited_t *C, heap_t *S, rset_t *R, int64_
     S->n = 0;
     R->n = 0;
     R->k = k;
+    Pl->n = 0;
     double seedd[64];
     int32_t nseedd = 0;
 
@@ -957,6 +981,7 @@ static void search_one(search_job *J, visited_t *C, heap_t *S, rset_t *R, int64_
         if (nseedd < 64) seedd[nseedd++] = d;
         if (!isinf(r)) margin = fmin(margin, rel_gap(d, r, mfloor));
         rset_offer(R, &r, d, s);
+        pool_offer(Pl, d, s);
         heap_push(S, d, s);
     }
     const int64_t budget = J->max_dc && J->max_dc[q] > 0 ? J->max_dc[q] : INT64_MAX;
@@ -980,6 +1005,7 @@ static void search_one(search_job *J, visited_t *C, heap_t *S, rset_t *R, int64_
             if (d <= thr) heap_push(S, d, nn);
             margin = fmin(margin, rel_gap(d, r, mfloor));
             rset_offer(R, &r, d, nn);
+            pool_offer(Pl, d, nn);
         }
         if (phase1 && hops == J->probe_hops) {
             if (J->feat) {
@@ -1005,6 +1031,7 @@ static void search_one(search_job *J, visited_t *C, heap_t *S, rset_t *R, int64_
                 F[12] = rmax;
                 F[13] = (double)dc;
             }
+            if (J->probe_only) break;   /* the state at the switch is all this call reports */
             f = range_factor(J->eps[q], J->base->metric);
             ep = J->ep[q];
         }
@@ -1020,6 +1047,18 @@ static void search_one(search_job *J, visited_t *C, heap_t *S, rset_t *R, int64_
     if (J->out_dc) J->out_dc[q] = dc;
     if (J->out_hops) J->out_hops[q] = hops;
     if (J->out_margin) J->out_margin[q] = margin;
+    if (J->pool_k > 0) {
+        int32_t *pid = J->pool_ids + q * J->pool_k;
+        double *pd = J->pool_d + q * J->pool_k;
+        for (int32_t t = 0; t < J->pool_k; t++) {
+            pid[t] = t < Pl->n ? (int32_t)Pl->id[t] : -1;
+            pd[t] = t < Pl->n ? Pl->d[t] : INFINITY;
+        }
+        /* membership of the pool_k-th against the next distance computed */
+        if (J->pool_margin)
+            J->pool_margin[q] = Pl->n > J->pool_k
+                ? rel_gap(Pl->d[J->pool_k - 1], Pl->d[J->pool_k], mfloor) : INFINITY;
+    }
 }
 
 static void *search_worker(void *arg)
@@ -1033,15 +1072,20 @@ static void *search_worker(void *arg)
     rset_t R;
     R.d = (double *)malloc(sizeof(double) * (size_t)(kmax + 1));
     R.id = (int64_t *)malloc(sizeof(int64_t) * (size_t)(kmax + 1));
+    pool_t Pl;
+    Pl.cap = J->pool_k > 0 ? J->pool_k + 1 : 0;
+    Pl.n = 0;
+    Pl.d = (double *)malloc(sizeof(double) * (size_t)(Pl.cap + 1));
+    Pl.id = (int64_t *)malloc(sizeof(int64_t) * (size_t)(Pl.cap + 1));
     for (;;) {
         pthread_mutex_lock(&J->mu);
         int64_t q = J->next++;
         pthread_mutex_unlock(&J->mu);
         if (q >= J->nq) break;
-        search_one(J, &C, &S, &R, q);
+        search_one(J, &C, &S, &R, &Pl, q);
     }
     visited_free(&C);
-    free(S.a); free(R.d); free(R.id);
+    free(S.a); free(R.d); free(R.id); free(Pl.d); free(Pl.id);
     return NULL;
 }
 
@@ -1052,19 +1096,23 @@ int or_search(const or_vecs *base, const int64_t *offsets, const int32_t *nbrs,
               const float *eps1, const uint32_t *ep1, int32_t probe_hops,
               const int32_t *max_dc, int32_t k_stride, int32_t *out_ids, double *out_d,
               int64_t *out_dc, int64_t *out_hops, double *out_margin,
-              double *feat, int32_t nthreads)
+              double *feat, int32_t pool_k, int32_t *pool_ids, double *pool_d,
+              double *pool_margin, int32_t probe_only, int32_t nthreads)
 {
     if (!base || !offsets || !queries || !seeds || !k || !eps || !ep || !out_ids || !out_d)
         return -1;
+    if (pool_k < 0 || (pool_k > 0 && (!pool_ids || !pool_d)))
+        return -1;
     if (n_nodes != base->n || base->dim != queries->dim || n_seeds <= 0 || k_stride <= 0)
         return -1;
-    if ((eps1 == NULL) != (ep1 == NULL))
+    if ((eps1 == NULL) != (ep1 == NULL) || (probe_only && !eps1))
         return -1;
     for (int64_t q = 0; q < nq; q++)
         if (k[q] <= 0 || k[q] > k_stride) return -1;
     search_job J = {base, queries, offsets, nbrs, n_nodes, nq, seeds, n_seeds, k, eps, eps1,
                     ep, ep1, probe_hops < 1 ? 1 : probe_hops, max_dc, k_stride, out_ids, out_d, out_dc,
-                    out_hops, out_margin, feat, 0, PTHREAD_MUTEX_INITIALIZER};
+                    out_hops, out_margin, feat, pool_k, pool_ids, pool_d, pool_margin,
+                    probe_only, 0, PTHREAD_MUTEX_INITIALIZER};
     run_pool(search_worker, &J, nthreads);
     return 0;
 }

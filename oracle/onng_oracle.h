@@ -113,7 +113,16 @@ int or_adjust_path(const int64_t *in_off, const int32_t *in_nbrs,
  * computations so far.
  * max_dc (optional, per query; <= 0 = none): a distance-computation budget,
  * an addition to the paper: before each pop, a query that has made max_dc[q]
- * or more distance computations stops and returns its current R. */
+ * or more distance computations stops and returns its current R.
+ * pool_k > 0 (an addition for the rerank of low-precision rows): pool_ids /
+ * pool_d [nq][pool_k] receive the pool_k smallest (d, id) over every distance
+ * the search computed (seeds and visited nodes), ascending, padded -1/+inf;
+ * like R this set does not depend on the order of the visits.  pool_margin
+ * (optional, [nq]) the relative gap between the pool_k-th and the next
+ * computed distance (+inf when fewer were computed).
+ * probe_only != 0 (needs eps1/ep1): stop at the switch after the probe
+ * expansions, as a pass that only predicts the range does; the outputs and
+ * the margin then describe that state. */
 #define OR_NFEAT 14
 int or_search(const or_vecs *base, const int64_t *offsets, const int32_t *nbrs,
               int64_t n_nodes, const or_vecs *queries, int64_t nq,
@@ -122,7 +131,8 @@ int or_search(const or_vecs *base, const int64_t *offsets, const int32_t *nbrs,
               const float *eps1, const uint32_t *ep1, int32_t probe_hops,
               const int32_t *max_dc, int32_t k_stride, int32_t *out_ids, double *out_d,
               int64_t *out_dc, int64_t *out_hops, double *out_margin,
-              double *feat, int32_t nthreads);
+              double *feat, int32_t pool_k, int32_t *pool_ids, double *pool_d,
+              double *pool_margin, int32_t probe_only, int32_t nthreads);
 
 /* Visited-node table of Algorithms 6/7, exposed for tests. */
 int64_t or_hash_size(int64_t n, int32_t b);

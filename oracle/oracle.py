@@ -57,7 +57,8 @@ def lib():
         _lib.or_vptree_build.argtypes = [P, P, C.c_int32, C.c_int32, P, P, P, P, P, P]
         _lib.or_vptree_seeds.argtypes = [P, P, C.c_int64, P, P, P, P, C.c_int32, P, P]
         _lib.or_search.argtypes = [P, P, P, C.c_int64, P, C.c_int64, P, C.c_int32, P, P, P, P,
-                                   P, C.c_int32, P, C.c_int32, P, P, P, P, P, P, C.c_int32]
+                                   P, C.c_int32, P, C.c_int32, P, P, P, P, P, P, C.c_int32, P, P,
+                                   P, C.c_int32, C.c_int32]
         _lib.or_hash_size.restype = C.c_int64
         _lib.or_hash_size.argtypes = [C.c_int64, C.c_int32]
         _lib.or_visited_replay.argtypes = [C.c_int64, P, C.c_int64, P]
@@ -390,8 +391,12 @@ def _per_query(v, nq, dtype):
 
 def search(base: Vectors, off, nbrs, queries: Vectors, seeds, k, eps, ep=INF_EP, eps1=None,
            ep1=None, k_stride=None, want_features=False, threads=None, probe_hops=1,
-           max_dc=None):
-    """Algorithm 1 for every query.  Returns dict with ids, dists, dc, hops, margin[, feat]."""
+           max_dc=None, pool_k=0, probe_only=False):
+    """Algorithm 1 for every query.  Returns dict with ids, dists, dc, hops,
+    margin[, feat][, pool_ids, pool_d, pool_margin].  pool_k > 0: the pool_k
+    smallest (d, id) over all distances computed (the candidates a rerank
+    of low-precision rows takes).  probe_only (with eps1/ep1): stop at the
+    switch after the probe expansions, like a pass that only predicts."""
     nq = queries.n
     seeds = np.ascontiguousarray(seeds, dtype=np.int32)
     kk = _per_query(k, nq, np.int32)
@@ -409,16 +414,22 @@ def search(base: Vectors, off, nbrs, queries: Vectors, seeds, k, eps, ep=INF_EP,
     hops = np.empty(nq, dtype=np.int64)
     margin = np.empty(nq, dtype=np.float64)
     feat = np.zeros((nq, NFEAT), dtype=np.float64) if want_features else None
+    pid = np.empty((nq, max(pool_k, 1)), dtype=np.int32)
+    pd = np.empty((nq, max(pool_k, 1)), dtype=np.float64)
+    pm = np.empty(nq, dtype=np.float64)
     rc = lib().or_search(base.ref, off.ctypes.data, nbrs.ctypes.data, base.n, queries.ref, nq,
                          seeds.ctypes.data, seeds.shape[1], kk.ctypes.data, ee.ctypes.data,
                          pp.ctypes.data, _ptr(e1), _ptr(p1), probe_hops, _ptr(md), ks,
                          ids.ctypes.data,
                          ds.ctypes.data, dc.ctypes.data, hops.ctypes.data, margin.ctypes.data,
-                         _ptr(feat), threads or nthreads())
+                         _ptr(feat), int(pool_k), pid.ctypes.data, pd.ctypes.data,
+                         pm.ctypes.data, int(bool(probe_only)), threads or nthreads())
     assert rc == 0, rc
     out = dict(ids=ids, dists=ds, dc=dc, hops=hops, margin=margin)
     if want_features:
         out["feat"] = feat
+    if pool_k > 0:
+        out.update(pool_ids=pid, pool_d=pd, pool_margin=pm)
     return out
 
 
@@ -479,6 +490,86 @@ def feature_transform(feat: np.ndarray, metric: int) -> np.ndarray:
         x[:, j] = np.log(np.maximum(feat[:, j], 0.0) + c) - lg[:, 0]
     x[:, 13] = np.log1p(feat[:, 13])
     return x
+
+
+_BF16_TABLE = None
+
+
+def decode_bf16(bits) -> np.ndarray:
+    """bfloat16 codes (uint16) -> exact fp64 values, through the oracle's codec."""
+    global _BF16_TABLE
+    if _BF16_TABLE is None:
+        _BF16_TABLE = np.array([decode(BF16, c) for c in range(1 << 16)], dtype=np.float64)
+    return _BF16_TABLE[np.asarray(bits, dtype=np.int64) & 0xFFFF]
+
+
+def predict(feat, metric: int, w1_bits, b1, w2_bits, b2, mean, std, mode: str, *,
+            head=0, head_per_query=None, shift=None, eps_cand=None, lam=0.0,
+            lam_per_query=None, eps_min=0.0, eps_max=math.inf, e0=30.0, we=-1.0,
+            ep_default=INF_EP):
+    """The learned search range of every query (an extension, not in the
+    paper), composed from its definition: raw state after the probe
+    expansions -> feature_transform -> z-score with the stored statistics ->
+    2-layer MLP in fp64 on the bf16-decoded weights -> choice.
+
+    mode "curve": heads [0, G) estimate the recall and [G, 2G) log(1 + cost)
+    at each candidate range eps_cand[g]; the query takes the first g of the
+    largest recall_g - lambda * (exp(cost head) - 1) and that candidate's
+    cost estimate.  mode "log_eps": head h (head_per_query[q] or `head`)
+    gives log10(eps + 0.01) after adding shift[h]; cost = eps.  eps is
+    clamped to [eps_min, eps_max]; e_p follows Equation 1 with (e0, we)
+    when we >= 0, else ep_default.
+
+    Returns dict eps (fp64), ep (int64), cost (fp64), margin: the relative
+    gap of the decision (curve: best vs second score over max(1, |best|);
+    log_eps: inf) and ep_margin: distance of 10^(we eps) + e0 to the next
+    integer boundary, relative to its value (inf when we < 0)."""
+    feat = np.asarray(feat, dtype=np.float64)
+    nq = feat.shape[0]
+    x = feature_transform(feat, metric)
+    z = (x - np.asarray(mean, np.float32).astype(np.float64)) / \
+        np.asarray(std, np.float32).astype(np.float64)
+    b1 = np.asarray(b1, np.float32).astype(np.float64)
+    b2 = np.asarray(b2, np.float32).astype(np.float64)
+    H, T = len(b1), len(b2)
+    W1 = decode_bf16(w1_bits).reshape(H, -1)
+    W2 = decode_bf16(w2_bits).reshape(T, H)
+    _, y = mlp_forward(z, W1, b1, W2, b2)
+    margin = np.full(nq, np.inf)
+    if mode == "curve":
+        cand = np.asarray(eps_cand, np.float32).astype(np.float64)
+        G = len(cand)
+        lq = (np.full(nq, np.float32(lam), np.float64) if lam_per_query is None
+              else np.asarray(lam_per_query, np.float32).astype(np.float64))
+        score = y[:, :G] - lq[:, None] * (np.exp(y[:, G:2 * G]) - 1.0)
+        best = np.argmax(score, axis=1)
+        eps = cand[best]
+        cost = np.exp(y[np.arange(nq), G + best]) - 1.0
+        if G > 1:
+            srt = np.sort(score, axis=1)
+            margin = (srt[:, -1] - srt[:, -2]) / np.maximum(1.0, np.abs(srt[:, -1]))
+    elif mode == "log_eps":
+        h = (np.full(nq, int(head)) if head_per_query is None
+             else np.asarray(head_per_query, np.int64))
+        sh = np.zeros(T) if shift is None else np.asarray(shift, np.float32).astype(np.float64)
+        yh = y[np.arange(nq), h] + sh[h]
+        eps = 10.0 ** yh - 0.01
+        cost = eps.copy()
+    else:
+        raise ValueError(mode)
+    eps = np.clip(eps, float(np.float32(eps_min)), float(np.float32(eps_max)))
+    if mode == "log_eps":
+        cost = eps.copy()
+    if we >= 0:
+        v = 10.0 ** (float(np.float32(we)) * eps) + float(np.float32(e0))
+        ep = np.minimum(np.floor(v), float(INF_EP)).astype(np.int64)
+        frac = v - np.floor(v)
+        ep_margin = np.minimum(frac, 1.0 - frac) / np.maximum(v, 1.0)
+        ep_margin[eps == 0.0] = np.inf        # 10^0 + e0 is exact in any precision
+    else:
+        ep = np.full(nq, int(ep_default), np.int64)
+        ep_margin = np.full(nq, np.inf)
+    return dict(eps=eps, ep=ep, cost=cost, margin=margin, ep_margin=ep_margin, y=y)
 
 
 def labels_from_sweep(recalls: np.ndarray, eps_grid, targets) -> np.ndarray:

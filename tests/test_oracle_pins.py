@@ -876,3 +876,127 @@ def test_mlp_fits_linear_target():
         for p, gr, m, v in zip(params, grads, ms, vs):
             orc.adam_step(p, gr, m, v, 0.01, t)
     assert loss < 0.02 * first
+
+
+# --------------------------------------------- rerank pool, learned range
+
+def _small_problem(kind, seed, n=400, nq=12):
+    cfg = dg.scaled(dg.PRESETS["c1" if kind == "u8" else "c3"], n, nq, n_clusters=4)
+    cfg = dataclass_replace(cfg, config_id=90 + seed)
+    x, q = dg._vectors(cfg, n, 1), dg._vectors(cfg, nq, 2)
+    metric = orc.L2SQ if kind == "u8" else orc.COS
+    bv, qv = orc.Vectors.from_array(x, metric), orc.Vectors.from_array(q, metric)
+    knn, kd = orc.knn_graph(bv, 12)
+    po, pn, _ = orc.adjust_path(*orc.adjust_degree(knn, kd, 4, 10))
+    seeds = dg.random_seeds(cfg, nq, 4, stream_offset=seed)
+    return cfg, x, q, bv, qv, metric, po, pn, seeds
+
+
+@pytest.mark.parametrize("kind", ["u8", "f32cos"])
+@pytest.mark.parametrize("seed", range(2))
+def test_search_pool_is_the_nearest_of_all_computed(kind, seed):
+    """The rerank pool is the pool_k smallest (d, id) over every node whose
+    distance the search computed: the set V of the definitional search."""
+    cfg, x, q, bv, qv, metric, po, pn, seeds = _small_problem(kind, seed)
+    adj = [pn[po[u]:po[u + 1]].tolist() for u in range(len(x))]
+    for eps, ep, k, P in [(0.0, orc.INF_EP, 5, 20), (0.1, 6, 3, 12), (0.05, orc.INF_EP, 2, 1000)]:
+        r = orc.search(bv, po, pn, qv, seeds, k, eps, ep, pool_k=P)
+        f = orc.range_factor(eps, metric)
+        for qi in range(len(q)):
+            dfun = lambda u: orc.lib().or_dist(bv.ref, u, qv.ref, qi)
+            if kind == "u8":
+                thr = lambda rr: math.inf if math.isinf(rr) else float(np.float32(rr) * f)
+            else:
+                thr = lambda rr: rr * float(f)
+            V = {}
+            literal.knn_search(adj, dfun, seeds[qi].tolist(), k, thr, ep, visited=V)
+            near = sorted((d, i) for i, d in V.items())
+            want = [i for _, i in near[:P]] + [-1] * max(0, P - len(near))
+            assert r["pool_ids"][qi].tolist() == want
+            assert r["pool_ids"][qi, :k].tolist() == r["ids"][qi, :k].tolist()   # R is its head
+            if len(near) > P:
+                a, b = near[P - 1][0], near[P][0]
+                gap = abs(a - b) / max(abs(a), abs(b), 1e-2 if kind != "u8" else 1e-300)
+                assert r["pool_margin"][qi] == pytest.approx(gap, rel=1e-12, abs=0)
+            else:
+                assert np.isinf(r["pool_margin"][qi])
+
+
+def test_search_pool_unbounded_is_bruteforce_over_reachable():
+    """eps = inf, e_p = inf: every reachable node is computed, so the pool is
+    the brute-force pool_k nearest of the reachable set."""
+    cfg, x, q, bv, qv, metric, po, pn, seeds = _small_problem("u8", 5, n=500, nq=8)
+    r = orc.search(bv, po, pn, qv, seeds, 3, np.inf, orc.INF_EP, pool_k=30)
+    for qi in range(8):
+        reach = np.array(sorted(_bfs(po, pn, seeds[qi])), dtype=np.int32)
+        ids, _ = orc.topk(orc.Vectors.from_array(q[qi:qi + 1], orc.L2SQ), bv, 30, cand=reach)
+        assert r["pool_ids"][qi].tolist() == ids[0].tolist()
+
+
+def test_two_phase_features_hand_traced():
+    """The 14 raw features after one unlimited expansion on the six-point
+    path graph, traced by hand (golden/features_path_graph.json), and their
+    transformed values."""
+    g = _gold("search_path_graph.json")
+    f = _gold("features_path_graph.json")
+    x = np.array(g["x"], dtype=np.uint8)[:, None]
+    q = np.array([[g["q"]]], dtype=np.uint8)
+    off = np.cumsum([0] + [len(a) for a in g["adj"]])
+    nb = np.array([t for a in g["adj"] for t in a], dtype=np.int32)
+    bv, qv = orc.Vectors.from_array(x, orc.L2SQ), orc.Vectors.from_array(q, orc.L2SQ)
+    r = orc.search(bv, off, nb, qv, np.array([f["seeds"]], np.int32), f["k"], 0.0,
+                   eps1=np.inf, ep1=orc.INF_EP, probe_hops=f["probe_hops"], want_features=True)
+    assert r["feat"][0].tolist() == f["raw"]
+    assert np.allclose(orc.feature_transform(r["feat"], orc.L2SQ)[0], f["transformed"],
+                       rtol=0, atol=1e-12)
+    # stopping at the switch reports the same state, after one expansion
+    p = orc.search(bv, off, nb, qv, np.array([f["seeds"]], np.int32), f["k"], 0.0,
+                   eps1=np.inf, ep1=orc.INF_EP, probe_hops=f["probe_hops"], want_features=True,
+                   probe_only=True)
+    assert p["feat"][0].tolist() == f["raw"]
+    assert p["dc"][0] == f["raw"][13] and p["hops"][0] == f["probe_hops"]
+    assert p["ids"][0].tolist() == [4, 5]
+
+
+def _hand_predictor(mode):
+    g = _gold("predictor_hand.json")
+    F, H = orc.NFEAT, 2
+    W1 = np.zeros((H, F))
+    for i, j, v in g["w1_nonzero"]:
+        W1[i, j] = v
+    w2 = np.array(g[mode]["w2"])
+    bits = lambda a: (np.asarray(a, np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    mean, std = np.zeros(F, np.float32), np.ones(F, np.float32)
+    mean[8], std[8] = g["mean8"], g["std8"]
+    feat = np.ones((2, F))
+    feat[:, 8] = g["raw_feature_8"]
+    return g, feat, bits(W1), np.array(g["b1"]), bits(w2), np.zeros(len(w2)), mean, std
+
+
+def test_predictor_curve_hand_example():
+    g, feat, w1, b1, w2, b2, mean, std = _hand_predictor("curve")
+    c = g["curve"]
+    p = orc.predict(feat, orc.L2SQ, w1, b1, w2, b2, mean, std, "curve", eps_cand=c["eps_cand"],
+                    lam_per_query=c["lambda"], e0=30.0, we=20.0)
+    assert np.allclose(p["eps"], np.float32(c["eps"]), rtol=0, atol=0)
+    assert p["ep"].tolist() == c["ep"]
+    assert np.allclose(p["cost"], c["cost"], rtol=1e-12)
+    assert np.allclose(p["margin"], c["margin"], rtol=1e-12)
+    # a transform that took log instead of log(1 + n) for |S| moves the hidden unit
+    bad = feat.copy()
+    bad[:, 8] = math.e ** 2
+    assert not np.allclose(orc.predict(bad, orc.L2SQ, w1, b1, w2, b2, mean, std, "curve",
+                                       eps_cand=c["eps_cand"], lam_per_query=c["lambda"])["cost"],
+                           c["cost"], rtol=1e-6)
+
+
+def test_predictor_log_eps_hand_example():
+    g, feat, w1, b1, w2, b2, mean, std = _hand_predictor("log_eps")
+    c = g["log_eps"]
+    p = orc.predict(feat, orc.L2SQ, w1, b1, w2, b2, mean, std, "log_eps", head_per_query=c["head"],
+                    shift=c["shift"], eps_max=c["eps_max"], e0=30.0, we=20.0)
+    # the clamp bounds are f32 fields: the clamped value is fp32(eps_max)
+    want = [c["eps"][0], float(np.float32(c["eps_max"]))]
+    assert np.allclose(p["eps"], want, rtol=1e-12)
+    assert p["ep"].tolist() == c["ep"]
+    assert np.allclose(p["cost"], p["eps"], rtol=0)
