@@ -39,7 +39,7 @@ def log(*a):
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "search_kernel_c3_counters.txt")
-KERNEL_SOURCES = ["search.hip", "search_args.h", "wave.h", "dist.h", "onng_internal.h"]
+KERNEL_SOURCES = ["search.hip", "search_args.h", "pred_inputs.h", "wave.h", "dist.h", "onng_internal.h"]
 
 
 def kernel_source_hash() -> str:

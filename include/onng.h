@@ -382,6 +382,13 @@ typedef struct {
      * pass, longest-first ordering and the search (three steps); 1 = one
      * search with the predictor fused after the probe expansions. */
     int32_t single_pass;
+    /* Workspace reuse.  Every onng_search leaves the visited bitsets of its
+     * workspace all zero and records the layout they belong to in the
+     * workspace.  ws_reuse = 1 vouches that nothing but onng_search calls has
+     * written `ws` since the last onng_search on it: when the recorded layout
+     * is this call's, the bitsets are trusted and not zeroed again.  0 (or a
+     * fresh workspace): they are zeroed first (N/8 bytes per wave slot). */
+    int32_t ws_reuse;
 } onng_search_params;
 
 /* Per-query statistics written by onng_search. */
@@ -412,7 +419,9 @@ typedef struct onng_query_stats_s {
  * rerank), ascending, padded with -1 / INT32_MAX or +inf; stats [nq].
  * With range factor f = (1+eps)^2 for ONNG_L2SQ and 1+eps for ONNG_COSINE
  * (rounded to f32), a node is pushed to the candidate set when
- * d <= f32(r * f) and the search stops when the nearest candidate is beyond it. */
+ * d <= f32(r * f) and the search stops when the nearest candidate is beyond it.
+ * An adjacency list may repeat an id: only its first copy is visited (the
+ * later ones still count towards e_p), as with Algorithm 1's visited set. */
 onng_status onng_search(const onng_vectors *base, const onng_graph *graph,
                         const onng_vectors *queries, const int32_t *seeds, int32_t n_seeds,
                         const onng_search_params *params, int32_t *ids, void *dists,
@@ -536,7 +545,8 @@ onng_status onng_autotune_search(const onng_vectors *base, const onng_graph *gra
  * order), or as one fused search when params->single_pass is set.  The
  * launch shape is params->launch, else the one onng_autotune_search cached
  * for this index and parameters, else the default.  All pointers must stay
- * valid while the handle lives. */
+ * valid while the handle lives, and `ws` belongs to the pipeline meanwhile:
+ * its replays keep search state in it (params->ws_reuse is ignored). */
 typedef struct onng_pipeline onng_pipeline;
 onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *graph,
                                  const onng_vectors *queries, const int32_t *pivots,

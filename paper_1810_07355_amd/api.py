@@ -332,7 +332,7 @@ class SearchRequest:
             C.cast(rerank_base.ref, C.c_void_p) if rerank_base else None,
             int(pool_factor), C.cast(C.byref(launch), C.c_void_p) if launch is not None else None,
             int(probe_hops), int(predict_only), _ptr(range_from), _ptr(order), int(max_dc),
-            _ptr(mdq), float(max_dc_factor), _ptr(id_map), int(single_pass))
+            _ptr(mdq), float(max_dc_factor), _ptr(id_map), int(single_pass), 0)
         self._keep += [range_from, order, id_map]
         self.gs = graph.struct()
         out_dt = torch.float32 if rerank_base is not None else base.dist_dtype
@@ -359,6 +359,8 @@ class SearchRequest:
                self.seeds.data_ptr(), self.seeds.shape[1], C.byref(self.params),
                self.ids.data_ptr(), self.dists.data_ptr(), self.stats.data_ptr(),
                self.ws.data_ptr(), self.ws.numel(), _stream())
+        # the workspace is this request's: later runs reuse its zeroed bitsets
+        self.params.ws_reuse = 1
         return self
 
     def autotune(self):
@@ -372,6 +374,7 @@ class SearchRequest:
                                                             C.byref(self.params))
         if self.ws_bytes > self.ws.numel():
             self.ws = _workspace(self.ws_bytes, self.ws.device)
+            self.params.ws_reuse = 0
         return best
 
     @property

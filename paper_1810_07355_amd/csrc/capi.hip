@@ -235,7 +235,8 @@ static onng_status make_plan(const onng_vectors *base, int64_t nq, const onng_se
     int need = (int)std::min<int64_t>((nq + P.wpb - 1) / P.wpb, 1 << 20);
     P.blocks = std::max(1, std::min(want, std::max(need, 1)));
     P.slots = P.blocks * P.wpb;
-    P.gbits_words = (base->n + 31) / 32;
+    // a slot's bitset starts on a 128-byte line
+    P.gbits_words = ((base->n + 31) / 32 + 31) / 32 * 32;
     Carver c(nullptr);
     c.take<int32_t>(64);
     c.take<uint32_t>((size_t)P.slots * P.gbits_words);
@@ -300,11 +301,24 @@ static onng_status validate_search(const onng_vectors *base, const onng_graph *g
     return ONNG_OK;
 }
 
+// Tag of a workspace layout (slot count and per-slot region sizes); never 0.
+static uint64_t search_ws_tag(const SearchPlan &P) {
+    uint64_t h = 0x6f6e6e6773656172ull;
+    for (uint64_t v : {(uint64_t)P.slots, (uint64_t)P.gbits_words, (uint64_t)P.vlog_cap,
+                       (uint64_t)P.spill_cap}) {
+        h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+        h *= 0xbf58476d1ce4e5b9ull;
+    }
+    return h | 1ull;
+}
+
+// reuse_override: -1 takes params->ws_reuse, 0/1 force it (the static
+// scratch is only ever written by searches).
 static onng_status run_search(const onng_vectors *base, const onng_graph *g,
                               const onng_vectors *queries, const int32_t *seeds, int32_t n_seeds,
                               const onng_search_params *p, int32_t *ids, void *dists,
                               onng_query_stats *stats, void *ws, size_t ws_bytes, hipStream_t st,
-                              const onng_launch_config *cfg) {
+                              const onng_launch_config *cfg, int reuse_override = -1) {
     ONNG_TRY(validate_search(base, g, queries, seeds, n_seeds, p));
     ONNG_CHECK_ARG(ids && dists && stats, "outputs are null");
     if (queries->n == 0) return ONNG_OK;
@@ -318,6 +332,9 @@ static onng_status run_search(const onng_vectors *base, const onng_graph *g,
     Carver c(ws);
     SearchKArgs a{};
     a.counter = c.take<int32_t>(64);
+    a.ws_tag_at = reinterpret_cast<uint64_t *>(a.counter + 2);
+    a.ws_tag = search_ws_tag(P);
+    a.ws_reuse = reuse_override >= 0 ? reuse_override : p->ws_reuse;
     a.gbits = c.take<uint32_t>((size_t)P.slots * P.gbits_words);
     a.vlog = c.take<int32_t>((size_t)P.slots * P.vlog_cap);
     a.spill = c.take<uint64_t>((size_t)P.slots * 2 * P.spill_cap);
@@ -893,7 +910,7 @@ onng_status onng_search_static(const onng_vectors *base, const onng_graph *graph
         return ONNG_ERR_CAPACITY;
     }
     return run_search(base, graph, queries, seeds, n_seeds, params, ids, dists, stats, ws, cap,
-                      as_stream(stream), &c);
+                      as_stream(stream), &c, 1);
 }
 
 size_t onng_order_by_cost_workspace_size(int64_t n) { return n < 0 ? 0 : order_ws(n); }
@@ -940,13 +957,14 @@ onng_status onng_autotune_search(const onng_vectors *base, const onng_graph *gra
         if (make_plan(base, queries->n, params, &c, &P) != ONNG_OK) continue;
         if (P.ws > ws_bytes) continue;
         // warm-up, then two timed runs
+        // the warm-up zeroes the bitsets of this shape; the timed runs reuse them
         if (run_search(base, graph, queries, seeds, n_seeds, params, ids, dists, stats, ws,
-                       ws_bytes, st, &c) != ONNG_OK)
+                       ws_bytes, st, &c, 0) != ONNG_OK)
             continue;
         ONNG_HIP(hipEventRecord(e0, st));
         for (int r = 0; r < 2; r++)
             run_search(base, graph, queries, seeds, n_seeds, params, ids, dists, stats, ws,
-                       ws_bytes, st, &c);
+                       ws_bytes, st, &c, 1);
         ONNG_HIP(hipEventRecord(e1, st));
         ONNG_HIP(hipEventSynchronize(e1));
         float ms = 0.0f;
@@ -1202,6 +1220,27 @@ onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *gra
     // seed distances are not needed: write them into the search outputs,
     // which the search overwrites afterwards
     void *seed_d = dists;
+    // The captured searches trust the visited bitsets their last replay left
+    // zero; the tag of the search workspace is cleared now (outside the
+    // graph), so the first replay zeroes them.
+    size_t pre_used = 0;
+    if (params->predictor && !params->single_pass) {
+        Carver c0(nullptr);
+        c0.take<onng_query_stats>(queries->n);
+        c0.take<int32_t>(queries->n);
+        c0.take<char>(order_ws(queries->n));
+        pre_used = (c0.size() + 255) / 256 * 256;
+    }
+    {
+        void *targs[] = {nullptr};
+        uint64_t *tag_at = reinterpret_cast<uint64_t *>(wsa + a + pre_used) + 1;
+        targs[0] = &tag_at;
+        if (hipLaunchKernel(clear_tag_kernel_ptr(), dim3(1), dim3(1), targs, 0, st) != hipSuccess) {
+            if (own) (void)hipStreamDestroy(st);
+            set_error("onng_pipeline_create: launch failed");
+            return ONNG_ERR_DEVICE;
+        }
+    }
     // the launch shape: the caller's, else a tuned one for this index, else the default
     onng_launch_config tuned;
     const onng_launch_config *cfg = params->launch;
@@ -1223,7 +1262,7 @@ onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *gra
                          st);
     if (rc == ONNG_OK && (!params->predictor || params->single_pass)) {
         rc = run_search(base, graph, queries, seeds, n_seeds, params, ids, dists, stats, wsa + a,
-                        ws_bytes - a, st, cfg);
+                        ws_bytes - a, st, cfg, 1);
     } else if (rc == ONNG_OK) {
         // predict the range of every query, order the queries by predicted
         // cost (longest first), then search with the predicted ranges
@@ -1232,7 +1271,7 @@ onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *gra
         int32_t *order = c.take<int32_t>(queries->n);
         size_t ob = order_ws(queries->n);
         void *ows = c.take<char>(ob);
-        size_t used = (c.size() + 255) / 256 * 256;
+        size_t used = (c.size() + 255) / 256 * 256;   // == pre_used
         onng_search_params p1 = *params;
         p1.predict_only = 1;
         p1.features_out = nullptr;
@@ -1244,11 +1283,11 @@ onng_status onng_pipeline_create(const onng_vectors *base, const onng_graph *gra
         p2.range_from = pst;
         p2.order = order;
         rc = run_search(base, graph, queries, seeds, n_seeds, &p1, ids, dists, pst,
-                        wsa + a + used, ws_bytes - a - used, st, cfg);
+                        wsa + a + used, ws_bytes - a - used, st, cfg, 1);
         if (rc == ONNG_OK) rc = order_launch(pst, queries->n, order, ows, ob, st);
         if (rc == ONNG_OK)
             rc = run_search(base, graph, queries, seeds, n_seeds, &p2, ids, dists, stats,
-                            wsa + a + used, ws_bytes - a - used, st, cfg);
+                            wsa + a + used, ws_bytes - a - used, st, cfg, 1);
     }
     hipGraph_t g = nullptr;
     hipError_t ce = hipStreamEndCapture(st, &g);

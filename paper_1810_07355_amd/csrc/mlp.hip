@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 
+#include "pred_inputs.h"
 #include "onng_internal.h"
 
 namespace onng {
@@ -113,19 +114,13 @@ __global__ void adam_kernel(float *p, const float *g, float *m, float *v, int64_
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// same transform as the search kernel applies before z-scoring
+// the transform the fused predictor of the search applies before z-scoring
 __global__ void feature_transform_kernel(const float *raw, int64_t n, int metric, float *out) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     const float *f = raw + r * ONNG_NFEAT;
     float *x = out + r * ONNG_NFEAT;
-    const float c = metric == ONNG_COSINE ? 1e-3f : 1.0f;
-    float lg0 = logf(fmaxf(f[0], 0.0f) + c);
-    x[0] = lg0;
-    for (int t = 1; t < 8; t++) x[t] = logf(fmaxf(f[t], 0.0f) + c) - lg0;
-    x[8] = log1pf(f[8]);
-    for (int t = 9; t < 13; t++) x[t] = logf(fmaxf(f[t], 0.0f) + c) - lg0;
-    x[13] = log1pf(f[13]);
+    for (int t = 0; t < ONNG_NFEAT; t++) x[t] = feature_input(t, f[t], f[0], metric);
 }
 
 }  // namespace

@@ -14,8 +14,10 @@
 //   vis    the visited set C, on chip for a window of consecutive ids around
 //          the first seed (one bit per id; the rows are in locality order, so
 //          much of a query's neighbourhood falls in it), and a per-slot
-//          global bitset (atomic OR) for the other ids, whose set words are
-//          cleared after the query.
+//          global bitset (atomic OR) for the other ids.  A query logs every
+//          word it turns non-zero and clears those words when it ends, so
+//          the bitset is all zero between queries; it is zeroed as a whole
+//          only when the workspace's tag says its state is unknown.
 //
 // One expansion (pop of s, scan of its first e_p edges) is processed as one
 // batch: the unvisited neighbours are marked, their distances computed by the
@@ -201,9 +203,18 @@ search_kernel(SearchKArgs a) {
     uint32_t *gbits = a.gbits + (size_t)slot * a.gbits_words;
     int32_t *vlog = a.vlog + (size_t)slot * a.vlog_cap;
     uint64_t *spill0 = a.spill + (size_t)slot * 2 * a.spill_cap;
-    // this slot's bitset is all zero at the start of every query once it has
-    // been cleared in this launch (each query clears the words it set)
-    bool gready = false;
+    // Every launch leaves each slot's bitset all zero (queries clear the words
+    // they set).  The workspace tag, written by the last wave of a launch,
+    // records the layout that state belongs to; when the caller does not vouch
+    // for the workspace or the tag differs, each slot zeroes its bitset first.
+    const bool ws_known =
+        a.ws_reuse && __hip_atomic_load(a.ws_tag_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                          a.ws_tag;
+    if (!ws_known) {
+        u32x4 *g4 = reinterpret_cast<u32x4 *>(gbits);
+        for (int64_t i = lane; i < a.gbits_words / 4; i += WAVE) g4[i] = u32x4{0, 0, 0, 0};
+        __threadfence();
+    }
 
     const int L = a.lanes_per_row;
     const int p = lane & (L - 1);
@@ -258,8 +269,7 @@ search_kernel(SearchKArgs a) {
         int head = 0, size = 0;
         int spill_n = 0, spill_sel = 0;
         uint64_t spill_min = KEY_MAX;
-        bool qglobal = false;   // this query set bits of the global bitset
-        int log_n = 0;
+        int log_n = 0;          // words of the global bitset this query made non-zero
         int dc = 0, hops = 0;
         int scanned = 0;   // adjacency entries read (sum of min(deg, e_p) over expansions)
         int flags = 0;
@@ -270,7 +280,9 @@ search_kernel(SearchKArgs a) {
         uint32_t spec_id = NO_SPEC;
         int64_t spec_e0 = 0, spec_deg = 0;
         uint32_t spec_nb = 0, spec_nb1 = 0;
-        bool spec_vis = false, spec_bit = false, spec_bit1 = false;
+        bool spec_vis = false;
+        // per guessed id, read ahead: its visited bit, and whether its bitset word was zero
+        bool spec_bit = false, spec_bit1 = false, spec_wz = false, spec_wz1 = false;
 
         // the on-chip window: W ids around the first seed, within [0, n)
         uint32_t w0 = 0;
@@ -286,42 +298,86 @@ search_kernel(SearchKArgs a) {
 
         // -------------------------------------------------- helpers ------
         // Mark a batch of ids visited; returns whether this lane's id is new.
-        // known_ok: in global mode the caller already read the bit (known_bit)
-        auto visit = [&](bool valid, uint32_t id, bool known_ok = false,
-                         bool known_bit = false) -> bool {
+        // known_ok: the caller read this id's bitset word after every earlier
+        // mark of the query (known_bit: the id's bit, known_zero: the whole
+        // word was zero); the mark then needs no reply, and *from_known tells
+        // the caller the answer came from that word (an id repeated in one
+        // list looks new in each copy: see dedupe_known).
+        auto visit = [&](bool valid, uint32_t id, bool known_ok = false, bool known_bit = false,
+                         bool known_zero = false, bool *from_known = nullptr) -> bool {
             const uint32_t off = id - w0;   // wraps below the window
             const bool inw = valid && off < W;
             const bool outw = valid && !inw;
-            if (!gready && ballot(outw)) {
-                // first global mark of this slot in this launch
-                for (int64_t i = lane; i < a.gbits_words; i += WAVE) gbits[i] = 0u;
-                __threadfence_block();
-                gready = true;
-                wave_sync();
-            }
-            bool isnew = false;
+            bool isnew = false, first = false;
             if (inw) {
                 const uint32_t bit = 1u << (off & 31);
                 isnew = (atomicOr(&lds.vis[off >> 5], bit) & bit) == 0u;
             } else if (outw) {
                 const uint32_t bit = 1u << (id & 31);
                 if (known_ok) {
-                    // ids of one adjacency list are distinct, so the bits read
-                    // before this expansion decide; the marks need no reply
                     isnew = !known_bit;
+                    first = known_zero;
                     if (isnew)
                         __hip_atomic_fetch_or(&gbits[id >> 5], bit, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
+                    if (from_known) *from_known = isnew;
                 } else {
-                    isnew = (atomicOr(&gbits[id >> 5], bit) & bit) == 0u;
+                    const uint32_t old = atomicOr(&gbits[id >> 5], bit);
+                    isnew = (old & bit) == 0u;
+                    first = old == 0u;
                 }
             }
-            const bool logged = isnew && outw;
+            // log each word when this query turns it non-zero
+            const bool logged = isnew && first;
             const uint64_t m = ballot(logged);
-            if (logged && log_n + mbcnt(m) < a.vlog_cap) vlog[log_n + mbcnt(m)] = (int32_t)id;
+            if (logged && log_n + mbcnt(m) < a.vlog_cap) vlog[log_n + mbcnt(m)] = (int32_t)(id >> 5);
             log_n += __popcll(m);
-            if (m) qglobal = true;
             return isnew;
+        };
+
+        // Ids of chunk 0 and chunk 1 of a guessed expansion that were found new
+        // from words read before it (k0/k1 set) are new in every copy when the
+        // list repeats an id.  Keep the first copy in list order (chunk 0
+        // before chunk 1, lower lane first), as Algorithm 1's visited set does:
+        // a bitmap of 8192 id hashes in LDS finds the lanes whose hash was
+        // already taken, and only for those the wave compares ids exactly.
+        // The bitmap lives in the distance-key buffer, unused until the batch.
+        auto dedupe_known = [&](uint32_t id0, bool &n0, bool k0, uint32_t id1, bool &n1,
+                                bool k1) {
+            uint32_t *bm = reinterpret_cast<uint32_t *>(kbuf);   // 1 KiB
+            reinterpret_cast<u32x4 *>(bm)[lane] = u32x4{0, 0, 0, 0};
+            wave_sync();
+            bool c0 = false, c1 = false;
+            if (k0) {
+                const uint32_t h = id0 & 8191u, b = 1u << (h & 31);
+                c0 = (atomicOr(&bm[h >> 5], b) & b) != 0u;
+            }
+            if (k1) {
+                const uint32_t h = id1 & 8191u, b = 1u << (h & 31);
+                c1 = (atomicOr(&bm[h >> 5], b) & b) != 0u;
+            }
+            uint64_t cm0 = ballot(c0), cm1 = ballot(c1);
+            uint64_t drop0 = 0, drop1 = 0;
+            while (cm0 | cm1) {
+                uint32_t cid;
+                if (cm0) {
+                    const int src = (int)__builtin_ctzll(cm0);
+                    cm0 &= cm0 - 1;
+                    cid = (uint32_t)__builtin_amdgcn_readlane((int)id0, src);
+                } else {
+                    const int src = (int)__builtin_ctzll(cm1);
+                    cm1 &= cm1 - 1;
+                    cid = (uint32_t)__builtin_amdgcn_readlane((int)id1, src);
+                }
+                uint64_t e0 = ballot(k0 && id0 == cid), e1 = ballot(k1 && id1 == cid);
+                if (e0) e0 &= e0 - 1;   // the first copy stays new
+                else e1 &= e1 - 1;
+                drop0 |= e0;
+                drop1 |= e1;
+            }
+            n0 = n0 && !((drop0 >> lane) & 1u);
+            n1 = n1 && !((drop1 >> lane) & 1u);
+            wave_sync();
         };
 
         // Distances of rows lds.ids[0..u) -> kbuf[i] as keys (u <= 128).  A lane
@@ -564,20 +620,37 @@ search_kernel(SearchKArgs a) {
             // marks of the group, then one distance batch for its new nodes.
             for (int64_t g0 = 0; g0 < np; g0 += 2 * WAVE) {
                 int u = 0;
-#pragma unroll
-                for (int cc = 0; cc < 2; cc++) {
-                    const int64_t c0 = g0 + cc * WAVE;
-                    if (c0 >= np) break;
-                    const int64_t j = c0 + lane;
-                    const bool pre = hit && g0 == 0;
-                    uint32_t id;
-                    if (pre) id = j < np ? (cc == 0 ? spec_nb : spec_nb1) : 0u;
-                    else id = j < np ? (uint32_t)a.nbrs[e0 + j] : 0u;
-                    bool valid = j < np && (int64_t)id < a.n_base;
-                    bool isnew = visit(valid, id, pre && spec_vis, cc == 0 ? spec_bit : spec_bit1);
-                    uint64_t m = ballot(isnew);
-                    if (isnew) lds.ids[u + mbcnt(m)] = id;
+                const bool pre = hit && g0 == 0;
+                if (pre && spec_vis) {
+                    // both chunks read ahead, with their visited words
+                    const bool v0 = lane < np && (int64_t)spec_nb < a.n_base;
+                    const bool v1 = WAVE + lane < np && (int64_t)spec_nb1 < a.n_base;
+                    bool k0 = false, k1 = false;
+                    bool n0 = visit(v0, spec_nb, true, spec_bit, spec_wz, &k0);
+                    bool n1 = false;
+                    if (WAVE < np) n1 = visit(v1, spec_nb1, true, spec_bit1, spec_wz1, &k1);
+                    dedupe_known(spec_nb, n0, k0, spec_nb1, n1, k1);
+                    uint64_t m = ballot(n0);
+                    if (n0) lds.ids[mbcnt(m)] = spec_nb;
+                    u = __popcll(m);
+                    m = ballot(n1);
+                    if (n1) lds.ids[u + mbcnt(m)] = spec_nb1;
                     u += __popcll(m);
+                } else {
+#pragma unroll
+                    for (int cc = 0; cc < 2; cc++) {
+                        const int64_t c0 = g0 + cc * WAVE;
+                        if (c0 >= np) break;
+                        const int64_t j = c0 + lane;
+                        uint32_t id;
+                        if (pre) id = j < np ? (cc == 0 ? spec_nb : spec_nb1) : 0u;
+                        else id = j < np ? (uint32_t)a.nbrs[e0 + j] : 0u;
+                        bool valid = j < np && (int64_t)id < a.n_base;
+                        bool isnew = visit(valid, id);
+                        uint64_t m = ballot(isnew);
+                        if (isnew) lds.ids[u + mbcnt(m)] = id;
+                        u += __popcll(m);
+                    }
                 }
                 if (u == 0) continue;
                 wave_sync();
@@ -643,24 +716,23 @@ search_kernel(SearchKArgs a) {
                     spec_nb1 = lane < nl1 ? (uint32_t)a.nbrs[spec_e0 + WAVE + lane] : 0u;
                 }
                 if (na > 0) absorb_s(k0, na, true);
-                spec_vis = go && gready;
+                spec_vis = go;
                 if (spec_vis) {
                     // the marks of this expansion are complete before the
-                    // visited bits of the guess are read (those outside the
+                    // visited words of the guess are read (those outside the
                     // window: the others are on chip)
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    spec_bit = false;
-                    spec_bit1 = false;
-                    if (lane < nl0 && (int64_t)spec_nb < a.n_base && spec_nb - w0 >= W) {
-                        uint32_t wd = __hip_atomic_load(&gbits[spec_nb >> 5], __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
-                        spec_bit = (wd >> (spec_nb & 31)) & 1u;
-                    }
-                    if (lane < nl1 && (int64_t)spec_nb1 < a.n_base && spec_nb1 - w0 >= W) {
-                        uint32_t wd = __hip_atomic_load(&gbits[spec_nb1 >> 5], __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
-                        spec_bit1 = (wd >> (spec_nb1 & 31)) & 1u;
-                    }
+                    uint32_t wd = 0u, wd1 = 0u;
+                    if (lane < nl0 && (int64_t)spec_nb < a.n_base && spec_nb - w0 >= W)
+                        wd = __hip_atomic_load(&gbits[spec_nb >> 5], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                    if (lane < nl1 && (int64_t)spec_nb1 < a.n_base && spec_nb1 - w0 >= W)
+                        wd1 = __hip_atomic_load(&gbits[spec_nb1 >> 5], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+                    spec_bit = (wd >> (spec_nb & 31)) & 1u;
+                    spec_bit1 = (wd1 >> (spec_nb1 & 31)) & 1u;
+                    spec_wz = wd == 0u;
+                    spec_wz1 = wd1 == 0u;
                 }
                 if (nb2 > 0) {
                     k1 = wave_sort(k1, pow2_at_least(nb2));
@@ -789,16 +861,26 @@ search_kernel(SearchKArgs a) {
         }
 
         // leave the global visited bitset clean for the next query
-        if (qglobal) {
+        if (log_n > 0) {
             __threadfence_block();   // the log was written by other lanes
             if (log_n <= a.vlog_cap) {
-                for (int i = lane; i < log_n; i += WAVE) gbits[(uint32_t)vlog[i] >> 5] = 0u;
+                for (int i = lane; i < log_n; i += WAVE) gbits[(uint32_t)vlog[i]] = 0u;
             } else {
-                for (int64_t i = lane; i < a.gbits_words; i += WAVE) gbits[i] = 0u;
+                u32x4 *g4 = reinterpret_cast<u32x4 *>(gbits);
+                for (int64_t i = lane; i < a.gbits_words / 4; i += WAVE) g4[i] = u32x4{0, 0, 0, 0};
             }
             __threadfence_block();
         }
         wave_sync();
+    }
+
+    // The last wave of the launch records the layout whose bitsets are now
+    // all zero.
+    if (lane == 0) {
+        __threadfence();
+        const int total = (int)gridDim.x * a.waves_per_block;
+        if (atomicAdd(a.counter + 1, 1) == total - 1)
+            __hip_atomic_store(a.ws_tag_at, a.ws_tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -817,7 +899,11 @@ ONNG_SEARCH_INST(ONNG_BF16, ONNG_COSINE)
 ONNG_SEARCH_INST(ONNG_FP8_E4M3, ONNG_L2SQ)
 ONNG_SEARCH_INST(ONNG_FP8_E4M3, ONNG_COSINE)
 
-__global__ void reset_counter_kernel(int32_t *c) { *c = 0; }
+// work ticket (c[0]) and finished-wave count (c[1]) of a search launch
+__global__ void reset_counter_kernel(int32_t *c) {
+    c[0] = 0;
+    c[1] = 0;
+}
 
 const void *search_kernel_ptr(int dtype, int metric) {
     switch (dtype) {
@@ -838,6 +924,10 @@ const void *search_kernel_ptr(int dtype, int metric) {
     return nullptr;
 }
 
+// forget the workspace tag, so that the next launch zeroes the bitsets
+__global__ void clear_tag_kernel(uint64_t *tag) { *tag = 0; }
+
 const void *reset_counter_kernel_ptr() { return (const void *)reset_counter_kernel; }
+const void *clear_tag_kernel_ptr() { return (const void *)clear_tag_kernel; }
 
 }  // namespace onng

@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "../../include/onng.h"
+#include "pred_inputs.h"
 
 namespace onng {
 
@@ -79,9 +80,12 @@ struct SearchKArgs {
     void *out_d;
     onng_query_stats *stats;
     // scheduling and scratch
-    int32_t *counter;
+    int32_t *counter;       // [0] work ticket, [1] waves finished
+    uint64_t *ws_tag_at;    // tag of the workspace layout whose bitsets are all zero
+    uint64_t ws_tag;        // this launch's layout
+    int32_t ws_reuse;       // caller vouches that only searches wrote the workspace
     uint32_t *gbits;
-    int64_t gbits_words;    // per slot
+    int64_t gbits_words;    // per slot, a multiple of 32
     int32_t *vlog;
     int32_t vlog_cap;       // per slot
     uint64_t *spill;
@@ -105,13 +109,8 @@ struct SearchKArgs {
 // per lane, the heads one per lane.  All lanes return the same value.
 __device__ inline float predict_eps(const PredArgs &P, float fv, int metric, int qi, int lane,
                                     float *scratch, float *cost) {
-    const float c = metric == ONNG_COSINE ? 1e-3f : 1.0f;
-    float lg = logf(fmaxf(fv, 0.0f) + c);
-    float lg0 = __shfl(lg, 0);
-    float x;
-    if (lane == 0) x = lg;
-    else if (lane == 8 || lane == 13) x = log1pf(fv);
-    else x = lg - lg0;
+    const float f0 = __shfl(fv, 0);
+    const float x = feature_input(lane, fv, f0, metric);
     float *z = scratch;          // [16]
     float *hid = scratch + 16;   // [64]
     float *yv = scratch + 80;    // [16]
@@ -161,13 +160,14 @@ __device__ inline float predict_eps(const PredArgs &P, float fv, int metric, int
     } else {
         const int head = P.head_pq ? P.head_pq[qi] : P.head;
         float yh = yv[head] + (P.shift ? P.shift[head] : 0.0f);
-        eps = exp10f(yh) - 0.01f;
-        *cost = eps;
+        eps = fminf(fmaxf(exp10f(yh) - 0.01f, P.eps_min), P.eps_max);
+        *cost = eps;   // the range itself
     }
     return fminf(fmaxf(eps, P.eps_min), P.eps_max);
 }
 
 const void *search_kernel_ptr(int dtype, int metric);
 const void *reset_counter_kernel_ptr();
+const void *clear_tag_kernel_ptr();
 
 }  // namespace onng

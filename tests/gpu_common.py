@@ -85,3 +85,35 @@ def margin_ok(ref, gpu_ids, gpu_d, margin, tol=1e-4):
                 return False, int(qi)
             differ += 1
     return True, differ
+
+
+def random_predictor(T, mode, g, feat, b2, metric, H=64, **kw):
+    """A predictor with random bf16 weights whose inputs are z-scored with the
+    statistics of `feat` (oracle features of the same queries), so that its
+    choices spread.  Returns (api.Predictor, dict of the host arrays the
+    oracle's predict() takes)."""
+    A = api()
+    x = orc.feature_transform(feat, metric)
+    w1 = torch.from_numpy(g.standard_normal((H, orc.NFEAT)).astype(np.float32) * 0.3).to(dev())
+    w2 = torch.from_numpy(g.standard_normal((T, H)).astype(np.float32) * 0.1).to(dev())
+    b1 = np.zeros(H, np.float32)
+    b2 = np.asarray(b2, np.float32)
+    mean = x.mean(0).astype(np.float32)
+    std = (x.std(0) + 1e-3).astype(np.float32)
+    w1b, w2b = A.to_bf16_bits(w1), A.to_bf16_bits(w2)
+    pred = A.Predictor(w1b, to_dev(b1), w2b, to_dev(b2), to_dev(mean), to_dev(std), mode=mode,
+                       **kw)
+    host_w = dict(w1_bits=host(w1b).view(np.uint16), b1=b1, w2_bits=host(w2b).view(np.uint16),
+                  b2=b2, mean=mean, std=std)
+    return pred, host_w
+
+
+def fp8_inrow(A, Lb, x_dev, metric, dim):
+    """fp8-e4m3 rows with the scale in each row's last 4 bytes (128-byte
+    pitch), as the benchmark stores them; and the oracle's view of the same
+    codes (exact decode)."""
+    lp = A.encode(x_dev, Lb.FP8_E4M3, Lb.COSINE if metric == orc.COS else Lb.L2SQ,
+                  scale_in_row=True, pitch=A.row_pitch(A.fp8_inrow_pitch(dim), Lb.U8, 128))
+    codes = host(lp.data)
+    scale = np.ascontiguousarray(codes[:, -4:]).view(np.float32).reshape(-1)
+    return lp, orc.Vectors(codes, orc.FP8, metric, dim=dim, scale=scale)

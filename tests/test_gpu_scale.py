@@ -285,6 +285,47 @@ def test_c3_knn_rows_sampled():
             assert abs(dj - kth) <= 1e-5 * max(kth, 1e-2)
 
 
+def test_c3_fp8_inrow_search_and_rerank_sampled():
+    """The headline kernel at full size: fp8 rows with the scale in the row,
+    cosine, at the recall-0.95 range of the benchmark (eps 0.111, dynamic
+    e_p), on 200 sampled queries against the fp64 oracle on the decoded rows
+    (margin rule); with the fused f32 rerank of the 4k best against the
+    oracle's rerank of its own pool."""
+    from gpu_common import fp8_inrow
+    P = c3()
+    A, Lb = api(), L()
+    eps = 0.1113
+    ep = orc.dynamic_ep(eps)
+    qs = _sample(P["cfg"].n_query, N_Q, 8)
+    po, pn = P["pa"]
+    qv = orc.Vectors.from_array(P["q"][qs], orc.COS)
+    lp, lbv = fp8_inrow(A, Lb, P["B"].data, orc.COS, P["x"].shape[1])
+    say("c3: fp8 in-row search, eps", eps)
+    r = A.search(lp, P["pa_graph"], P["Q"], to_dev(P["seeds"]), k=10, eps=eps, ep=ep)
+    rr = A.search(lp, P["pa_graph"], P["Q"], to_dev(P["seeds"]), k=10, eps=eps, ep=ep,
+                  rerank_base=P["B"], pool_factor=4)
+    ref = orc.search(lbv, po, pn, qv, P["seeds"][qs], 10, eps, ep, pool_k=40)
+    gi = host(r.ids)[qs]
+    ok, info = margin_ok(ref, gi, host(r.dists)[qs], ref["margin"])
+    assert ok, f"sampled query {info} differs beyond the margin"
+    assert info <= 0.05 * len(qs), f"{info} sampled queries differ"
+    sure = ref["margin"] >= 1e-4
+    assert np.array_equal(host(r.dc)[qs][sure], ref["dc"][sure])
+    fb = orc.Vectors.from_array(P["x"], orc.COS)
+    rid, rd = orc.rerank(qv, fb, ref["pool_ids"], 11)
+    gap = np.abs(rd[:, 10] - rd[:, 9]) / np.maximum(np.abs(rd[:, 10]), 1e-2)
+    sure = sure & (ref["pool_margin"] >= 1e-4) & (gap >= 1e-4)
+    ri, rdist = host(rr.ids)[qs], host(rr.dists)[qs]
+    same = np.array([set(a.tolist()) == set(b.tolist()) for a, b in zip(ri, rid[:, :10])])
+    say("c3 fp8: queries certain through the rerank:", int(sure.sum()), "of", len(qs),
+        "; same reranked ids:", int(same.sum()))
+    assert sure.sum() >= 10
+    assert np.all(same[sure]), np.flatnonzero(sure & ~same)
+    assert same.mean() >= 0.9
+    for i in np.flatnonzero(same):
+        assert np.all(np.abs(np.sort(rdist[i]) - rd[i, :10]) <= 1e-5 * np.maximum(rd[i, :10], 1e-2))
+
+
 @pytest.mark.parametrize("lp", [None, "f16"])
 def test_c3_search_sampled_margin(lp):
     """Plain f32 search, and f16 rows (the oracle searches the decoded rows)
