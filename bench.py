@@ -51,11 +51,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per launch of the timed search kernel from the committed
+def measured_traffic(workload: str, bytes_per_launch: float):
+    """HBM bytes per launch of the standalone search launch from the committed
     counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's
-    reading), or None when that summary was taken on other kernel sources or
-    on another workload."""
+    reading), or None when that summary was taken on other kernel sources, on
+    another workload or on a launch of other algorithmic bytes (another
+    learned setting)."""
     try:
         with open(COUNTERS) as fh:
             text = fh.read()
@@ -68,6 +69,9 @@ def measured_traffic(workload: str):
     if kv.get("kernel_source_sha256") != kernel_source_hash():
         return None
     try:
+        alg = float(kv["algorithmic_bytes_per_launch"])
+        if abs(alg - bytes_per_launch) > 0.02 * bytes_per_launch:
+            return None
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
@@ -86,9 +90,24 @@ def parse():
     ap.add_argument("--lp", default="fp8", choices=["f16", "bf16", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds-1t", type=float, default=5.0,
+                    help="CPU seconds of the one-thread oracle run")
+    ap.add_argument("--no-dtype-report", action="store_true",
+                    help="skip the f16/bf16/fp8 recall and error report")
+    ap.add_argument("--learned-pick", default=None, metavar="FORM,FACTOR,BUDGET",
+                    help="take this learned setting at 0.95 (e.g. 3-step,2.0,19047) instead of "
+                         "choosing by pipelined timing (profiler runs change the timing)")
+    ap.add_argument("--markers", action="store_true",
+                    help="launch a marker kernel right before and after the timed window "
+                         "(to find it in a profiler trace)")
     ap.add_argument("--dump", default=None, help="save per-query sweep data (.npz)")
     ap.add_argument("--probe-hops", type=int, default=1,
                     help="expansions before the learned range is chosen")
+    ap.add_argument("--summarize-trace", default=None, metavar="DIR",
+                    help="summarise a rocprofv3 kernel trace or counter run of a --markers "
+                         "benchmark: the dispatches of its timed window")
+    ap.add_argument("--probe-kind", default="copy", choices=["copy", "read", "write"],
+                    help="--copy-probe: a plain copy, a read-only sum or a write-only fill")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times and exit (the plain copy "
                          "whose counters calibrate FETCH_SIZE / WRITE_SIZE)")
@@ -128,8 +147,100 @@ def parse():
     return ap.parse_args()
 
 
+SEGMENTS = ["timed window (pipelines in flight)",
+            "standalone search launches (learned, low-precision rows)",
+            "standalone search launches (plain f32 rows)"]
+
+
+def _kernel_short(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return name.split("(")[0]
+
+
+def _trace_segment(win, label, steps):
+    t0 = min(int(r["Start_Timestamp"]) for r in win)
+    t1 = max(int(r["End_Timestamp"]) for r in win)
+    print(f"{label}: {len(win)} dispatches, span {(t1 - t0) / 1e6:.3f} ms, "
+          f"{(t1 - t0) / 1e6 / steps:.4f} ms per step or launch ({steps})")
+    per = {}
+    for r in win:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        per.setdefault(_kernel_short(r["Kernel_Name"]), []).append(d)
+    print(f"  {'kernel':58s} {'count':>6s} {'avg us':>10s} {'min us':>10s} {'max us':>10s} "
+          f"{'sum us/step':>12s}")
+    for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        print(f"  {k[:58]:58s} {len(v):6d} {np.mean(v):10.1f} {np.min(v):10.1f} "
+              f"{np.max(v):10.1f} {sum(v) / steps:12.1f}")
+    # busy time of the search kernel: the union of its dispatch intervals
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in win
+                if "search_kernel" in r["Kernel_Name"])
+    busy, cur_s, cur_e = 0, None, None
+    for a_, b_ in iv:
+        if cur_e is None or a_ > cur_e:
+            if cur_e is not None:
+                busy += cur_e - cur_s
+            cur_s, cur_e = a_, b_
+        else:
+            cur_e = max(cur_e, b_)
+    if cur_e is not None:
+        busy += cur_e - cur_s
+    print(f"  search_kernel busy (union of its dispatch intervals): {busy / 1e6:.3f} ms, "
+          f"{busy / 1e6 / steps:.4f} ms per step or launch")
+
+
+def summarize_trace(path: str, steps: int) -> None:
+    """The measured regions of a --markers run in a rocprofv3 CSV output:
+    the dispatches between consecutive pairs of marker kernels (the timed
+    window, then the two standalone search legs).  Kernel traces give
+    per-kernel dispatch counts and durations and each region's span; counter
+    runs give each counter's sum per region, per step and per dispatch."""
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(path, "**", "*.csv"), recursive=True))
+    trace = [f for f in files if f.endswith("kernel_trace.csv")]
+    ctr = [f for f in files if f.endswith("counter_collection.csv")]
+    if trace:
+        rows = [r for f in trace for r in csv.DictReader(open(f))]
+        rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+        marks = [i for i, r in enumerate(rows) if "spin_kernel" in r["Kernel_Name"]]
+        if len(marks) < 2:
+            raise SystemExit("fewer than two marker kernels in the trace")
+        for seg, (m0, m1) in enumerate(zip(marks[0::2], marks[1::2])):
+            _trace_segment(rows[m0 + 1:m1], SEGMENTS[seg] if seg < len(SEGMENTS) else
+                           f"segment {seg}", steps if seg == 0 else 5)
+    if ctr:
+        rows = [r for f in ctr for r in csv.DictReader(open(f))]
+        disp = {}
+        for r in rows:
+            d = disp.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"]})
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        allids = sorted(disp)
+        marks = [i for i in allids if "spin_kernel" in disp[i]["name"]]
+        if len(marks) < 2:
+            marks = [allids[0] - 1, allids[-1] + 1]
+        for seg, (m0, m1) in enumerate(zip(marks[0::2], marks[1::2])):
+            ids = [i for i in allids if m0 < i < m1]
+            nsteps = steps if seg == 0 else 5
+            print(f"{SEGMENTS[seg] if seg < len(SEGMENTS) else f'segment {seg}'}: {len(ids)} "
+                  f"dispatches ({nsteps} steps or launches)")
+            sums = {}
+            for i in ids:
+                nm = _kernel_short(disp[i]["name"])
+                for c, v in disp[i].items():
+                    if c != "name":
+                        e = sums.setdefault((nm, c), [0, 0.0])
+                        e[0] += 1
+                        e[1] += v
+            for (nm, c), (n_, v) in sorted(sums.items()):
+                print(f"  {nm[:58]:58s} {c:12s} dispatches {n_:5d} sum {v:16.1f} per step "
+                      f"{v / nsteps:14.1f} per dispatch {v / n_:14.1f}")
+
+
 def main():
     args = parse()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.steps)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}). The search would shard "
               "by query (index replicated on every GPU) or by base (each GPU searches its "
@@ -141,12 +252,17 @@ def main():
 
     if args.copy_probe:
         n = args.copy_probe << 20
-        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        src = torch.ones(n // 4, dtype=torch.int32, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(5):
-            dst.copy_(src)
+            if args.probe_kind == "copy":
+                dst.copy_(src)
+            elif args.probe_kind == "read":
+                dst[:1] = src.sum()
+            else:
+                dst.fill_(7)
         torch.cuda.synchronize()
-        log(f"copied {args.copy_probe} MiB 5 times")
+        log(f"{args.probe_kind} probe over {args.copy_probe} MiB, 5 times")
         return
 
     if args.workload == "c5":
@@ -183,7 +299,11 @@ def main():
     # ------------------------------------------------------------ inputs --
     log("generating", cfg.name, cfg.n_base, "x", cfg.dim, cfg.kind)
     x = dg.base(cfg)
-    q = dg.queries(cfg)
+    # NB distinct batches of n_query queries (batch 0 is the workload's query
+    # set): the timed steps rotate them, so no batch in flight repeats
+    # another's queries; every operating point is calibrated on all of them
+    NB = 1 if (args.da_sweep or args.tune_degrees) else max(1, args.inflight)
+    q = np.concatenate([dg.query_batch(cfg, b) for b in range(NB)])
     xt = torch.from_numpy(x).to(dev)
     qt = torch.from_numpy(q).to(dev)
     base = A.Vectors.from_tensor(xt, metric)
@@ -287,9 +407,20 @@ def main():
     gt = to_orig(gt_ids).cpu().numpy()
 
     # ------------------------------------------- operating points (recall) --
-    def time_req(req, reps=3):
+    def mark():
+        """A marker kernel that delimits a measured region in a profiler trace."""
+        if args.markers:
+            torch.cuda.synchronize()
+            torch.cuda._sleep(2000)
+            torch.cuda.synchronize()
+
+    def time_req(req, reps=3, marked=False):
+        """Median launch time of the request's search, by HIP events recorded
+        on the stream the search is launched on (torch's current stream)."""
         req.run()
         torch.cuda.synchronize()
+        if marked:
+            mark()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ts = []
         for _ in range(reps):
@@ -298,6 +429,8 @@ def main():
             e1.record()
             torch.cuda.synchronize()
             ts.append(e0.elapsed_time(e1))
+        if marked:
+            mark()
         return float(np.median(ts))
 
     pq_stats = {}
@@ -594,49 +727,85 @@ def main():
         log(f"tuned launch shapes: {tuned}")
 
     # ----------------------------------------------- timed region (graph) --
+    # A step is one captured pipeline launch over one batch of n_query
+    # queries.  NB distinct batches rotate, batch i on stream i, so NF steps
+    # are in flight and none repeats another's queries.  (A second form
+    # splits batch 0 into NF quarters launched together per step.)
     NF = max(1, args.inflight)
+    nbq = cfg.n_query
     streams = [torch.cuda.Stream(device=dev) for _ in range(NF)]
+    batch_parts = [A.Vectors.from_tensor(qt[b * nbq:(b + 1) * nbq], metric) for b in range(NB)]
+    quarter_parts = [A.Vectors.from_tensor(qt[i * nbq // NF:(i + 1) * nbq // NF], metric)
+                     for i in range(NF)]
 
-    def run_steps(pl, n):
-        """n batches, batch i on stream i mod NF; returns the last request."""
+    def make_pipes(rows, quarters=False, **kw):
+        return [A.Pipeline(rows, graph, qp, piv, NS, k=K, **idm, **kw)
+                for qp in (quarter_parts if quarters else batch_parts)]
+
+    def run_steps(pl, n, quarters=False):
         cur = torch.cuda.current_stream()
         for s_ in streams:
             s_.wait_stream(cur)
-        last = None
         for i in range(n):
-            with torch.cuda.stream(streams[i % NF]):
-                last = pl[i % NF].launch()
+            for j in (range(len(pl)) if quarters else (i % len(pl),)):
+                with torch.cuda.stream(streams[j % NF]):
+                    pl[j].launch()
         for s_ in streams:
             cur.wait_stream(s_)
-        return last
 
-    def learned_pipes(tgt, pt):
+    def pipes_out(pl, field):
+        return np.concatenate([getattr(p_.req, field).cpu().numpy() for p_ in pl])
+
+    def close(pl):
+        for p_ in pl:
+            p_.close()
+
+    def time_pipes(pl, steps, markers=False, quarters=False):
+        """(queries/s, wall seconds, recall) of `steps` steps after the warm-up;
+        recall over every batch's last output."""
+        run_steps(pl, max(args.warmup, len(pl)), quarters)
+        torch.cuda.synchronize()
+        if markers:
+            mark()
+        t0 = time.time()
+        run_steps(pl, steps, quarters)
+        torch.cuda.synchronize()
+        wall = time.time() - t0
+        if markers:
+            mark()
+        got = pipes_out(pl, "ids")
+        rec = float(LR.recall_by_ids(got, gt[:len(got)], K).mean())
+        return nbq * steps / wall, wall, rec
+
+    def learned_pipes(tgt, pt, quarters=False):
         pred = learned_pred(tgt, pt["knob"])
-        return [A.Pipeline(search_rows, graph, queries, piv, NS, k=K, eps=0.0, ep=L.EP_INF, **idm,
-                           two_phase=True, ep_first=EPF, probe_hops=PROBE, predictor=pred,
-                           max_dc=pt["max_dc"], max_dc_factor=pt["max_dc_factor"],
-                           single_pass=pt["single_pass"], **rr) for _ in range(NF)]
+        return make_pipes(search_rows, quarters, eps=0.0, ep=L.EP_INF, two_phase=True,
+                          ep_first=EPF, probe_hops=PROBE, predictor=pred, max_dc=pt["max_dc"],
+                          max_dc_factor=pt["max_dc_factor"], single_pass=pt["single_pass"], **rr)
 
     # The learned pipeline's setting (form and budget) is chosen by a short
     # pipelined run of every setting: the batches in flight hide tails that
     # the single-batch search time counts, so its ranking is not the
-    # pipeline's.
+    # pipeline's.  The chosen setting is then timed afresh.
     sel_steps = max(5, args.steps // 2)
     for tgt in (0.95, 0.99):
         forms = sorted(learned_var[tgt], key=lambda p_: -p_["qps"])
+        if tgt == 0.95 and args.learned_pick:
+            fm, fac, bud = args.learned_pick.split(",")
+            pick = [p_ for p_ in forms if p_["single_pass"] == (fm == "fused") and
+                    abs(p_["max_dc_factor"] - float(fac)) < 1e-9 and p_["max_dc"] == int(bud)]
+            if pick:
+                learned_pts["0.95"] = pick[0]
+                log(f"learned setting at 0.95 taken as given: {args.learned_pick}")
+                continue
+            log(f"--learned-pick {args.learned_pick} matches no setting; choosing by timing")
         if len(forms) < 2:
             continue
         rates = []
         for pt in forms:
             pl = learned_pipes(tgt, pt)
-            run_steps(pl, args.warmup)
-            torch.cuda.synchronize()
-            t0 = time.time()
-            run_steps(pl, sel_steps)
-            torch.cuda.synchronize()
-            rates.append(queries.n / ((time.time() - t0) / sel_steps))
-            for p_ in pl:
-                p_.close()
+            rates.append(time_pipes(pl, sel_steps)[0])
+            close(pl)
             pt["selection_pipeline_qps"] = round(rates[-1], 1)
         learned_pts[str(tgt)] = forms[int(np.argmax(rates))]
         log(f"learned settings at {tgt} (pipelined q/s): " + ", ".join(
@@ -644,19 +813,6 @@ def main():
             f"f={pt['max_dc_factor']:g} dc={pt['dc']:.0f} {r:.0f}" for pt, r in zip(forms, rates)))
     knobs, budgets, bfactors, single = learned_params()
 
-    pred95 = learned_pred(0.95, knobs[0.95])
-    # one pipeline (own outputs and workspace) and one stream per batch in flight
-    pipes = [A.Pipeline(search_rows, graph, queries, piv, NS, k=K, eps=0.0, ep=L.EP_INF, **idm,
-                        two_phase=True, ep_first=EPF, probe_hops=PROBE, predictor=pred95,
-                        max_dc=budgets[0.95], max_dc_factor=bfactors[0.95],
-                        single_pass=single[0.95], **rr)
-             for _ in range(NF)]
-    pipe = pipes[0]
-    plain95 = result["plain"]["0.95"]
-    pipes_plain = []
-    if plain95 is not None:
-        pipes_plain = [A.Pipeline(base, graph, queries, piv, NS, k=K, eps=plain95["knob"], **idm,
-                                  ep=LR.dynamic_ep(plain95["knob"])) for _ in range(NF)]
     if args.search_only:
         req = make_learned_b(0.95, single[0.95])(knobs[0.95], budgets[0.95], bfactors[0.95])
         for _ in range(args.warmup + args.steps):
@@ -665,79 +821,102 @@ def main():
         log("search-only loop done")
         return
 
-    run_steps(pipes, args.warmup)
-    torch.cuda.synchronize()
-    t = time.time()
-    req = run_steps(pipes, args.steps)
-    torch.cuda.synchronize()
-    wall = time.time() - t
+    # the headline: the learned low-precision pipeline at 0.95
+    pipes = learned_pipes(0.95, learned_pts["0.95"])
+    value, wall, rec95 = time_pipes(pipes, args.steps, markers=True)
     ms_step = wall * 1e3 / args.steps
-    value = queries.n / (ms_step / 1e3)
-    rec95 = float(np.mean([LR.recall_by_ids(p_.req.ids.cpu().numpy(), gt, K).mean()
-                           for p_ in pipes[:min(NF, args.steps)]]))
-    log(f"timed: {args.steps} steps, {NF} in flight, {ms_step:.2f} ms/step, {value:.0f} q/s, "
-        f"recall {rec95:.4f}")
+    st_win = [p_.req.stats.cpu().numpy() for p_ in pipes]     # one per batch
+    close(pipes)
+    log(f"timed: {args.steps} steps, {NB} batches rotating over {NF} streams, {ms_step:.2f} "
+        f"ms/step, {value:.0f} q/s, recall {rec95:.4f}")
 
-    plain_pipe_qps = None
-    if pipes_plain:
-        run_steps(pipes_plain, args.warmup)
-        torch.cuda.synchronize()
-        t = time.time()
-        run_steps(pipes_plain, args.steps)
-        torch.cuda.synchronize()
-        plain_pipe_qps = queries.n / ((time.time() - t) / args.steps)
-        log(f"plain f32 pipeline at eps={plain95['knob']}, {NF} in flight: "
-            f"{plain_pipe_qps:.0f} q/s")
-    for p_ in pipes + pipes_plain:
-        p_.close()
+    # every comparator as a pipeline too, at its own best budget
+    def plain_pipes(pt, quarters=False):
+        return make_pipes(base, quarters, eps=pt["knob"], ep=LR.dynamic_ep(pt["knob"]),
+                          max_dc=pt.get("max_dc", 0))
 
-    # the same two pipelines at recall 0.99
-    def pipe_qps(pl):
-        run_steps(pl, args.warmup)
-        torch.cuda.synchronize()
-        t0 = time.time()
-        last = run_steps(pl, args.steps)
-        torch.cuda.synchronize()
-        q_ = queries.n / ((time.time() - t0) / args.steps)
-        rec = float(LR.recall_by_ids(last.ids.cpu().numpy(), gt, K).mean())
-        for p_ in pl:
-            p_.close()
-        return q_, rec
+    def lp_pipes(pt):
+        return make_pipes(lp_rows, eps=pt["knob"], ep=LR.dynamic_ep(pt["knob"]),
+                          max_dc=pt.get("max_dc", 0), rerank_base=base, pool_factor=4)
 
-    learned99_pipe = plain99_pipe = None
+    pipe_res = {}
+    plain95 = result["plain"]["0.95"]
+
+    def pipe_time(name, make, pt):
+        if pt is None:
+            return None
+        pl = make(pt)
+        q_, _, r_ = time_pipes(pl, args.steps)
+        close(pl)
+        pipe_res[name] = dict(qps=round(q_, 1), recall=round(r_, 4),
+                              max_dc=pt.get("max_dc", 0), knob=pt["knob"])
+        log(f"{name}: {q_:.0f} q/s, recall {r_:.4f}")
+        return q_
+
+    for t in ("0.95", "0.99"):
+        pipe_time(f"plain_f32@{t}", plain_pipes, result["plain"][t])
+        pipe_time(f"plain_f32_budget@{t}", plain_pipes, result["plain_budget"][t])
+        if lp_rows is not None:
+            pipe_time(f"lp_fixed_eps_budget@{t}", lp_pipes, result["lp_budget"][t])
     if learned_pts.get("0.99") is not None:
-        pred99 = learned_pred(0.99, knobs[0.99])
-        learned99_pipe = pipe_qps([A.Pipeline(
-            search_rows, graph, queries, piv, NS, k=K, **idm, eps=0.0, ep=L.EP_INF, two_phase=True,
-            ep_first=EPF, probe_hops=PROBE, predictor=pred99, max_dc=budgets[0.99],
-            max_dc_factor=bfactors[0.99], single_pass=single[0.99], **rr) for _ in range(NF)])
-        log(f"learned pipeline at 0.99, {NF} in flight: {learned99_pipe[0]:.0f} q/s, "
-            f"recall {learned99_pipe[1]:.4f}")
-    plain99 = result["plain"]["0.99"]
-    if plain99 is not None:
-        plain99_pipe = pipe_qps([A.Pipeline(base, graph, queries, piv, NS, k=K, **idm,
-                                            eps=plain99["knob"], ep=LR.dynamic_ep(plain99["knob"]))
-                                 for _ in range(NF)])
-        log(f"plain f32 pipeline at 0.99, {NF} in flight: {plain99_pipe[0]:.0f} q/s")
+        pl = learned_pipes(0.99, learned_pts["0.99"])
+        q99, _, r99 = time_pipes(pl, args.steps)
+        close(pl)
+        pipe_res["learned_lp@0.99"] = dict(qps=round(q99, 1), recall=round(r99, 4))
+        log(f"learned pipeline at 0.99: {q99:.0f} q/s, recall {r99:.4f}")
+    pipe_res["learned_lp@0.95"] = dict(qps=round(value, 1), recall=round(rec95, 4))
+
+    def best_plain(t):
+        c = [pipe_res[n]["qps"] for n in (f"plain_f32@{t}", f"plain_f32_budget@{t}")
+             if n in pipe_res]
+        return max(c) if c else None
+
+    # the quarters form at 0.95: batch 0 split in NF parts launched together
+    quarters = {}
+    if plain95 is not None:
+        for nm, pl in (("learned_lp@0.95", learned_pipes(0.95, learned_pts["0.95"], True)),
+                       ("plain_f32@0.95", plain_pipes(plain95, True)),
+                       ("plain_f32_budget@0.95", plain_pipes(result["plain_budget"]["0.95"],
+                                                             True))):
+            q_, _, r_ = time_pipes(pl, args.steps, quarters=True)
+            close(pl)
+            quarters[nm] = dict(qps=round(q_, 1), recall=round(r_, 4))
+        log(f"quarters of batch 0 in flight: {quarters}")
 
     # ---------------------------------------- roofline of the search kernel --
+    dim = cfg.dim
+    q_bytes = dim if is_u8 else 4 * dim
+
+    def query_bytes(st, rows_dtype, rerank):
+        """Algorithmic bytes of each query of a search: its query row, seed
+        ids, per expansion the offsets (16 B) and its scanned adjacency ids,
+        one stored row per distance computation, the rerank's f32 rows, the
+        outputs and the stats."""
+        dc, hops, scanned = (st[:, 0].astype(np.float64), st[:, 1].astype(np.float64),
+                             st[:, 5].astype(np.float64))
+        row_bytes = {L.U8: dim, L.F32: 4 * dim, L.F16: 2 * dim, L.BF16: 2 * dim,
+                     L.FP8_E4M3: dim + 4}[rows_dtype]
+        pool = np.minimum(dc, 4 * K) if rerank else 0
+        return (q_bytes + 4 * NS + 16 * hops + 4 * scanned + row_bytes * dc + (4 * dim) * pool
+                + 8 * K + 32)
+
     lreq = make_learned_b(0.95, single[0.95])(knobs[0.95], budgets[0.95], bfactors[0.95])
     lreq.run()
     req = lreq if single[0.95] else lreq.req   # the search pass (predict pass, order excluded)
-    ms_search = time_req(req, reps=5)
+    ms_search = time_req(req, reps=5, marked=True)
     st = req.stats.cpu().numpy()
     log(f"queries with candidate-set spill: {(st[:, 2] & L.QF_SPILLED != 0).mean():.3f}; "
         f"over capacity: {(st[:, 2] & L.QF_CAPACITY != 0).mean():.4f}")
-    dc, hops, scanned = st[:, 0].astype(np.float64), st[:, 1].astype(np.float64), st[:, 5].astype(np.float64)
-    dim = cfg.dim
-    row_bytes = {L.U8: dim, L.F32: 4 * dim, L.F16: 2 * dim, L.BF16: 2 * dim,
-                 L.FP8_E4M3: dim + 4}[search_rows.dtype]
-    q_bytes = dim if is_u8 else 4 * dim
-    pool = np.minimum(dc, 4 * K) if lp_rows is not None else 0
-    per_query = (q_bytes + 4 * NS + 16 * hops + 4 * scanned + row_bytes * dc
-                 + (4 * dim) * pool + 8 * K + 32)
+    per_query = query_bytes(st, search_rows.dtype, lp_rows is not None)
     bytes_launch = float(per_query.sum())
     achieved = bytes_launch / (ms_search / 1e3) / 1e9
+    # the same count over the timed window: step i searches batch i mod NB
+    # (the three-step form's predict passes, about 1% of the bytes, excluded)
+    per_batch = [float(query_bytes(st_b, search_rows.dtype, lp_rows is not None).sum())
+                 for st_b in st_win]
+    bytes_win = sum(per_batch[i % len(per_batch)] for i in range(args.steps))
+    bytes_step = bytes_win / args.steps
+    achieved_win = bytes_win / wall / 1e9
     workload_str = (f"{cfg.name}: {cfg.n_base:,} base + {cfg.n_query:,} queries, dim "
                     f"{cfg.dim}, {cfg.kind}, {cfg.n_clusters} clusters; kNN k={cfg.knn_k}, "
                     f"e_o={cfg.e_o}/e_i={cfg.e_i}"
@@ -746,12 +925,71 @@ def main():
                     f"from {piv.numel()} pivots; learned eps for recall 0.95, "
                     f"{args.lp if not is_u8 else 'u8'} rows + f32 rerank of 4k")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=8000.0, unit="GB/s",
-                    frac=round(achieved / 8000.0, 4), traffic=measured_traffic(workload_str),
+                    frac=round(achieved / 8000.0, 4),
+                    traffic=measured_traffic(workload_str, bytes_launch),
                     kernel="search_kernel", bytes_per_launch=bytes_launch,
                     ms_per_launch=round(ms_search, 4),
-                    bytes_per_query_mean=round(float(per_query.mean()), 1))
+                    bytes_per_query_mean=round(float(per_query.mean()), 1),
+                    window=dict(achieved=round(achieved_win, 1),
+                                frac=round(achieved_win / 8000.0, 4),
+                                bytes_per_step=bytes_step, ms_per_step=round(ms_step, 4),
+                                what="algorithmic bytes of the search launches of all timed "
+                                     "steps over the timed window's wall time"))
     log(f"search kernel: {ms_search:.3f} ms, {bytes_launch / 1e6:.1f} MB algorithmic, "
-        f"{achieved:.0f} GB/s ({achieved / 8000:.1%} of 8 TB/s)")
+        f"{achieved:.0f} GB/s ({achieved / 8000:.1%} of 8 TB/s); over the timed window "
+        f"{achieved_win:.0f} GB/s ({achieved_win / 8000:.1%})")
+    # the plain f32 search at its 0.95 operating point (rows larger than the
+    # 256 MB last-level cache)
+    roofline_plain = None
+    if plain95 is not None:
+        preq = A.SearchRequest(base, graph, queries, seeds, k=K, eps=plain95["knob"], **idm,
+                               ep=LR.dynamic_ep(plain95["knob"]))
+        ms_p = time_req(preq, reps=5, marked=True)
+        bp = float(query_bytes(preq.stats.cpu().numpy(), base.dtype, False).sum())
+        ach_p = bp / (ms_p / 1e3) / 1e9
+        roofline_plain = dict(bound="hbm", achieved=round(ach_p, 1), peak=8000.0, unit="GB/s",
+                              frac=round(ach_p / 8000.0, 4), kernel="search_kernel (f32 rows)",
+                              bytes_per_launch=bp, ms_per_launch=round(ms_p, 4))
+        log(f"plain f32 search kernel: {ms_p:.3f} ms, {bp / 1e6:.1f} MB algorithmic, "
+            f"{ach_p:.0f} GB/s ({ach_p / 8000:.1%} of 8 TB/s)")
+
+    # ---------------------------------------- storage types against fp64 --
+    lp_report = {}
+    if not is_u8 and plain95 is not None and not args.no_dtype_report:
+        e95 = plain95["knob"]
+        for nm, dt in (("f16", L.F16), ("bf16", L.BF16), ("fp8", L.FP8_E4M3)):
+            if dt == L.FP8_E4M3:
+                rows = A.encode(xt, dt, metric, scale_in_row=True,
+                                pitch=A.row_pitch(A.fp8_inrow_pitch(cfg.dim), L.U8, 128))
+            else:
+                rows = A.encode(xt, dt, metric, pitch=A.row_pitch(cfg.dim, dt, 128))
+            ent = {}
+            for rr_ in (False, True):
+                extra = dict(rerank_base=base, pool_factor=4) if rr_ else {}
+                r_ = A.SearchRequest(rows, graph, queries, seeds, k=K, eps=e95,
+                                     ep=LR.dynamic_ep(e95), **extra).run()
+                ids_ = r_.ids
+                ex_ids, ex_d = A.rerank(queries, base, ids_, K, use_f64=True)
+                torch.cuda.synchronize()
+                a_i, a_d = ids_.cpu().numpy(), r_.dists.cpu().numpy().astype(np.float64)
+                b_i, b_d = ex_ids.cpu().numpy(), ex_d.cpu().numpy()
+                oa, ob = np.argsort(a_i, axis=1), np.argsort(b_i, axis=1)
+                a_d = np.take_along_axis(a_d, oa, 1)
+                b_d = np.take_along_axis(b_d, ob, 1)
+                ok = np.take_along_axis(a_i, oa, 1) >= 0
+                floor = 1e-2 if metric == L.COSINE else 1e-30
+                err = np.abs(a_d - b_d)[ok] / np.maximum(np.abs(b_d[ok]), floor)
+                rec = float(LR.recall_by_ids(to_orig(ids_).cpu().numpy(), gt, K).mean())
+                key = "rerank" if rr_ else "search"
+                ent[f"recall_{key}"] = round(rec, 5)
+                ent[f"max_rel_err_{key}"] = float(f"{err.max():.3e}")
+            ent["eps"] = e95
+            lp_report[nm] = ent
+            log(f"{nm} rows at eps {e95}: {ent}")
+            del rows
+        lp_report["what"] = ("recall@10 and the largest |d - d_fp64| / max(d_fp64, floor) over "
+                             "the returned (id, d), searched at the plain f32 range for 0.95, "
+                             "without and with the f32 rerank of 4k; floor 1e-2 for cosine")
 
     # ----------------------------------------------------- CPU oracle leg --
     cpu = None
@@ -762,30 +1000,42 @@ def main():
         sd = seeds.cpu().numpy()
         x_or = xt.cpu().numpy() if perm is not None else x     # rows in the graph's order
         bv = orc.Vectors.from_array(x_or, orc.COS if metric == L.COSINE else orc.L2SQ)
-        qv_all = q
         eps0 = plain95["knob"]
         ep0 = LR.dynamic_ep(eps0)
+
+        def oracle_rate(thr, seconds):
+            n, spent, done = 64 if thr > 1 else 8, 0.0, 0
+            while spent < seconds and done < len(q):
+                m = min(n, len(q) - done)
+                qv = orc.Vectors.from_array(q[done:done + m], bv.metric)
+                t = time.time()
+                orc.search(bv, off, nb, qv, sd[done:done + m], K, eps0, ep0, threads=thr)
+                spent += time.time() - t
+                done += m
+                n = min(4 * n, 4096)
+            return done / spent, done, spent
+
         thr = orc.nthreads()
-        n = 64
-        spent = 0.0
-        done = 0
-        while spent < args.cpu_seconds and done < len(q):
-            m = min(n, len(q) - done)
-            qv = orc.Vectors.from_array(qv_all[done:done + m], bv.metric)
-            t = time.time()
-            orc.search(bv, off, nb, qv, sd[done:done + m], K, eps0, ep0, threads=thr)
-            spent += time.time() - t
-            done += m
-            n = min(4 * n, 4096)
-        cpu = dict(value=round(done / spent, 1), unit="queries/s", cores=thr, kind="oracle",
-                   sample=f"first {done} queries of the workload, plain "
-                          f"{'u8' if is_u8 else 'f32'} search at eps={eps0} (its operating "
-                          f"point for recall 0.95), "
-                          f"{'exact int' if is_u8 else 'fp64'} distances, {thr} threads")
-        log(f"cpu oracle: {done} queries in {spent:.1f} s on {thr} threads")
+        rate, done, spent = oracle_rate(thr, args.cpu_seconds)
+        rate1, done1, spent1 = oracle_rate(1, args.cpu_seconds_1t)
+        what = (f"plain {'u8' if is_u8 else 'f32'} search at eps={eps0} (its operating point "
+                f"for recall 0.95), {'exact int' if is_u8 else 'fp64'} distances")
+        cpu = dict(value=round(rate, 1), unit="queries/s", cores=thr, kind="oracle",
+                   sample=f"first {done} queries of the workload, {what}, {thr} threads",
+                   single_thread=dict(value=round(rate1, 1), unit="queries/s", cores=1,
+                                      sample=f"first {done1} queries, {what}, one thread "
+                                             "(the paper's single-threaded setting)"))
+        log(f"cpu oracle: {done} queries in {spent:.1f} s on {thr} threads; {done1} in "
+            f"{spent1:.1f} s on one thread")
 
     def qps_of(pt):
         return round(pt["qps"], 1) if pt else None
+
+    def ratio(a_, b_):
+        return round(a_ / b_, 3) if a_ and b_ else None
+
+    def pq(name):
+        return pipe_res[name]["qps"] if name in pipe_res else None
 
     out = {
         "metric": "queries/sec at recall@10 = 0.95 and 0.99, learned+low-precision vs plain FP32",
@@ -805,37 +1055,42 @@ def main():
             "workload": workload_str,
             "global_batch": cfg.n_query,
             "batches_in_flight": NF,
+            "query_batches": NB,
+            "in_flight": (f"{NB} distinct batches of {cfg.n_query} queries (batch 0 the "
+                          f"workload's query set) rotate over {NF} streams; operating points "
+                          f"and recall over all {NB * cfg.n_query} queries"),
             "max_dc": {str(t): budgets[t] for t in (0.95, 0.99)},
             "max_dc_factor": {str(t): bfactors[t] for t in (0.95, 0.99)},
             "learned_single_pass": {str(t): single[t] for t in (0.95, 0.99)},
             "launch_shapes": tuned,
         },
         "recall_at_timed_point": round(rec95, 4),
-        "qps": {
-            "learned_lp@0.95": round(value, 1),
-            "learned_lp@0.99": round(learned99_pipe[0], 1) if learned99_pipe else None,
-            "learned_lp_search@0.99": qps_of(learned_pts.get("0.99")),
+        "pipelines": pipe_res,
+        "quarters_of_batch0_in_flight": quarters,
+        "speedup_vs_plain_f32@0.95": ratio(value, best_plain("0.95")),
+        "speedup_vs_plain_f32@0.99": ratio(pq("learned_lp@0.99"), best_plain("0.99")),
+        "learned_gain_over_lp_fixed_eps@0.95": ratio(value, pq("lp_fixed_eps_budget@0.95")),
+        "learned_gain_over_lp_fixed_eps@0.99": ratio(pq("learned_lp@0.99"),
+                                                     pq("lp_fixed_eps_budget@0.99")),
+        "single_batch_search_qps": {
+            "learned_lp@0.95": qps_of(learned_pts.get("0.95")),
+            "learned_lp@0.99": qps_of(learned_pts.get("0.99")),
             "plain_f32@0.95": qps_of(plain95),
             "plain_f32@0.99": qps_of(result["plain"]["0.99"]),
-            "plain_f32_pipeline@0.95": round(plain_pipe_qps, 1) if plain_pipe_qps else None,
-            "plain_f32_pipeline@0.99": round(plain99_pipe[0], 1) if plain99_pipe else None,
+            "plain_f32_budget@0.95": qps_of(result["plain_budget"]["0.95"]),
+            "plain_f32_budget@0.99": qps_of(result["plain_budget"]["0.99"]),
             "lp_fixed_eps@0.95": qps_of(result.get("lp", {}).get("0.95")),
             "lp_fixed_eps@0.99": qps_of(result.get("lp", {}).get("0.99")),
             "lp_fixed_eps_budget@0.95": qps_of(result.get("lp_budget", {}).get("0.95")),
             "lp_fixed_eps_budget@0.99": qps_of(result.get("lp_budget", {}).get("0.99")),
-            "plain_f32_budget@0.95": qps_of(result["plain_budget"]["0.95"]),
-            "plain_f32_budget@0.99": qps_of(result["plain_budget"]["0.99"]),
-            "learned_lp_search@0.95": qps_of(learned_pts.get("0.95")),
         },
-        "speedup_vs_plain_f32@0.95": (round(value / plain_pipe_qps, 3) if plain_pipe_qps else None),
-        "speedup_vs_plain_f32@0.99": (round(learned99_pipe[0] / plain99_pipe[0], 3)
-                                      if learned99_pipe and plain99_pipe else None),
-        "recall_at_timed_point@0.99": round(learned99_pipe[1], 4) if learned99_pipe else None,
+        "storage_vs_fp64": lp_report,
         "operating_points": result,
         "curve": curve,
         "build_s": build,
         "graph_stats": gstats,
         "roofline": roofline,
+        "roofline_plain_f32": roofline_plain,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

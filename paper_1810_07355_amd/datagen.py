@@ -9,7 +9,9 @@ produce stand-ins with the same shapes, value ranges and cluster structure.
 Every stream comes from numpy PCG64 seeded by
 ``SeedSequence(18100735, spawn_key=(config_id, stream))`` with
 stream 0 = cluster centres, 1 = base vectors, 2 = queries,
-3 = training queries, 4 = pivot ids, 5 = per-query mixed parameters.
+3 = training queries, 4 = pivot ids, 5 = per-query mixed parameters,
+6 + i = random seeds, 100 + b = further query batches b = 1, 2, ... (distinct
+batches that keep several batches of fresh queries in flight).
 
 Workloads (sizes in ``PRESETS``):
 
@@ -151,6 +153,12 @@ def base(cfg: Preset) -> np.ndarray:
 
 def queries(cfg: Preset) -> np.ndarray:
     return _vectors(cfg, cfg.n_query, 2)
+
+
+def query_batch(cfg: Preset, b: int) -> np.ndarray:
+    """Batch b of n_query queries from the query distribution: batch 0 is
+    queries(cfg), batch b >= 1 its own stream."""
+    return queries(cfg) if b == 0 else _vectors(cfg, cfg.n_query, 100 + b)
 
 
 def train_queries(cfg: Preset, n: int | None = None) -> np.ndarray:
