@@ -215,6 +215,17 @@ onng_status onng_graph_add_edges(const onng_graph *in, const int32_t *src, const
                                  size_t ws_bytes, void *stream);
 size_t onng_graph_add_edges_workspace_size(int64_t n, int64_t nnz, int64_t n_edges);
 
+/* The first step of ConstructGraph (Algorithm 8, Section 2.6):
+ * G_k = ConstructAdjustedGraph(G_a, k_c, 0), Algorithm 2 with e_i = 0, which
+ * keeps the k = k_c shortest edges of every node of the graph (an ANNG) and
+ * adds no reverse edge: the approximate k-NN graph (AKNNG) the degree
+ * adjustments start from.  Output as the table they take: ids [n][k] and
+ * dists [n][k] (device), row v = the first min(k, deg(v)) entries of v's
+ * (length, id)-sorted list, padded with -1 and INT32_MAX (u8, squared L2) or
+ * +inf.  Needs g->lens.  Asynchronous. */
+onng_status onng_graph_head(const onng_graph *g, int32_t data_dtype, int32_t metric, int32_t k,
+                            int32_t *ids, void *dists, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Entry seeds from a tree — Section 3.2 (tree-based index), Table 5        */
 /* ------------------------------------------------------------------------ */

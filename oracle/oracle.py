@@ -332,6 +332,31 @@ def anng(x: np.ndarray, metric: int, order, k_c: int, eps_c: float, n_seeds: int
     return csr()
 
 
+def aknng(off, nbrs, lens, k_c: int):
+    """The first step of ConstructGraph (Algorithm 8, Section 2.6):
+    G_k = ConstructAdjustedGraph(G_a, k_c, 0), i.e. Algorithm 2 with e_i = 0
+    run on the graph G_a (an ANNG), each node's list being the S of
+    Algorithm 2.  Returns G_k as the padded table it feeds the degree
+    adjustments: ids [n][k_c] (-1 padding) and dists [n][k_c] (+inf)."""
+    off = np.asarray(off, np.int64)
+    n = len(off) - 1
+    deg = np.diff(off)
+    width = max(1, int(deg.max()) if n else 1)
+    ids = np.full((n, width), -1, np.int32)
+    dd = np.full((n, width), np.inf)
+    for v in range(n):
+        ids[v, :deg[v]] = nbrs[off[v]:off[v + 1]]
+        dd[v, :deg[v]] = lens[off[v]:off[v + 1]]
+    go, gn, gl = adjust_degree(ids, dd, k_c, 0)
+    out_i = np.full((n, k_c), -1, np.int32)
+    out_d = np.full((n, k_c), np.inf)
+    for v in range(n):
+        m = go[v + 1] - go[v]
+        out_i[v, :m] = gn[go[v]:go[v + 1]]
+        out_d[v, :m] = gl[go[v]:go[v + 1]]
+    return out_i, out_d
+
+
 # ------------------------------------------------- tree-based seeds ------
 
 def vptree_build(B: Vectors, prio, leaf_size: int = 100, n_seeds: int = 10):

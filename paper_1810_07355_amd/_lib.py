@@ -84,6 +84,7 @@ PROTOS = {
     "onng_graph_add_edges": (C.c_int, [P, P, P, P, C.c_int64, C.c_int32, C.c_int32, P, P, P,
                                        C.c_int64, P, P, C.c_size_t, P]),
     "onng_graph_add_edges_workspace_size": (C.c_size_t, [C.c_int64, C.c_int64, C.c_int64]),
+    "onng_graph_head": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32, P, P, P]),
     "onng_vptree_build": (C.c_int, [P, P, P, P, C.c_size_t, P]),
     "onng_vptree_build_workspace_size": (C.c_size_t, [C.c_int64]),
     "onng_vptree_seeds": (C.c_int, [P, P, P, P, P, P]),

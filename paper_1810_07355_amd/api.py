@@ -180,6 +180,18 @@ def graph_add_edges(g: Graph, src: torch.Tensor, dst: torch.Tensor, lens: torch.
     return Graph(off, nb[:nnz.value].clone(), ln[:nnz.value].clone())
 
 
+def graph_head(g: Graph, k: int, dtype: int, metric: int):
+    """Algorithm 8's first step: every node's k shortest edges as a padded
+    table (ids [n][k], dists [n][k]), the AKNNG of an ANNG."""
+    dev = g.offsets.device
+    ids = torch.empty((g.n, k), dtype=torch.int32, device=dev)
+    dt = torch.int32 if (dtype == L.U8 and metric == L.L2SQ) else torch.float32
+    d = torch.empty((g.n, k), dtype=dt, device=dev)
+    L.call("onng_graph_head", C.byref(g.struct()), dtype, metric, k, ids.data_ptr(), d.data_ptr(),
+           _stream())
+    return ids, d
+
+
 class VPTree:
     """A 4-way vantage-point tree for entry seeds (Section 3.2, Table 5);
     built by vptree_build, its arrays live on the device."""

@@ -741,6 +741,44 @@ onng_status graph_stats_launch(const onng_graph *g, bool int_len, bool sqrt_len,
     return graph_stats_impl<float>(g, sqrt_len, frac, keep, out, ws, st);
 }
 
+// ---------------------------------------------- first k edges of a graph --
+
+namespace {
+
+// Row v of the table: the first min(k, deg(v)) edges of v's list (sorted by
+// (length, id)), then padding (-1, INT32_MAX or +inf).  One lane per entry.
+template <typename LT>
+__global__ void graph_head_kernel(const int64_t *off, const int32_t *nb, const LT *len, int64_t n,
+                                  int32_t k, LT pad, int32_t *ids, LT *dists) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * (int64_t)k) return;
+    const int64_t v = t / k;
+    const int32_t j = (int32_t)(t - v * k);
+    const int64_t e = off[v] + j;
+    const bool has = e < off[v + 1];
+    ids[t] = has ? nb[e] : -1;
+    dists[t] = has ? len[e] : pad;
+}
+
+}  // namespace
+
+onng_status graph_head_launch(const onng_graph *g, bool int_len, int32_t k, int32_t *ids,
+                              void *dists, hipStream_t st) {
+    const int64_t total = g->n * (int64_t)k;
+    if (total == 0) return ONNG_OK;
+    const unsigned blocks = (unsigned)((total + 255) / 256);
+    if (int_len)
+        hipLaunchKernelGGL(graph_head_kernel<int32_t>, dim3(blocks), dim3(256), 0, st, g->offsets,
+                           g->nbrs, static_cast<const int32_t *>(g->lens), g->n, k, INT32_MAX, ids,
+                           static_cast<int32_t *>(dists));
+    else
+        hipLaunchKernelGGL(graph_head_kernel<float>, dim3(blocks), dim3(256), 0, st, g->offsets,
+                           g->nbrs, static_cast<const float *>(g->lens), g->n, k,
+                           __builtin_huge_valf(), ids, static_cast<float *>(dists));
+    ONNG_HIP(hipGetLastError());
+    return ONNG_OK;
+}
+
 size_t add_edges_ws(int64_t n, int64_t nnz, int64_t m) {
     Carver c(nullptr);
     c.take<int64_t>(n + 1);

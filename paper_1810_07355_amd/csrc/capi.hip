@@ -45,6 +45,8 @@ onng_status add_edges_launch(const onng_graph *g, const int32_t *src, const int3
                              int32_t *out_nb, void *out_len, int64_t nnz_cap, int64_t *nnz_out,
                              void *ws, hipStream_t st);
 size_t add_edges_ws(int64_t n, int64_t nnz, int64_t m);
+onng_status graph_head_launch(const onng_graph *g, bool int_len, int32_t k, int32_t *ids,
+                              void *dists, hipStream_t st);
 onng_status adjust_path_launch(const onng_graph *g, bool int_len, int64_t *offsets,
                                int32_t *nbrs, void *lens, int64_t *nnz_out, void *ws,
                                hipStream_t st);
@@ -742,6 +744,18 @@ onng_status onng_graph_add_edges(const onng_graph *in, const int32_t *src, const
     }
     return add_edges_launch(in, src, dst, lens, n_edges, int_dist(data_dtype, metric), offsets,
                             nbrs, out_lens, nnz_capacity, nnz_out, ws, as_stream(stream));
+}
+
+onng_status onng_graph_head(const onng_graph *g, int32_t data_dtype, int32_t metric, int32_t k,
+                            int32_t *ids, void *dists, void *stream) {
+    set_error("");
+    ONNG_CHECK_ARG(g && g->offsets && (g->nnz == 0 || (g->nbrs && g->lens)), "graph is null");
+    ONNG_CHECK_ARG(g->n >= 0 && g->nnz >= 0 && g->n <= 0x7fffffffLL, "bad sizes");
+    ONNG_CHECK_ARG(k >= 1 && k <= 4096, "k must be in [1, 4096]");
+    ONNG_CHECK_ARG(g->n == 0 || (ids && dists), "outputs are null");
+    ONNG_CHECK_ARG(data_dtype >= ONNG_U8 && data_dtype <= ONNG_FP8_E4M3, "unknown dtype");
+    ONNG_CHECK_ARG(metric == ONNG_L2SQ || metric == ONNG_COSINE, "unknown metric");
+    return graph_head_launch(g, int_dist(data_dtype, metric), k, ids, dists, as_stream(stream));
 }
 
 // ------------------------------------------------------- tree-based seeds --

@@ -379,3 +379,47 @@ def test_label_sweep_matches_oracle_u8():
                                                 ep=orc.dynamic_ep(grid[e]), two_phase=True,
                                                 ep_first=EPF, probe_hops=1).ids), gt_ids, 10)
         assert np.array_equal(by_ids[untied], rec_orc[e][untied])
+
+
+def test_mixed_k_learned_range_per_class_against_oracle_u8():
+    """The mixed batch of extension 2 with the learned range: each query has
+    its own k in {1, 10, 100} and target class, the fused predictor takes the
+    class's head (head_per_query, a calibration shift per head), and one
+    persistent launch (k_stride 100) serves them all.  Against the oracle's
+    predictor and Algorithm 1 with each query's k, range and e_p: bit for bit
+    (u8), the ranges within 1e-4."""
+    P = c1_problem()
+    po, pn, _ = P["pa"]
+    A, Lb = api(), L()
+    g = np.random.default_rng(23)
+    nq = len(P["q"])
+    ks, ts = np.array([1, 10, 100]), np.array([0.9, 0.95, 0.99])
+    kq = ks[g.integers(0, 3, nq)].astype(np.int32)
+    cls = (np.searchsorted(ks, kq) * 3 + g.integers(0, 3, nq)).astype(np.int32)
+    # the features come from each query's own k
+    feat = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], kq, 0.0, orc.INF_EP, eps1=np.inf,
+                      ep1=64, probe_hops=1, want_features=True, k_stride=100)["feat"]
+    shift = np.linspace(-0.2, 0.2, 9).astype(np.float32)
+    pred, hw = random_predictor(9, Lb.PRED_LOG_EPS, g, feat, np.linspace(-1.8, -0.9, 9), orc.L2SQ,
+                                head_per_query=to_dev(cls), shift=to_dev(shift), eps_min=0.0,
+                                eps_max=0.3, e0=30.0, we=20.0)
+    ref = orc.predict(feat, orc.L2SQ, **hw, mode="log_eps", head_per_query=cls, shift=shift,
+                      eps_min=0.0, eps_max=0.3, e0=30.0, we=20.0)
+    say("mixed k with learned range per class")
+    r = A.search(gpu_vectors(P["x"], orc.L2SQ), gpu_graph(po, pn), gpu_vectors(P["q"], orc.L2SQ),
+                 to_dev(P["seeds"]), k=to_dev(kq), k_stride=100, two_phase=True, ep_first=64,
+                 predictor=pred, probe_hops=1)
+    torch.cuda.synchronize()
+    ge, gp, gc = host(r.eps_used), host(r.ep_used), host(r.cost)
+    sure = _check_predictor(ge, gp, gc, ref, "log_eps")
+    assert sure.all()
+    assert len(np.unique(ge)) > 5
+    oref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], kq, ge.astype(np.float32),
+                      gp.astype(np.uint32), eps1=np.inf, ep1=64, probe_hops=1, k_stride=100)
+    gi = host(r.ids)
+    assert np.array_equal(gi, oref["ids"])
+    assert np.array_equal(host(r.dc), oref["dc"])
+    assert np.array_equal(host(r.hops), oref["hops"])
+    for kk in ks:
+        sel = kq == kk
+        assert np.all(gi[sel][:, kk:] == -1)          # rows padded past each query's k

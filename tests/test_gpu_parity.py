@@ -315,6 +315,45 @@ def test_anng_u8_against_oracle(max_batch, n_pivots):
     assert np.array_equal(host(g.lens), ln.astype(np.int32))
 
 
+def test_construct_graph_from_anng_u8_against_oracle():
+    """Algorithm 8 end to end on c1's rows: ANNG (k_c = 40, eps_c = 0.1) ->
+    G_k = ConstructAdjustedGraph(G_a, k_c, 0) -> Algorithm 2 (e_o = 10,
+    e_i = 30) -> path adjustment, every stage bit for bit against the oracle,
+    then searches over the result."""
+    from paper_1810_07355_amd import anng
+    P = c1_problem()
+    A, Lb = api(), L()
+    x = P["x"]
+    n, k_c = len(x), 40
+    order = dg.vp_priority(n, 12).astype(np.int64)
+    say("Algorithm 8 from an ANNG, k_c", k_c)
+    g = anng.build_anng(to_dev(x), Lb.L2SQ, to_dev(order.astype(np.int32)), k_c, 0.1)
+    off, nb, ln = orc.anng(x, orc.L2SQ, order, k_c, 0.1)
+    assert np.array_equal(host(g.offsets), off) and np.array_equal(host(g.nbrs), nb)
+    ids, d = A.graph_head(g, k_c, Lb.U8, Lb.L2SQ)
+    rid, rd = orc.aknng(off, nb, ln, k_c)
+    assert np.array_equal(host(ids), rid)
+    assert np.array_equal(host(d).astype(np.int64),
+                          np.where(np.isinf(rd), 2 ** 31 - 1, rd).astype(np.int64))
+    sa = A.adjust_degree(ids, d, Lb.U8, Lb.L2SQ, 10, 30)
+    so, sn, sl = orc.adjust_degree(rid, rd, 10, 30)
+    assert np.array_equal(host(sa.offsets), so) and np.array_equal(host(sa.nbrs), sn)
+    pa = A.adjust_path(sa, Lb.U8, Lb.L2SQ)
+    po, pn, pl = orc.adjust_path(so, sn, sl)
+    assert np.array_equal(host(pa.offsets), po) and np.array_equal(host(pa.nbrs), pn)
+    ref = orc.search(P["bv"], po, pn, P["qv"], P["seeds"], 10, 0.05)
+    r = A.search(gpu_vectors(x, orc.L2SQ), pa, gpu_vectors(P["q"], orc.L2SQ),
+                 to_dev(P["seeds"]), k=10, eps=0.05)
+    assert np.array_equal(host(r.ids), ref["ids"]) and np.array_equal(host(r.dc), ref["dc"])
+    # rows of fewer than k_c edges are padded; a k beyond every degree pads all rows
+    deg = np.diff(off)
+    big = int(deg.max()) + 3
+    ids2, d2 = A.graph_head(g, big, Lb.U8, Lb.L2SQ)
+    h = host(ids2)
+    assert np.all(h[np.arange(n), deg] == -1)
+    assert np.array_equal(h[np.arange(n), deg - 1], nb[off[1:] - 1])
+
+
 def test_graph_add_edges_against_numpy():
     say("graph_add_edges")
     A, Lb = api(), L()

@@ -1000,3 +1000,38 @@ def test_predictor_log_eps_hand_example():
     assert np.allclose(p["eps"], want, rtol=1e-12)
     assert p["ep"].tolist() == c["ep"]
     assert np.allclose(p["cost"], p["eps"], rtol=0)
+
+
+# --------------------------------------- Algorithm 8, first step (AKNNG) --
+
+def test_aknng_is_algorithm2_with_no_reverse_edges_on_the_anng():
+    """G_k of an ANNG: the definitional Algorithm 2 with (k_c, 0) on the
+    ANNG's lists, and a prefix of each (length, id)-sorted list."""
+    x = dg.random_tie_u8(300, 5, 31, levels=6)
+    order = dg.vp_priority(300, 4)
+    off, nb, ln = orc.anng(x, orc.L2SQ, order, 6, 0.1, n_pivots=16, max_batch=32)
+    for k_c in (1, 4, 9):
+        ids, d = orc.aknng(off, nb, ln, k_c)
+        rows = [nb[off[v]:off[v + 1]].tolist() for v in range(300)]
+        rowd = [ln[off[v]:off[v + 1]].tolist() for v in range(300)]
+        lit = literal.adjusted_graph(rows, rowd, k_c, 0)
+        for v in range(300):
+            want = lit[v]
+            got = [(float(a), int(b)) for a, b in zip(d[v], ids[v]) if b >= 0]
+            assert got == [(float(a), int(b)) for a, b in want], (k_c, v)
+            srt = sorted(zip(rowd[v], rows[v]))
+            assert got == [(float(a), int(b)) for a, b in srt[:k_c]]
+            assert np.all(ids[v, len(got):] == -1) and np.all(np.isinf(d[v, len(got):]))
+
+
+def test_aknng_of_a_symmetric_knn_graph_is_the_knn_table():
+    """On G_a = Algorithm 2 (k, k) of the exact k-NN table (every edge in both
+    directions), the k shortest edges of every node are its exact k nearest
+    neighbours: the first step returns the k-NN table itself."""
+    x = dg.random_vectors(250, 8, "u8", 41)
+    v = orc.Vectors.from_array(x, orc.L2SQ)
+    knn, kd = orc.knn_graph(v, 7)
+    off, nb, ln = orc.adjust_degree(knn, kd, 7, 7)
+    ids, d = orc.aknng(off, nb, ln, 7)
+    assert np.array_equal(ids, knn)
+    assert np.array_equal(d, kd)
