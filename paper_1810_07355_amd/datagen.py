@@ -11,7 +11,8 @@ Every stream comes from numpy PCG64 seeded by
 stream 0 = cluster centres, 1 = base vectors, 2 = queries,
 3 = training queries, 4 = pivot ids, 5 = per-query mixed parameters,
 6 + i = random seeds, 100 + b = further query batches b = 1, 2, ... (distinct
-batches that keep several batches of fresh queries in flight).
+batches that keep several batches of fresh queries in flight), 200 + b their
+mixed parameters, 300 the training queries' mixed parameters.
 
 Workloads (sizes in ``PRESETS``):
 
@@ -191,9 +192,12 @@ def random_seeds(cfg: Preset, n_query: int, n_seeds: int, stream_offset: int = 0
     return g.integers(0, cfg.n_base, size=(n_query, n_seeds)).astype(np.int32)
 
 
-def mixed_params(cfg: Preset, n_query: int, ks=(1, 10, 100), targets=(0.9, 0.95, 0.99)):
-    """Per-query (k, target recall) drawn uniformly from the product set."""
-    g = rng(cfg.config_id, 5)
+def mixed_params(cfg: Preset, n_query: int, ks=(1, 10, 100), targets=(0.9, 0.95, 0.99),
+                 stream: int = 5):
+    """Per-query (k, target recall) drawn uniformly from the product set
+    (stream 5 for the workload's queries, another stream for other batches
+    or training queries)."""
+    g = rng(cfg.config_id, stream)
     k = np.asarray(ks, dtype=np.int32)[g.integers(0, len(ks), size=n_query)]
     t = np.asarray(targets, dtype=np.float32)[g.integers(0, len(targets), size=n_query)]
     return k, t

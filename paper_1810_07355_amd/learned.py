@@ -76,10 +76,13 @@ class Trained:
 
 
 def train_targets(features: torch.Tensor, Y: np.ndarray, metric: int, hidden: int = 64,
-                  steps: int = 4000, batch: int = 1024, lr: float = 3e-3, seed: int = 0) -> Trained:
+                  steps: int = 4000, batch: int = 1024, lr: float = 3e-3, seed: int = 0,
+                  weights: np.ndarray | None = None) -> Trained:
     """Fit the perceptron to targets Y [n, T] (mean squared error, each target
     column standardised during training and folded back into the last layer).
-    features: raw [n, 14] f32 on the GPU."""
+    features: raw [n, 14] f32 on the GPU.  weights [n, T] (optional): the
+    weight of each target in the loss, e.g. one-hot when each sample labels
+    only its own head; the standardisation then uses the weighted moments."""
     dev = features.device
     X = api.feature_transform(features.contiguous(), metric)
     torch.cuda.synchronize()
@@ -89,10 +92,17 @@ def train_targets(features: torch.Tensor, Y: np.ndarray, metric: int, hidden: in
     std = np.where(std < 1e-6, 1.0, std)
     Xz = torch.from_numpy(((xh - mean) / std).astype(np.float32)).to(dev)
     Y = np.asarray(Y, dtype=np.float64)
-    ym = Y.mean(axis=0)
-    ys = Y.std(axis=0)
+    Wn = None if weights is None else np.asarray(weights, dtype=np.float64)
+    if Wn is None:
+        ym = Y.mean(axis=0)
+        ys = Y.std(axis=0)
+    else:
+        tot = np.maximum(Wn.sum(axis=0), 1e-12)
+        ym = (Wn * Y).sum(axis=0) / tot
+        ys = np.sqrt((Wn * (Y - ym) ** 2).sum(axis=0) / tot)
     ys = np.where(ys < 1e-6, 1.0, ys)
     Yt = torch.from_numpy(((Y - ym) / ys).astype(np.float32)).to(dev)
+    Wt = None if Wn is None else torch.from_numpy(Wn.astype(np.float32)).to(dev)
     n, F = Xz.shape
     T = Yt.shape[1]
     g = np.random.default_rng(seed)
@@ -115,7 +125,8 @@ def train_targets(features: torch.Tensor, Y: np.ndarray, metric: int, hidden: in
         pos += batch
         xb = Xz.index_select(0, idx).contiguous()
         yb = Yt.index_select(0, idx).contiguous()
-        loss, grads = api.mlp_backward(xb, yb, W1, b1, W2, b2)
+        wb = None if Wt is None else Wt.index_select(0, idx).contiguous()
+        loss, grads = api.mlp_backward(xb, yb, W1, b1, W2, b2, w=wb)
         step_lr = lr * (0.5 * (1.0 + math.cos(math.pi * t / steps)) * 0.9 + 0.1)
         for p, gr, m, v in zip(params, grads, ms, vs):
             api.adam_step(p, gr, m, v, step_lr, t)
