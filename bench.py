@@ -94,6 +94,9 @@ def parse():
                     help="CPU seconds of the one-thread oracle run")
     ap.add_argument("--no-dtype-report", action="store_true",
                     help="skip the f16/bf16/fp8 recall and error report")
+    ap.add_argument("--learned-select", action="store_true",
+                    help="choose the learned pipeline's form and budget by a short timed run "
+                         "of every setting instead of the fixed rule")
     ap.add_argument("--learned-pick", default=None, metavar="FORM,FACTOR,BUDGET",
                     help="take this learned setting at 0.95 (e.g. 3-step,2.0,19047) instead of "
                          "choosing by pipelined timing (profiler runs change the timing)")
@@ -798,13 +801,33 @@ def main():
                           ep_first=EPF, probe_hops=PROBE, predictor=pred, max_dc=pt["max_dc"],
                           max_dc_factor=pt["max_dc_factor"], single_pass=pt["single_pass"], **rr)
 
-    # The learned pipeline's setting (form and budget) is chosen by a short
-    # pipelined run of every setting: the batches in flight hide tails that
-    # the single-batch search time counts, so its ranking is not the
-    # pipeline's.  The chosen setting is then timed afresh.
+    # The learned pipeline's setting (form and budget) follows a fixed rule,
+    # so that every run, profiled or not, times the same configuration: the
+    # three-step form (longest predicted cost first, which shortens the batch
+    # tail), a cost-relative budget of 2x the predicted cost where the target
+    # is reachable with it (else none), and the largest scalar budget among
+    # the bisected ones (a cap on rare runaway queries).  --learned-select
+    # instead times a short pipelined run of every setting and keeps the
+    # fastest (a selection that favours settings whose short run was lucky).
+    def rule_pick(forms):
+        cand = [p_ for p_ in forms if not p_["single_pass"]] or forms
+        for fac in (2.0, 0.0):
+            got = [p_ for p_ in cand if abs(p_["max_dc_factor"] - fac) < 1e-9]
+            if got:
+                return max(got, key=lambda p_: p_["max_dc"])
+        return max(cand, key=lambda p_: p_["qps"])
+
     sel_steps = max(5, args.steps // 2)
     for tgt in (0.95, 0.99):
         forms = sorted(learned_var[tgt], key=lambda p_: -p_["qps"])
+        if not forms:
+            continue
+        if not args.learned_select and not (tgt == 0.95 and args.learned_pick):
+            learned_pts[str(tgt)] = rule_pick(forms)
+            pt = learned_pts[str(tgt)]
+            log(f"learned setting at {tgt} by rule: {'fused' if pt['single_pass'] else '3-step'} "
+                f"b={pt['max_dc']} f={pt['max_dc_factor']:g} dc={pt['dc']:.0f}")
+            continue
         if tgt == 0.95 and args.learned_pick:
             fm, fac, bud = args.learned_pick.split(",")
             pick = [p_ for p_ in forms if p_["single_pass"] == (fm == "fused") and
@@ -1077,6 +1100,10 @@ def main():
             "max_dc": {str(t): budgets[t] for t in (0.95, 0.99)},
             "max_dc_factor": {str(t): bfactors[t] for t in (0.95, 0.99)},
             "learned_single_pass": {str(t): single[t] for t in (0.95, 0.99)},
+            "learned_setting": ("timed selection" if args.learned_select else
+                                "given (--learned-pick) at 0.95" if args.learned_pick else
+                                "fixed rule: three steps, cost-relative budget 2x where the "
+                                "target is reachable with it, largest scalar budget"),
             "launch_shapes": tuned,
         },
         "recall_at_timed_point": round(rec95, 4),

@@ -22,65 +22,14 @@
 #include <cstdint>
 
 #include "onng_internal.h"
+#include "topk_common.h"
 #include "wave.h"
 
 namespace onng {
 
+using namespace topk_detail;
+
 namespace {
-
-typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int BN = 64;        // base rows per tile
-// Per-row list capacity (k rounded up to 8 keys) and candidate slots: a
-// tile adds at most BN candidates to a row, whose buffer is merged once it
-// holds more than cb - BN.  Small k takes 80 slots (merges after 16
-// candidates), which halves the buffer's LDS.
-__host__ __device__ inline int topk_kcap(int k) { return (k + 7) / 8 * 8; }
-__host__ __device__ inline int topk_cb(int k) { return k <= 16 ? 80 : 128; }
-
-// A staged row is NCH * 64 bytes: u8, NCH k-steps of 64 components (a lane
-// feeds 16 of them per step); f32, 4 k-groups of KQ = 4 * NCH components,
-// k-group kg covering [kg * KQ, kg * KQ + KQ), so that a lane reads four
-// k-steps of its B column with one 16-byte LDS read.  NCH is a compile-time
-// constant of the kernel, taken from a short list (rows are zero-extended up
-// to it), so the contraction unrolls into one straight run of LDS reads and
-// MFMAs.
-__host__ __device__ inline int nch_for(int dtype, int dim) {
-    if (dtype == ONNG_U8) {
-        const int need = (dim + 63) / 64;
-        return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
-    }
-    const int need = (dim + 15) / 16;
-    return need <= 2 ? 2 : need <= 4 ? 4 : need <= 6 ? 6 : need <= 7 ? 7 : need <= 8 ? 8
-           : need <= 12 ? 12 : 16;
-}
-
-struct TopkArgs {
-    const uint8_t *q;
-    int64_t q_pitch;
-    int64_t nq;
-    const uint8_t *b;         // base rows (or gathered candidate rows)
-    int64_t b_pitch;
-    int64_t nb;
-    const int32_t *b_ids;     // global id of each base row (null: the row index)
-    const void *qn;           // query norms (int32 or float), null for cosine
-    const void *bn;           // base norms
-    int32_t dim;
-    int32_t k;
-    int32_t kcap;             // list capacity per row (topk_kcap)
-    int32_t cb;               // candidate slots per row (topk_cb)
-    int32_t bm;               // query rows per block (16 per wave)
-    int32_t exclude_self;
-    int32_t rotate;           // rows and candidates are the same rows: start at the own tile
-    int32_t lds_pitch;        // bytes per staged base row
-    int32_t *out_ids;
-    void *out_d;
-    int32_t side_norms;       // stage the tile's base norms in LDS (L2 metrics)
-    int32_t splits;           // blocks sharing one row block's base tiles
-    int32_t tiles_per_split;
-    uint64_t *part;           // splits > 1: [nq][splits][k] keys of each part
-};
 
 // ---- per-row norms (int32 |x-128|^2 for u8, f32 |x|^2 otherwise) ----------
 __global__ void norms_u8_kernel(const uint8_t *x, int64_t pitch, int64_t n, int dim,
@@ -117,23 +66,6 @@ __global__ void gather_rows_kernel(const uint8_t *src, int64_t pitch, const int3
     uint8_t *d = dst + i * pitch;
     for (int64_t c = threadIdx.x * 16; c < pitch; c += blockDim.x * 16)
         *reinterpret_cast<uint4 *>(d + c) = *reinterpret_cast<const uint4 *>(s + c);
-}
-
-// 16 int8 values of (x - 128) at row bytes [c, c+16), zero past dim
-__device__ __forceinline__ i32x4 shifted16(const uint8_t *row, int c, int dim) {
-    i32x4 out;
-#pragma unroll
-    for (int w = 0; w < 4; w++) {
-        uint32_t v = 0;
-#pragma unroll
-        for (int b = 0; b < 4; b++) {
-            int idx = c + 4 * w + b;
-            uint32_t byte = idx < dim ? (uint32_t)(uint8_t)((int)row[idx] - 128) : 0u;
-            v |= byte << (8 * b);
-        }
-        out[w] = (int32_t)v;
-    }
-    return out;
 }
 
 template <int DT, int MT, int NCH>
@@ -537,16 +469,6 @@ int topk_splits(int64_t nq, int64_t nb, int bm) {
 }
 
 
-// Bytes of a staged row: what the MFMA operands read (u8: whole 64-byte
-// k-steps; f32: 4 k-groups of KQ components), rounded up to an odd number of
-// 16-byte chunks, which spreads the 16 rows read together over the LDS banks
-// (no more than two rows per bank group).
-int lds_pitch_for(int dtype, int32_t dim) {
-    int p = nch_for(dtype, dim) * 64;
-    if ((p / 16) % 2 == 0) p += 16;
-    return p;
-}
-
 template <int DT, int MT>
 const void *topk_fn_for(int nch) {
     if constexpr (DT == ONNG_U8) {
@@ -588,6 +510,14 @@ int topk_bm(int32_t k, int dtype, int32_t dim, int side_words) {
                                                                                             : 32;
 }
 
+// The wide u8 kernel takes over when its 256-row blocks alone fill the chip
+// (one per compute unit at least) and the rows fit two 64-byte k-steps.
+bool topk_use_wide(const onng_vectors *Q, int64_t nb, int32_t k) {
+    return Q->dtype == ONNG_U8 && nch_for(ONNG_U8, Q->dim) <= 2 && nb >= 16 * BN &&
+           Q->n >= (int64_t)WIDE_ROWS * device_cu_count() &&
+           wide_lds_bytes(lds_pitch_for(ONNG_U8, Q->dim), topk_kcap(k)) <= 64 * 1024;
+}
+
 }  // namespace
 
 size_t topk_ws_size(const onng_vectors *Q, const onng_vectors *B, int64_t n_cand, int32_t k) {
@@ -596,6 +526,11 @@ size_t topk_ws_size(const onng_vectors *Q, const onng_vectors *B, int64_t n_cand
     c.take<float>(Q->n);
     c.take<float>(nb);
     if (n_cand > 0) c.take<uint8_t>((size_t)nb * B->pitch_bytes);
+    if (topk_use_wide(Q, nb, k)) {
+        c.take<uint64_t>((size_t)Q->n * topk_kcap(k));
+        c.take<uint64_t>((size_t)Q->n * WIDE_CB);
+        return c.size() + 256;
+    }
     const int sp = topk_splits(Q->n, nb, topk_bm(k, Q->dtype, Q->dim, topk_side_words(Q->dtype, Q->metric, n_cand > 0)));
     if (sp > 1) c.take<uint64_t>((size_t)Q->n * sp * k);
     return c.size() + 256;
@@ -622,10 +557,11 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     }
     const bool u8 = Q->dtype == ONNG_U8;
     const int64_t nb = cand ? n_cand : B->n;
+    const bool wide = topk_use_wide(Q, nb, k);
     Carver c(ws);
     void *qn = c.take<float>(Q->n);
     void *bn = c.take<float>(nb);
-    const int sp = topk_splits(Q->n, nb, topk_bm(k, Q->dtype, Q->dim, topk_side_words(Q->dtype, Q->metric, cand != nullptr)));
+    const int sp = wide ? 1 : topk_splits(Q->n, nb, topk_bm(k, Q->dtype, Q->dim, topk_side_words(Q->dtype, Q->metric, cand != nullptr)));
     uint64_t *part = sp > 1 ? c.take<uint64_t>((size_t)Q->n * sp * k) : nullptr;
     const uint8_t *brows = static_cast<const uint8_t *>(B->data);
     if (cand && nb > 0) {
@@ -634,6 +570,8 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
                            B->pitch_bytes, cand, nb, g);
         brows = g;
     }
+    uint64_t *glist = wide ? c.take<uint64_t>((size_t)Q->n * topk_kcap(k)) : nullptr;
+    uint64_t *gcand = wide ? c.take<uint64_t>((size_t)Q->n * WIDE_CB) : nullptr;
     if (Q->n > 0) {
         if (u8)
             hipLaunchKernelGGL(norms_u8_kernel, dim3((unsigned)((Q->n + 3) / 4)), dim3(256), 0, st,
@@ -678,6 +616,13 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     a.lds_pitch = lds_pitch_for(Q->dtype, B->dim);
     a.out_ids = ids;
     a.out_d = dists;
+    if (wide) {
+        a.splits = 1;
+        a.tiles_per_split = (int)((nb + BN - 1) / BN);
+        a.part = nullptr;
+        a.rotate = (!cand && Q->data == B->data && Q->n == B->n) ? 1 : 0;
+        return launch_topk_wide(a, nch_for(ONNG_U8, Q->dim), glist, gcand, st);
+    }
     size_t lds = topk_lds_bytes(a.bm, a.kcap, a.cb, a.lds_pitch, side_words);
     if (lds > 160 * 1024) {
         set_error("onng_topk: k or dim too large for the on-chip tile");

@@ -57,6 +57,54 @@ def test_topk_u8_ragged(n, dim, k):
     assert np.array_equal(host(d), rd.astype(np.int32))
 
 
+WIDE_N = 70_001      # above 256 query rows per compute unit: the wide u8 kernel
+
+
+@pytest.mark.parametrize("dim,k,tie", [(128, 100, False), (100, 10, True), (40, 1, True),
+                                       (64, 256, False)])
+def test_topk_u8_wide_rows_sampled(dim, k, tie):
+    """From 65,536 query rows the u8 top-k runs 256 rows per block with the
+    rows' lists and candidate buffers in global memory.  Its kNN rows, at
+    dims with one and two 64-byte k-steps (zero-extended), k from 1 to 256
+    and heavy distance ties, equal the oracle's bit for bit on sampled rows,
+    the first and last rows, and the rows at block and tile edges."""
+    say("topk wide", dim, k, tie)
+    n = WIDE_N
+    x = dg.random_tie_u8(n, dim, 11) if tie else dg.random_vectors(n, dim, "u8", 12)
+    g = np.random.default_rng(dim + k)
+    rows = np.unique(np.concatenate([
+        np.arange(0, 80), np.arange(n - 150, n), [255, 256, 511, 512, 65535, 65536, 65792],
+        g.choice(n, 120, replace=False)])).astype(np.int32)
+    bv = orc.Vectors.from_array(x, orc.L2SQ)
+    rid, rd = orc.knn_graph(bv, k, rows=rows)
+    ids, d = api().build_knn(gpu_vectors(x, orc.L2SQ), k)
+    ids, d = host(ids), host(d)
+    assert np.array_equal(ids[rows], rid)
+    assert np.array_equal(d[rows], rd.astype(np.int32))
+    # every row is a valid top-k list: ascending (d, id), no self, no repeat
+    assert np.all(ids >= 0) and np.all(ids < n)
+    assert not np.any(ids == np.arange(n)[:, None])
+    key = d.astype(np.int64) * (1 << 32) + ids
+    assert np.all(np.diff(key, axis=1) > 0)
+
+
+def test_topk_u8_wide_candidate_list():
+    """The wide u8 kernel over a candidate list (gathered rows with their
+    global ids), as for seeds: sampled query rows equal the oracle's."""
+    say("topk wide candidate list")
+    x = dg.random_tie_u8(20_000, 128, 13, levels=5)
+    q = dg.random_tie_u8(WIDE_N, 128, 14, levels=5)
+    cand = np.sort(np.random.default_rng(5).choice(20_000, 3000, replace=False)).astype(np.int32)
+    rows = np.unique(np.concatenate([np.arange(0, 40), np.arange(WIDE_N - 40, WIDE_N),
+                                     np.random.default_rng(6).choice(WIDE_N, 100)]))
+    bv = orc.Vectors.from_array(x, orc.L2SQ)
+    qv = orc.Vectors.from_array(q[rows], orc.L2SQ)
+    sid, sd = orc.topk(qv, bv, 8, cand=cand)
+    ids, d = api().topk(gpu_vectors(q, orc.L2SQ), gpu_vectors(x, orc.L2SQ), 8, cand=to_dev(cand))
+    assert np.array_equal(host(ids)[rows], sid)
+    assert np.array_equal(host(d)[rows], sd.astype(np.int32))
+
+
 def test_topk_seeds_from_pivots_c1():
     P = c1_problem()
     say("seeds from pivots c1")
