@@ -803,19 +803,21 @@ def main():
 
     # The learned pipeline's setting (form and budget) follows a fixed rule,
     # so that every run, profiled or not, times the same configuration: the
-    # three-step form (longest predicted cost first, which shortens the batch
-    # tail), a cost-relative budget of 2x the predicted cost where the target
-    # is reachable with it (else none), and the largest scalar budget among
-    # the bisected ones (a cap on rare runaway queries).  --learned-select
-    # instead times a short pipelined run of every setting and keeps the
-    # fastest (a selection that favours settings whose short run was lucky).
-    def rule_pick(forms):
-        cand = [p_ for p_ in forms if not p_["single_pass"]] or forms
+    # fused form (no separate predict pass in the pipeline), the scalar
+    # budget of the plain pipeline at the same target (like for like), and a
+    # cost-relative budget of 2x the predicted cost where the target is
+    # reachable with it (else none).  --learned-select instead times a short
+    # pipelined run of every setting and keeps the fastest (a selection that
+    # favours settings whose short run was lucky).
+    def rule_pick(forms, tgt):
+        cand = [p_ for p_ in forms if p_["single_pass"]] or forms
+        pb = (result["plain_budget"][str(tgt)] or {}).get("max_dc", 0)
+        same_b = [p_ for p_ in cand if p_["max_dc"] == pb] or cand
         for fac in (2.0, 0.0):
-            got = [p_ for p_ in cand if abs(p_["max_dc_factor"] - fac) < 1e-9]
+            got = [p_ for p_ in same_b if abs(p_["max_dc_factor"] - fac) < 1e-9]
             if got:
-                return max(got, key=lambda p_: p_["max_dc"])
-        return max(cand, key=lambda p_: p_["qps"])
+                return got[0]
+        return max(same_b, key=lambda p_: p_["qps"])
 
     sel_steps = max(5, args.steps // 2)
     for tgt in (0.95, 0.99):
@@ -823,7 +825,7 @@ def main():
         if not forms:
             continue
         if not args.learned_select and not (tgt == 0.95 and args.learned_pick):
-            learned_pts[str(tgt)] = rule_pick(forms)
+            learned_pts[str(tgt)] = rule_pick(forms, tgt)
             pt = learned_pts[str(tgt)]
             log(f"learned setting at {tgt} by rule: {'fused' if pt['single_pass'] else '3-step'} "
                 f"b={pt['max_dc']} f={pt['max_dc_factor']:g} dc={pt['dc']:.0f}")
@@ -1102,8 +1104,8 @@ def main():
             "learned_single_pass": {str(t): single[t] for t in (0.95, 0.99)},
             "learned_setting": ("timed selection" if args.learned_select else
                                 "given (--learned-pick) at 0.95" if args.learned_pick else
-                                "fixed rule: three steps, cost-relative budget 2x where the "
-                                "target is reachable with it, largest scalar budget"),
+                                "fixed rule: fused form, the plain pipeline's scalar budget, "
+                                "cost-relative budget 2x where the target is reachable with it"),
             "launch_shapes": tuned,
         },
         "recall_at_timed_point": round(rec95, 4),
@@ -1163,11 +1165,17 @@ def build_only(args, torch, A, dg, cfg, xt, metric, dev):
     n = cfg.n_base
     ops = 2.0 * n * n * cfg.dim
     u8 = cfg.kind == "u8"
-    peak = 5000.0 if u8 else 157.3           # dense int8 POP/s x 1e3, f32 TFLOP/s
+    # float rows of at most 128 components at this size take the bf16 screen
+    # (exact f32 recompute of the survivors); its MFMAs run over 128 components
+    bf16 = not u8 and cfg.dim <= 128 and n >= 32768
+    peak = 5000.0 if u8 else 2500.0 if bf16 else 157.3   # dense int8 / bf16 / f32, x 1e12
     achieved = ops / (ms * 1e-3) / 1e12
     out = {"build": "exact kNN table", "workload": cfg.name, "n": n, "dim": cfg.dim,
-           "k": cfg.knn_k, "dtype": "u8 (int8 MFMA)" if u8 else "f32 (f32 MFMA)",
+           "k": cfg.knn_k,
+           "dtype": "u8 (int8 MFMA)" if u8 else ("f32 (bf16 MFMA screen, f32 recompute)" if bf16
+                                                 else "f32 (f32 MFMA)"),
            "ms_per_build": round(ms, 3), "ops_per_build": ops,
+           "mfma_ops_per_build": 2.0 * n * n * (128 if bf16 else cfg.dim),
            "achieved": round(achieved, 2), "peak": peak,
            "unit": "TOP/s" if u8 else "TFLOP/s", "frac": round(achieved / peak, 4),
            "reps": args.build_reps}

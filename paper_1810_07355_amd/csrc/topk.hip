@@ -512,6 +512,13 @@ int topk_bm(int32_t k, int dtype, int32_t dim, int side_words) {
 
 // The wide u8 kernel takes over when its 256-row blocks alone fill the chip
 // (one per compute unit at least) and the rows fit two 64-byte k-steps.
+// The bf16-screened f32 kernel: f32 rows of at most 128 components, its
+// 128-row blocks filling the chip.
+bool topk_use_wide_f32(const onng_vectors *Q, int64_t nb, int32_t k) {
+    return Q->dtype == ONNG_F32 && Q->dim <= FW_NCH * 32 && nb >= 16 * FW_BN &&
+           Q->n >= (int64_t)FW_ROWS * device_cu_count() && fw_lds_bytes(topk_kcap(k)) <= 64 * 1024;
+}
+
 bool topk_use_wide(const onng_vectors *Q, int64_t nb, int32_t k) {
     return Q->dtype == ONNG_U8 && nch_for(ONNG_U8, Q->dim) <= 2 && nb >= 16 * BN &&
            Q->n >= (int64_t)WIDE_ROWS * device_cu_count() &&
@@ -529,6 +536,14 @@ size_t topk_ws_size(const onng_vectors *Q, const onng_vectors *B, int64_t n_cand
     if (topk_use_wide(Q, nb, k)) {
         c.take<uint64_t>((size_t)Q->n * topk_kcap(k));
         c.take<uint64_t>((size_t)Q->n * WIDE_CB);
+        return c.size() + 256;
+    }
+    if (topk_use_wide_f32(Q, nb, k)) {
+        c.take<uint8_t>((size_t)nb * FW_NCH * 64);
+        c.take<uint8_t>((size_t)Q->n * FW_NCH * 64);
+        c.take<uint32_t>(1);
+        c.take<uint64_t>((size_t)Q->n * topk_kcap(k));
+        c.take<uint32_t>((size_t)Q->n * FW_CB);
         return c.size() + 256;
     }
     const int sp = topk_splits(Q->n, nb, topk_bm(k, Q->dtype, Q->dim, topk_side_words(Q->dtype, Q->metric, n_cand > 0)));
@@ -558,10 +573,11 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     const bool u8 = Q->dtype == ONNG_U8;
     const int64_t nb = cand ? n_cand : B->n;
     const bool wide = topk_use_wide(Q, nb, k);
+    const bool wide_f32 = !wide && topk_use_wide_f32(Q, nb, k);
     Carver c(ws);
     void *qn = c.take<float>(Q->n);
     void *bn = c.take<float>(nb);
-    const int sp = wide ? 1 : topk_splits(Q->n, nb, topk_bm(k, Q->dtype, Q->dim, topk_side_words(Q->dtype, Q->metric, cand != nullptr)));
+    const int sp = (wide || wide_f32) ? 1 : topk_splits(Q->n, nb, topk_bm(k, Q->dtype, Q->dim, topk_side_words(Q->dtype, Q->metric, cand != nullptr)));
     uint64_t *part = sp > 1 ? c.take<uint64_t>((size_t)Q->n * sp * k) : nullptr;
     const uint8_t *brows = static_cast<const uint8_t *>(B->data);
     if (cand && nb > 0) {
@@ -572,6 +588,16 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     }
     uint64_t *glist = wide ? c.take<uint64_t>((size_t)Q->n * topk_kcap(k)) : nullptr;
     uint64_t *gcand = wide ? c.take<uint64_t>((size_t)Q->n * WIDE_CB) : nullptr;
+    uint8_t *fbh = nullptr, *fqh = nullptr;
+    uint32_t *fymax = nullptr, *fcand = nullptr;
+    uint64_t *flist = nullptr;
+    if (wide_f32) {
+        fbh = c.take<uint8_t>((size_t)nb * FW_NCH * 64);
+        fqh = c.take<uint8_t>((size_t)Q->n * FW_NCH * 64);
+        fymax = c.take<uint32_t>(1);
+        flist = c.take<uint64_t>((size_t)Q->n * topk_kcap(k));
+        fcand = c.take<uint32_t>((size_t)Q->n * FW_CB);
+    }
     if (Q->n > 0) {
         if (u8)
             hipLaunchKernelGGL(norms_u8_kernel, dim3((unsigned)((Q->n + 3) / 4)), dim3(256), 0, st,
@@ -616,6 +642,15 @@ onng_status launch_topk(const onng_vectors *Q, const onng_vectors *B, const int3
     a.lds_pitch = lds_pitch_for(Q->dtype, B->dim);
     a.out_ids = ids;
     a.out_d = dists;
+    if (wide_f32) {
+        a.splits = 1;
+        a.tiles_per_split = (int)((nb + FW_BN - 1) / FW_BN);
+        a.part = nullptr;
+        const bool same = !cand && Q->data == B->data && Q->n == B->n &&
+                          Q->pitch_bytes == B->pitch_bytes;
+        a.rotate = same ? 1 : 0;
+        return launch_topk_wide_f32(a, Q, same, fqh, fbh, fymax, flist, fcand, st);
+    }
     if (wide) {
         a.splits = 1;
         a.tiles_per_split = (int)((nb + BN - 1) / BN);

@@ -120,5 +120,33 @@ __host__ __device__ inline size_t wide_lds_bytes(int lds_pitch, int kcap) {
 onng_status launch_topk_wide(const TopkArgs &a, int nch, uint64_t *glist, uint64_t *gcand,
                              hipStream_t st);
 
+// f32 rows of at most 128 components: the bf16-screened wide kernel.
+constexpr int FW_RB = 2;                  // 16-row blocks per wave
+constexpr int FW_ROWS = 4 * FW_RB * 16;   // query rows per block (4 waves)
+constexpr int FW_NCH = 4;                 // 64-byte k-steps: 128 bf16 components
+constexpr int FW_BN = 64;                 // base rows per staged tile
+constexpr int FW_CB = 2 * FW_BN;          // global candidate slots per row
+constexpr int FW_LDS_PITCH = FW_NCH * 64 + 16;   // odd count of 16-byte chunks
+// |dot(bf16(x), bf16(y)) in f32 - dot(x, y)| <= FW_C |x| |y| for at most 128
+// components: 2^-7 + 2^-16 for the rounded factors, 128 * 2^-24 for the sum.
+constexpr float FW_C = 0.0078278f + 1.6e-5f;
+
+struct FwRows {
+    const uint8_t *q;       // bf16 query rows
+    int64_t q_pitch;
+    const uint8_t *b;       // bf16 base rows
+    int64_t b_pitch;
+    const float *ymax;      // max |y| over the base rows
+};
+
+__host__ __device__ inline size_t fw_lds_bytes(int kcap) {
+    return (size_t)FW_BN * FW_LDS_PITCH + (size_t)FW_BN * 4 + (size_t)FW_ROWS * 20 +
+           (size_t)4 * (kcap + WAVE + 64) * 8;
+}
+
+onng_status launch_topk_wide_f32(const TopkArgs &a, const onng_vectors *Q, bool same_rows,
+                                 uint8_t *qh, uint8_t *bh, uint32_t *ymax, uint64_t *glist,
+                                 uint32_t *gcand, hipStream_t st);
+
 }  // namespace topk_detail
 }  // namespace onng

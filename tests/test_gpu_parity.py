@@ -1,6 +1,7 @@
 """GPU parity: every kernel of the path against the CPU oracle on the same
 seeded inputs.  u8 data is compared bit for bit (ids, distances, distance
 computations, expansions); float data by the margin rule."""
+import dataclasses
 import math
 
 import numpy as np
@@ -161,6 +162,70 @@ def test_topk_f32_cosine_and_l2():
                 for j in set(gi[r]) ^ set(rid[r]):
                     dj = full.or_dist(bv.ref, int(j), qv.ref, r)
                     assert abs(dj - kth) <= 1e-4 * max(abs(kth), floor), (kind, r, j)
+
+
+FW_N = 40_001       # above 128 query rows per compute unit: the bf16-screened f32 kernel
+
+
+@pytest.mark.parametrize("kind,dim,k", [("f32cos", 100, 100), ("f32l2", 96, 10),
+                                        ("f32l2", 37, 100), ("f32cos", 128, 1)])
+def test_topk_f32_wide_rows(kind, dim, k):
+    """From 32,768 query rows float top-k screens on bf16 matrix cores and
+    recomputes the survivors exactly in f32.  The screen is conservative
+    (its bound covers the bf16 rounding), so sampled rows, the first and last
+    rows and the rows at block edges meet the float rule of the general
+    kernel against the fp64 oracle: every distance within 1e-4 relative of
+    its id's exact distance (cosine floor 1e-2), sorted distances within 1e-4
+    of the oracle's, ids differing only at ties with the k-th within 1e-4."""
+    say("topk f32 wide", kind, dim, k)
+    metric = orc.COS if kind == "f32cos" else orc.L2SQ
+    cfg = dg.scaled(dg.PRESETS["c3" if kind == "f32cos" else "c5"], FW_N, 10,
+                    n_clusters=200)
+    cfg = dataclasses.replace(cfg, dim=dim)
+    x = dg.base(cfg)
+    g = np.random.default_rng(dim + k)
+    rows = np.unique(np.concatenate([np.arange(0, 40), np.arange(FW_N - 60, FW_N),
+                                     [127, 128, 32767, 32768, 32895],
+                                     g.choice(FW_N, 100, replace=False)])).astype(np.int32)
+    bv = orc.Vectors.from_array(x, metric)
+    rid, rd = orc.knn_graph(bv, k, rows=rows)
+    ids, d = api().build_knn(gpu_vectors(x, metric), k)
+    gi, gd = host(ids)[rows], host(d)[rows].astype(np.float64)
+    floor = 1e-2 if metric == orc.COS else 0.0
+    full = orc.lib()
+    ex = np.array([[full.or_dist(bv.ref, int(j), bv.ref, int(rows[r])) for j in gi[r]]
+                   for r in range(len(rows))])
+    assert np.all(gi >= 0) and not np.any(gi == rows[:, None])
+    assert np.all(np.abs(gd - ex) <= 1e-4 * np.maximum(np.abs(ex), floor))
+    assert np.all(np.abs(gd - rd) <= 1e-4 * np.maximum(np.abs(rd), floor))
+    for r in range(len(rows)):
+        diff = set(gi[r].tolist()) ^ set(rid[r].tolist())
+        kth = rd[r, -1]
+        for j in diff:
+            dj = full.or_dist(bv.ref, int(j), bv.ref, int(rows[r]))
+            assert abs(dj - kth) <= 1e-4 * max(abs(kth), floor), (r, j)
+
+
+def test_topk_f32_wide_candidate_list():
+    """The bf16-screened f32 kernel over a candidate list (gathered rows, ids
+    mapped back), cosine, k = 8 as for seeds."""
+    say("topk f32 wide candidate list")
+    cfg = dg.scaled(dg.PRESETS["c3"], 20_000, FW_N, n_clusters=100)
+    x, q = dg.base(cfg), dg.queries(cfg)
+    cand = np.sort(np.random.default_rng(7).choice(20_000, 3000, replace=False)).astype(np.int32)
+    rows = np.unique(np.concatenate([np.arange(0, 30), np.arange(FW_N - 30, FW_N),
+                                     np.random.default_rng(8).choice(FW_N, 100)]))
+    bv = orc.Vectors.from_array(x, orc.COS)
+    qv = orc.Vectors.from_array(q[rows], orc.COS)
+    sid, sd = orc.topk(qv, bv, 8, cand=cand)
+    ids, d = api().topk(gpu_vectors(q, orc.COS), gpu_vectors(x, orc.COS), 8, cand=to_dev(cand))
+    gi, gd = host(ids)[rows], host(d)[rows].astype(np.float64)
+    assert np.all(np.isin(gi, cand))
+    assert np.all(np.abs(gd - sd) <= 1e-4 * np.maximum(np.abs(sd), 1e-2))
+    for r in range(len(rows)):
+        for j in set(gi[r].tolist()) ^ set(sid[r].tolist()):
+            dj = orc.lib().or_dist(bv.ref, int(j), qv.ref, r)
+            assert abs(dj - sd[r, -1]) <= 1e-4 * max(abs(sd[r, -1]), 1e-2), (r, j)
 
 
 # ---------------------------------------------------------- adjustments
