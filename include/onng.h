@@ -535,6 +535,35 @@ onng_status onng_adam_step(float *p, const float *g, float *m, float *v, int64_t
  * kernel applies before z-scoring. */
 onng_status onng_feature_transform(const float *raw, int64_t n, int32_t metric, float *out,
                                    void *stream);
+/* Training support of the learned range (not part of the paper).
+ * onng_column_stats: mean[c] and std[c] of the columns of x [n][cols]
+ * (device), weighted by w [n][cols] when w is not NULL: mean = sum(w x) /
+ * sum(w), std = sqrt(sum(w (x - mean)^2) / sum(w)), sums in double; a std
+ * below 1e-6 is stored as 1 (the z-score the predictor applies, and the
+ * target scaling of training).  onng_standardize: out = (x - mean) / std per
+ * column (out may alias x).  onng_mlp_fold_output: turns the output layer of
+ * a network trained on targets (y - shift) / scale into the same network on
+ * y: w2[t][h] *= scale[t], b2[t] = b2[t] * scale[t] + shift[t] (in place).
+ * All asynchronous on the stream; ONNG_ERR_INVALID_ARG on negative sizes. */
+onng_status onng_column_stats(const float *x, const float *w, int64_t n, int32_t cols,
+                              float *mean, float *std_out, void *stream);
+onng_status onng_standardize(const float *x, int64_t n, int32_t cols, const float *mean,
+                             const float *std_in, float *out, void *stream);
+onng_status onng_mlp_fold_output(float *w2, float *b2, int32_t T, int32_t H, const float *scale,
+                                 const float *shift, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Degree-parameter loss (Section 2.6, Equation 2)                          */
+/* ------------------------------------------------------------------------ */
+
+/* L of Equation 2 from n >= 1 measured samples (precision p[i], mean
+ * distance computations c[i] > 0), host arrays: the samples sorted by
+ * precision, the trapezoidal rule over log10 c, divided by the samples'
+ * precision span (the printed normalisation by p_u - p_l, with the span the
+ * bracketed searches actually reach); with a zero span, the mean of log10 c.
+ * Host computation, no device work.  ONNG_ERR_INVALID_ARG when n < 1 or some
+ * c[i] <= 0. */
+onng_status onng_degree_loss(const double *p, const double *c, int32_t n, double *loss);
 
 /* ------------------------------------------------------------------------ */
 /* Launch tuning and graph capture (not part of the paper)                  */

@@ -108,6 +108,10 @@ PROTOS = {
     "onng_adam_step": (C.c_int, [P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_float,
                                  C.c_float, C.c_int32, P]),
     "onng_feature_transform": (C.c_int, [P, C.c_int64, C.c_int32, P, P]),
+    "onng_column_stats": (C.c_int, [P, P, C.c_int64, C.c_int32, P, P, P]),
+    "onng_standardize": (C.c_int, [P, C.c_int64, C.c_int32, P, P, P, P]),
+    "onng_mlp_fold_output": (C.c_int, [P, P, C.c_int32, C.c_int32, P, P, P]),
+    "onng_degree_loss": (C.c_int, [P, P, C.c_int32, P]),
     "onng_autotune_search": (C.c_int, [P, P, P, P, C.c_int32, P, P, P, P, P, C.c_size_t, P, P]),
     "onng_pipeline_create": (C.c_int, [P, P, P, P, C.c_int64, C.c_int32, P, P, P, P, P, P,
                                        C.c_size_t, P, P]),

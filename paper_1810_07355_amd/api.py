@@ -9,6 +9,7 @@ import ctypes as C
 import dataclasses
 import math
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -569,6 +570,43 @@ def feature_transform(raw: torch.Tensor, metric: int) -> torch.Tensor:
     L.call("onng_feature_transform", raw.data_ptr(), raw.shape[0], metric, out.data_ptr(),
            _stream())
     return out
+
+
+def column_stats(x: torch.Tensor, w: torch.Tensor | None = None):
+    """(mean, std) of the columns of x [n][cols] (f32, device), weighted by w."""
+    x = x.contiguous()
+    n, cols = x.shape
+    mean = torch.empty(cols, dtype=torch.float32, device=x.device)
+    std = torch.empty(cols, dtype=torch.float32, device=x.device)
+    wp = None if w is None else w.contiguous()
+    L.call("onng_column_stats", x.data_ptr(), None if wp is None else wp.data_ptr(), n, cols,
+           mean.data_ptr(), std.data_ptr(), _stream())
+    return mean, std
+
+
+def standardize(x: torch.Tensor, mean: torch.Tensor, std: torch.Tensor) -> torch.Tensor:
+    x = x.contiguous()
+    out = torch.empty_like(x)
+    L.call("onng_standardize", x.data_ptr(), x.shape[0], x.shape[1], mean.data_ptr(),
+           std.data_ptr(), out.data_ptr(), _stream())
+    return out
+
+
+def mlp_fold_output(W2: torch.Tensor, b2: torch.Tensor, scale: torch.Tensor,
+                    shift: torch.Tensor) -> None:
+    """In place: the output layer of a network trained on (y - shift) / scale
+    becomes the same network on y."""
+    L.call("onng_mlp_fold_output", W2.data_ptr(), b2.data_ptr(), W2.shape[0], W2.shape[1],
+           scale.data_ptr(), shift.data_ptr(), _stream())
+
+
+def degree_loss_from_samples(p, c) -> float:
+    """Equation 2's L from (precision, distance computations) samples (host)."""
+    pa = np.ascontiguousarray(p, dtype=np.float64)
+    ca = np.ascontiguousarray(c, dtype=np.float64)
+    out = C.c_double(0.0)
+    L.call("onng_degree_loss", pa.ctypes.data, ca.ctypes.data, len(pa), C.byref(out))
+    return out.value
 
 
 def to_bf16_bits(w: torch.Tensor) -> torch.Tensor:

@@ -67,6 +67,12 @@ onng_status mlp_backward_launch(const float *X, const float *target, const float
                                 void *ws, hipStream_t st);
 onng_status adam_launch(float *p, const float *g, float *m, float *v, int64_t n, float lr,
                         float b1, float b2, float eps, int32_t t, hipStream_t st);
+onng_status column_stats_launch(const float *x, const float *w, int64_t n, int32_t cols,
+                                float *mean, float *stdv, hipStream_t st);
+onng_status standardize_launch(const float *x, int64_t n, int32_t cols, const float *mean,
+                               const float *stdv, float *out, hipStream_t st);
+onng_status fold_output_launch(float *w2, float *b2, int32_t T, int32_t H, const float *scale,
+                               const float *shift, hipStream_t st);
 onng_status feature_transform_launch(const float *raw, int64_t n, int32_t metric, float *out,
                                      hipStream_t st);
 
@@ -1172,6 +1178,67 @@ onng_status onng_feature_transform(const float *raw, int64_t n, int32_t metric, 
     set_error("");
     ONNG_CHECK_ARG(n >= 0 && (n == 0 || (raw && out)), "bad arguments");
     return feature_transform_launch(raw, n, metric, out, as_stream(stream));
+}
+
+onng_status onng_column_stats(const float *x, const float *w, int64_t n, int32_t cols,
+                              float *mean, float *std_out, void *stream) {
+    set_error("");
+    if (n < 0 || cols < 0 || (cols > 0 && (!mean || !std_out)) || (n > 0 && cols > 0 && !x)) {
+        set_error("onng_column_stats: negative size or missing array");
+        return ONNG_ERR_INVALID_ARG;
+    }
+    return column_stats_launch(x, w, n, cols, mean, std_out, as_stream(stream));
+}
+
+onng_status onng_standardize(const float *x, int64_t n, int32_t cols, const float *mean,
+                             const float *std_in, float *out, void *stream) {
+    set_error("");
+    if (n < 0 || cols < 0 || (n > 0 && cols > 0 && (!x || !mean || !std_in || !out))) {
+        set_error("onng_standardize: negative size or missing array");
+        return ONNG_ERR_INVALID_ARG;
+    }
+    return standardize_launch(x, n, cols, mean, std_in, out, as_stream(stream));
+}
+
+onng_status onng_mlp_fold_output(float *w2, float *b2, int32_t T, int32_t H, const float *scale,
+                                 const float *shift, void *stream) {
+    set_error("");
+    if (T < 0 || H < 0 || (T > 0 && (!w2 || !b2 || !scale || !shift))) {
+        set_error("onng_mlp_fold_output: negative size or missing array");
+        return ONNG_ERR_INVALID_ARG;
+    }
+    return fold_output_launch(w2, b2, T, H, scale, shift, as_stream(stream));
+}
+
+onng_status onng_degree_loss(const double *p, const double *c, int32_t n, double *loss) {
+    set_error("");
+    if (n < 1 || !p || !c || !loss) {
+        set_error("onng_degree_loss: needs n >= 1 samples");
+        return ONNG_ERR_INVALID_ARG;
+    }
+    std::vector<int> ord(n);
+    for (int i = 0; i < n; i++) {
+        if (!(c[i] > 0.0)) {
+            set_error("onng_degree_loss: distance counts must be positive");
+            return ONNG_ERR_INVALID_ARG;
+        }
+        ord[i] = i;
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return p[a] < p[b]; });
+    const double span = p[ord[n - 1]] - p[ord[0]];
+    if (!(span > 0.0)) {
+        double s = 0.0;
+        for (int i = 0; i < n; i++) s += std::log10(c[i]);
+        *loss = s / n;
+        return ONNG_OK;
+    }
+    double area = 0.0;
+    for (int i = 0; i + 1 < n; i++) {
+        const int a = ord[i], b = ord[i + 1];
+        area += (p[b] - p[a]) * (std::log10(c[a]) + std::log10(c[b])) * 0.5;
+    }
+    *loss = area / span;
+    return ONNG_OK;
 }
 
 // ----------------------------------------------------------- pipeline -----

@@ -123,7 +123,97 @@ __global__ void feature_transform_kernel(const float *raw, int64_t n, int metric
     for (int t = 0; t < ONNG_NFEAT; t++) x[t] = feature_input(t, f[t], f[0], metric);
 }
 
+// Per-column mean and standard deviation of x [n][cols] (weights w [n][cols]
+// or all ones): one block per column, sums in double, the deviations in a
+// second pass over the column.  A standard deviation below 1e-6 becomes 1.
+__global__ void column_stats_kernel(const float *x, const float *w, int64_t n, int cols,
+                                    float *mean, float *stdv) {
+    __shared__ double red[2][256];
+    const int c = blockIdx.x;
+    double sw = 0.0, sx = 0.0;
+    for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+        const double wi = w ? (double)w[r * cols + c] : 1.0;
+        sw += wi;
+        sx += wi * (double)x[r * cols + c];
+    }
+    red[0][threadIdx.x] = sw;
+    red[1][threadIdx.x] = sx;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    const double tot = red[0][0] > 1e-12 ? red[0][0] : 1e-12;
+    const double mu = red[1][0] / tot;
+    __syncthreads();
+    double sv = 0.0;
+    for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+        const double wi = w ? (double)w[r * cols + c] : 1.0;
+        const double d = (double)x[r * cols + c] - mu;
+        sv += wi * d * d;
+    }
+    red[0][threadIdx.x] = sv;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) red[0][threadIdx.x] += red[0][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double sd = sqrt(red[0][0] / tot);
+        mean[c] = (float)mu;
+        stdv[c] = sd < 1e-6 ? 1.0f : (float)sd;
+    }
+}
+
+__global__ void standardize_kernel(const float *x, int64_t n, int cols, const float *mean,
+                                   const float *stdv, float *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * cols) return;
+    const int c = (int)(i % cols);
+    out[i] = (x[i] - mean[c]) / stdv[c];
+}
+
+// W2 [T][H] and b2 [T] of a network trained on targets (y - shift) / scale:
+// the same network on the targets themselves.
+__global__ void fold_output_kernel(float *w2, float *b2, int T, int H, const float *scale,
+                                   const float *shift) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < T * H) w2[i] *= scale[i / H];
+    if (i < T) b2[i] = b2[i] * scale[i] + shift[i];
+}
+
 }  // namespace
+
+onng_status column_stats_launch(const float *x, const float *w, int64_t n, int32_t cols,
+                                float *mean, float *stdv, hipStream_t st) {
+    if (cols == 0) return ONNG_OK;
+    hipLaunchKernelGGL(column_stats_kernel, dim3((unsigned)cols), dim3(256), 0, st, x, w, n, cols,
+                       mean, stdv);
+    ONNG_HIP(hipGetLastError());
+    return ONNG_OK;
+}
+
+onng_status standardize_launch(const float *x, int64_t n, int32_t cols, const float *mean,
+                               const float *stdv, float *out, hipStream_t st) {
+    if (n == 0 || cols == 0) return ONNG_OK;
+    hipLaunchKernelGGL(standardize_kernel, dim3((unsigned)((n * cols + 255) / 256)), dim3(256), 0,
+                       st, x, n, cols, mean, stdv, out);
+    ONNG_HIP(hipGetLastError());
+    return ONNG_OK;
+}
+
+onng_status fold_output_launch(float *w2, float *b2, int32_t T, int32_t H, const float *scale,
+                               const float *shift, hipStream_t st) {
+    if (T == 0) return ONNG_OK;
+    const int m = T * H > T ? T * H : T;
+    hipLaunchKernelGGL(fold_output_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, w2,
+                       b2, T, H, scale, shift);
+    ONNG_HIP(hipGetLastError());
+    return ONNG_OK;
+}
 
 size_t mlp_backward_ws(int32_t batch, int32_t H, int32_t T) {
     Carver c(nullptr);

@@ -85,24 +85,12 @@ def train_targets(features: torch.Tensor, Y: np.ndarray, metric: int, hidden: in
     only its own head; the standardisation then uses the weighted moments."""
     dev = features.device
     X = api.feature_transform(features.contiguous(), metric)
-    torch.cuda.synchronize()
-    xh = X.cpu().numpy().astype(np.float64)
-    mean = xh.mean(axis=0)
-    std = xh.std(axis=0)
-    std = np.where(std < 1e-6, 1.0, std)
-    Xz = torch.from_numpy(((xh - mean) / std).astype(np.float32)).to(dev)
-    Y = np.asarray(Y, dtype=np.float64)
-    Wn = None if weights is None else np.asarray(weights, dtype=np.float64)
-    if Wn is None:
-        ym = Y.mean(axis=0)
-        ys = Y.std(axis=0)
-    else:
-        tot = np.maximum(Wn.sum(axis=0), 1e-12)
-        ym = (Wn * Y).sum(axis=0) / tot
-        ys = np.sqrt((Wn * (Y - ym) ** 2).sum(axis=0) / tot)
-    ys = np.where(ys < 1e-6, 1.0, ys)
-    Yt = torch.from_numpy(((Y - ym) / ys).astype(np.float32)).to(dev)
-    Wt = None if Wn is None else torch.from_numpy(Wn.astype(np.float32)).to(dev)
+    mean_t, std_t = api.column_stats(X)
+    Xz = api.standardize(X, mean_t, std_t)
+    Yd = torch.from_numpy(np.asarray(Y, dtype=np.float32)).to(dev)
+    Wt = None if weights is None else torch.from_numpy(np.asarray(weights, dtype=np.float32)).to(dev)
+    ym_t, ys_t = api.column_stats(Yd, Wt)
+    Yt = api.standardize(Yd, ym_t, ys_t)
     n, F = Xz.shape
     T = Yt.shape[1]
     g = np.random.default_rng(seed)
@@ -133,12 +121,7 @@ def train_targets(features: torch.Tensor, Y: np.ndarray, metric: int, hidden: in
         if t % 100 == 0 or t == 1:
             losses.append(float(loss.item()))
     # fold the target standardisation into the last layer
-    ys_t = torch.from_numpy(ys.astype(np.float32)).to(dev)
-    ym_t = torch.from_numpy(ym.astype(np.float32)).to(dev)
-    W2 = (W2 * ys_t[:, None]).contiguous()
-    b2 = (b2 * ys_t + ym_t).contiguous()
-    mean_t = torch.from_numpy(mean.astype(np.float32)).to(dev)
-    std_t = torch.from_numpy(std.astype(np.float32)).to(dev)
+    api.mlp_fold_output(W2, b2, ys_t, ym_t)
     return Trained(W1, b1, W2, b2, mean_t, std_t, losses)
 
 

@@ -13,7 +13,8 @@ brackets).  L is minimised over (e_o, e_i) by hill climbing in steps of 5
 (Section 3.2), which the paper justifies by L being convex (Figure 3b).
 
 Host orchestration only: every search and graph build it drives runs in the
-library's kernels, through caller-supplied functions.
+library's kernels, through caller-supplied functions, and the loss of the
+samples is the library's onng_degree_loss.
 """
 from __future__ import annotations
 
@@ -69,14 +70,8 @@ def degree_loss(search: Callable[[float], Tuple[float, float]], p_l: float = 0.9
         e = el + (eu - el) * i / (samples - 1)
         p, c = search(e)
         pts.append((e, p, c))
-    srt = sorted(pts, key=lambda t: t[1])
-    span = srt[-1][1] - srt[0][1]
-    if span <= 0:
-        return sum(math.log10(c) for _, _, c in pts) / len(pts), pts
-    area = 0.0
-    for (_, pa, ca), (_, pb, cb) in zip(srt, srt[1:]):
-        area += (pb - pa) * (math.log10(ca) + math.log10(cb)) * 0.5
-    return area / span, pts
+    from . import api
+    return api.degree_loss_from_samples([p for _, p, _ in pts], [c for _, _, c in pts]), pts
 
 
 def hill_climb(loss: Callable[[int, int], float], e_o: int, e_i: int, step: int = 5,

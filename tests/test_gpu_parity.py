@@ -1054,6 +1054,40 @@ def test_ground_truth_and_recall_against_oracle():
 
 # ------------------------------------------------------------------- MLP
 
+def test_training_support_against_numpy():
+    """The learned range's training steps in the library: column statistics
+    (plain and weighted, a constant column taking std 1), z-scoring and the
+    fold of the target scaling into the output layer, against numpy in fp64."""
+    say("column stats, standardize, fold")
+    A = api()
+    g = np.random.default_rng(3)
+    x = (g.standard_normal((5000, 14)) * g.uniform(0.1, 10, 14) + g.uniform(-5, 5, 14)).astype(np.float32)
+    x[:, 3] = 2.5
+    w = (g.random((5000, 14)) < 0.3).astype(np.float32)
+    xd = x.astype(np.float64)
+    for ww in (None, w):
+        m, s = A.column_stats(to_dev(x), None if ww is None else to_dev(ww))
+        if ww is None:
+            mu, sd = xd.mean(0), xd.std(0)
+        else:
+            tot = ww.sum(0)
+            mu = (ww * xd).sum(0) / tot
+            sd = np.sqrt((ww * (xd - mu) ** 2).sum(0) / tot)
+        sd = np.where(sd < 1e-6, 1.0, sd)
+        assert np.allclose(host(m), mu, rtol=2e-6, atol=1e-5)
+        assert np.allclose(host(s), sd, rtol=2e-6, atol=1e-6)
+    z = A.standardize(to_dev(x), m, s)
+    assert np.allclose(host(z), (x - host(m)) / host(s), rtol=1e-5, atol=1e-5)
+    W2 = g.standard_normal((6, 64)).astype(np.float32)
+    b2 = g.standard_normal(6).astype(np.float32)
+    sc = g.uniform(0.5, 2, 6).astype(np.float32)
+    sh = g.standard_normal(6).astype(np.float32)
+    W2d, b2d = to_dev(W2), to_dev(b2)
+    A.mlp_fold_output(W2d, b2d, to_dev(sc), to_dev(sh))
+    assert np.allclose(host(W2d), W2 * sc[:, None], rtol=1e-6)
+    assert np.allclose(host(b2d), b2 * sc + sh, rtol=1e-6, atol=1e-6)
+
+
 def test_mlp_forward_backward_adam_against_oracle():
     say("mlp")
     A = api()
