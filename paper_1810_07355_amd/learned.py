@@ -1,11 +1,14 @@
 """Learned per-query search range: labels from eps sweeps, training of the
-2-layer perceptron with the library's forward/backward/Adam kernels, and
-calibration of the per-target shift.  Not part of the paper; the plain eps
-sweep stays the fallback and the judge of recall.
+2-layer perceptron with the library's kernels (column statistics and
+z-scoring, forward/backward, Adam, the fold of the target scaling into the
+output layer), and calibration of the per-target shift.  Not part of the
+paper; the plain eps sweep stays the fallback and the measure of recall.
 
-Model: 14 features of the state after the first expansion -> 64 ReLU ->
-one head per target recall, each predicting log10(eps + 0.01) of the
-smallest grid eps at which the query reaches that recall."""
+Model: 14 features of the state after the probe expansions -> 64 ReLU ->
+heads.  Log-eps mode: one head per target (or per (k, target) class), each
+predicting log10(eps + 0.01) of the smallest grid eps at which the query
+reaches that recall.  Curve mode: for each candidate range, the query's
+recall and log(1 + distance computations) there."""
 from __future__ import annotations
 
 import dataclasses
