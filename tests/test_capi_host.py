@@ -151,6 +151,36 @@ def test_other_entry_points_validate(lib):
     assert lib.onng_adjust_degree(p, p, 10, 4, L.U8, L.L2SQ, 2, 2, p, p, p, 80, C.byref(nnz), p,
                                   16, None) == L.ERR_WORKSPACE
     assert lib.onng_pipeline_destroy(None) == L.OK
+    assert lib.onng_column_stats(p, None, -1, 3, p, p, None) == L.ERR_INVALID_ARG
+    assert lib.onng_column_stats(p, None, 10, 3, None, p, None) == L.ERR_INVALID_ARG
+    assert lib.onng_standardize(p, 10, -2, p, p, p, None) == L.ERR_INVALID_ARG
+    assert lib.onng_mlp_fold_output(p, None, 3, 4, p, p, None) == L.ERR_INVALID_ARG
+
+
+def test_degree_loss_in_the_library(lib):
+    """onng_degree_loss (Equation 2 from samples, host code in the library):
+    log10 C linear in p integrates exactly by the trapezoid (L = the mean of
+    the end values); unsorted samples give the same L; a zero precision span
+    gives the mean of log10 C; bad inputs are rejected."""
+    import ctypes as Cc
+    out = Cc.c_double(0.0)
+    p = np.linspace(0.90, 0.98, 10)
+    c = 10.0 ** (2.0 + 10.0 * (p - 0.90))            # log10 C = 2 + 10 (p - 0.9)
+    perm = np.random.default_rng(1).permutation(10)
+    pa, ca = np.ascontiguousarray(p[perm]), np.ascontiguousarray(c[perm])
+    assert lib.onng_degree_loss(pa.ctypes.data, ca.ctypes.data, 10,
+                                    Cc.byref(out)) == L.OK
+    assert abs(out.value - (2.0 + 2.8) / 2) < 1e-12
+    flat = np.full(4, 0.95)
+    cc = np.array([10.0, 100.0, 1000.0, 10000.0])
+    assert lib.onng_degree_loss(flat.ctypes.data, cc.ctypes.data, 4,
+                                    Cc.byref(out)) == L.OK
+    assert abs(out.value - 2.5) < 1e-12
+    bad = np.array([1.0, 0.0])
+    assert lib.onng_degree_loss(flat.ctypes.data, bad.ctypes.data, 2,
+                                    Cc.byref(out)) == L.ERR_INVALID_ARG
+    assert lib.onng_degree_loss(flat.ctypes.data, cc.ctypes.data, 0,
+                                    Cc.byref(out)) == L.ERR_INVALID_ARG
 
 
 def test_recall_by_ids_definition():
