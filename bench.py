@@ -104,6 +104,9 @@ def parse():
                     help="launch a marker kernel right before and after the timed window "
                          "(to find it in a profiler trace)")
     ap.add_argument("--dump", default=None, help="save per-query sweep data (.npz)")
+    ap.add_argument("--learned-cost", choices=("time", "dc"), default="time",
+                    help="cost the learned range's curve heads predict: per-query search time "
+                         "(scaled to distance-computation units) or distance computations")
     ap.add_argument("--probe-hops", type=int, default=1,
                     help="expansions before the learned range is chosen")
     ap.add_argument("--summarize-trace", default=None, metavar="DIR",
@@ -596,7 +599,7 @@ def main():
     tgt_ids, _ = A.ground_truth(tq, base, K)
     tgt_np = to_orig(tgt_ids).cpu().numpy()
 
-    def label_sweep(vq, vseeds, vgt):
+    def label_sweep(vq, vseeds, vgt, extra=None):
         feats, recs, dcs = None, [], []
         for i, eps in enumerate(grid):
             req = A.SearchRequest(search_rows, graph, vq, vseeds, k=K, eps=eps, **idm,
@@ -608,27 +611,40 @@ def main():
                 feats = req.features.clone()
             recs.append(LR.recall_by_ids(req.ids.cpu().numpy(), vgt, K))
             dcs.append(req.dc.cpu().numpy())
+            if extra is not None:
+                extra.setdefault("hops", []).append(req.hops.cpu().numpy())
+                extra.setdefault("us", []).append(req.us.cpu().numpy())
         return feats, np.stack(recs), np.stack(dcs)
 
     t_lab = time.time()
-    feats, recalls, dcs = label_sweep(tq, tseeds, tgt_np)
+    sweep_extra = {}
+    feats, recalls, dcs = label_sweep(tq, tseeds, tgt_np, sweep_extra)
+    # the cost the curve heads learn: each query's search time (in units of
+    # distance computations), or its distance computations
+    cost_lab = (LR.time_cost(np.stack(sweep_extra["us"]), dcs) if args.learned_cost == "time"
+                else dcs)
     log(f"sweep of {len(grid)} ranges over {len(tq_np)} training queries in "
         f"{time.time() - t_lab:.1f} s")
     if args.dump:
-        hf, hr, hd = label_sweep(queries, seeds, gt)
+        test_extra = {}
+        hf, hr, hd = label_sweep(queries, seeds, gt, test_extra)
         np.savez_compressed(args.dump, grid=np.array(grid), train_feat=feats.cpu().numpy(),
                             train_recall10=np.rint(recalls * K).astype(np.uint8),
                             train_dc=np.minimum(dcs, 65535).astype(np.uint16),
+                            train_hops=np.stack(sweep_extra["hops"]).astype(np.int32),
+                            train_us=np.stack(sweep_extra["us"]).astype(np.float32),
                             test_feat=hf.cpu().numpy(),
                             test_recall10=np.rint(hr * K).astype(np.uint8),
-                            test_dc=np.minimum(hd, 65535).astype(np.uint16), probe_hops=PROBE)
+                            test_dc=np.minimum(hd, 65535).astype(np.uint16),
+                            test_hops=np.stack(test_extra["hops"]).astype(np.int32),
+                            test_us=np.stack(test_extra["us"]).astype(np.float32), probe_hops=PROBE)
         log("dumped sweep data to", args.dump)
     garr = np.array(grid)
     models = {}
     for tgt in (0.95, 0.99):
         idx = [int(np.argmin(np.abs(garr - e))) for e in cand[tgt]]
         t_tr = time.time()
-        models[tgt] = LR.train_targets(feats, LR.curve_targets(recalls, dcs, idx), metric,
+        models[tgt] = LR.train_targets(feats, LR.curve_targets(recalls, cost_lab, idx), metric,
                                        steps=4000)
         log(f"trained predictor for {tgt} in {time.time() - t_tr:.1f} s; loss "
             f"{models[tgt].losses[0]:.4f} -> {models[tgt].losses[-1]:.4f}")
@@ -805,15 +821,20 @@ def main():
     # so that every run, profiled or not, times the same configuration: the
     # fused form (no separate predict pass in the pipeline), the scalar
     # budget of the plain pipeline at the same target (like for like), and a
-    # cost-relative budget of 2x the predicted cost where the target is
-    # reachable with it (else none).  --learned-select instead times a short
-    # pipelined run of every setting and keeps the fastest (a selection that
-    # favours settings whose short run was lucky).
+    # cost-relative budget where the target is reachable with it (else none):
+    # 4x the predicted cost when the cost is search time (in distance-
+    # computation units, below the distance computations of the queries whose
+    # expansions yield many new nodes), 2x when it is distance computations.
+    # --learned-select instead times a short pipelined run of every setting
+    # and keeps the fastest (a selection that favours settings whose short
+    # run was lucky).
+    RULE_FACTOR = 4.0 if args.learned_cost == "time" else 2.0
+
     def rule_pick(forms, tgt):
         cand = [p_ for p_ in forms if p_["single_pass"]] or forms
         pb = (result["plain_budget"][str(tgt)] or {}).get("max_dc", 0)
         same_b = [p_ for p_ in cand if p_["max_dc"] == pb] or cand
-        for fac in (2.0, 0.0):
+        for fac in (RULE_FACTOR, 0.0):
             got = [p_ for p_ in same_b if abs(p_["max_dc_factor"] - fac) < 1e-9]
             if got:
                 return got[0]
@@ -1105,7 +1126,10 @@ def main():
             "learned_setting": ("timed selection" if args.learned_select else
                                 "given (--learned-pick) at 0.95" if args.learned_pick else
                                 "fixed rule: fused form, the plain pipeline's scalar budget, "
-                                "cost-relative budget 2x where the target is reachable with it"),
+                                f"cost-relative budget {RULE_FACTOR:g}x where the target is "
+                                "reachable with it"),
+            "learned_cost": ("per-query search time in distance-computation units"
+                             if args.learned_cost == "time" else "distance computations"),
             "launch_shapes": tuned,
         },
         "recall_at_timed_point": round(rec95, 4),

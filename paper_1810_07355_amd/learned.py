@@ -8,7 +8,8 @@ Model: 14 features of the state after the probe expansions -> 64 ReLU ->
 heads.  Log-eps mode: one head per target (or per (k, target) class), each
 predicting log10(eps + 0.01) of the smallest grid eps at which the query
 reaches that recall.  Curve mode: for each candidate range, the query's
-recall and log(1 + distance computations) there."""
+recall and log(1 + cost) there, the cost being its distance computations or
+its search time (time_cost)."""
 from __future__ import annotations
 
 import dataclasses
@@ -133,12 +134,27 @@ def train(features: torch.Tensor, labels: np.ndarray, metric: int, **kw) -> Trai
     return train_targets(features, eps_to_target(labels), metric, **kw)
 
 
-def curve_targets(recalls: np.ndarray, dcs: np.ndarray, cand_idx) -> np.ndarray:
-    """[n, 2G]: recall at each candidate range, then log(1 + distance
-    computations) there (recalls, dcs: [n_eps, n])."""
+def curve_targets(recalls: np.ndarray, cost: np.ndarray, cand_idx) -> np.ndarray:
+    """[n, 2G]: recall at each candidate range, then log(1 + cost) there
+    (recalls, cost: [n_eps, n]; the cost is the distance computations, or
+    time_cost of the queries' search times)."""
     cand_idx = list(cand_idx)
-    return np.concatenate([recalls[cand_idx].T, np.log1p(dcs[cand_idx].T.astype(np.float64))],
+    return np.concatenate([recalls[cand_idx].T, np.log1p(cost[cand_idx].T.astype(np.float64))],
                           axis=1)
+
+
+def time_cost(us: np.ndarray, dcs: np.ndarray) -> np.ndarray:
+    """Per-query search time in units of distance computations: each
+    query's device time at each range (the search's own per-query clock),
+    scaled so that the sweep's total equals its total distance computations.
+    A query's time follows its expansions about as much as its distance
+    computations (each expansion costs a fixed sequence of marks, sorts and
+    merges), so a range chosen by time favours queries whose expansions still
+    yield new nodes; the scale keeps a budget relative to the cost in the
+    units of max_dc."""
+    us = np.asarray(us, dtype=np.float64)
+    scale = float(np.asarray(dcs, dtype=np.float64).sum()) / max(float(us.sum()), 1e-30)
+    return us * scale
 
 
 def calibrate(run_recall, target: float, lo: float = -1.0, hi: float = 1.0, iters: int = 9,

@@ -334,6 +334,88 @@ def test_learned_three_step_pipeline_timed_setting_matches_oracle():
     pl.close()
 
 
+def test_learned_fused_search_timed_setting_matches_oracle():
+    """The benchmark's timed form of the learned range: one search per query
+    with the curve predictor fused after the probe expansion, a scalar budget
+    and, from the switch on, a budget of max(64, int32(4.0 * predicted
+    cost)), fp8 rows with the scale in the row, cosine, and the f32 rerank of
+    the 4k best; eager and as the captured single-pass pipeline.  The oracle:
+    its features of the decoded rows -> its predictor -> Algorithm 1 that
+    switches to that range after the probe, under the smaller budget -> its
+    pool -> fp64 rerank on the f32 rows."""
+    C = cos_problem()
+    A, Lb = api(), L()
+    g = np.random.default_rng(23)
+    nq = len(C["q"])
+    feat_ref = orc.search(C["lbv"], C["off"], C["nb"], C["qv"], C["seeds"], 10, 0.0, orc.INF_EP,
+                          eps1=np.inf, ep1=EPF, probe_hops=1, want_features=True,
+                          probe_only=True)
+    cand = np.array([0.05, 0.07, 0.09, 0.11, 0.13, 0.16], np.float32)
+    G = len(cand)
+    b2 = [0.5 + 0.08 * i for i in range(G)] + [5.0 + 0.3 * i for i in range(G)]
+    lam = np.float32(10.0 ** -2.5)
+    pred, hw = random_predictor(2 * G, Lb.PRED_CURVE, g, feat_ref["feat"], b2, orc.COS,
+                                eps_min=0.0, eps_max=1.0, e0=30.0, we=20.0,
+                                eps_cand=to_dev(cand), lam=float(lam))
+    factor = 4.0
+    kw = dict(k=10, eps=0.0, ep=Lb.EP_INF, two_phase=True, ep_first=EPF, probe_hops=1,
+              predictor=pred, rerank_base=C["B"], pool_factor=4)
+    say("learned fused search, no budget")
+    free = A.search(C["lp"], C["G"], C["Q"], to_dev(C["seeds"]), **kw)
+    torch.cuda.synchronize()
+    scalar = int(np.median(host(free.dc)))     # binds for about half the queries
+    kw.update(max_dc=scalar, max_dc_factor=factor)
+    say("learned fused search, scalar budget", scalar, "and factor", factor)
+    r = A.search(C["lp"], C["G"], C["Q"], to_dev(C["seeds"]), **kw)
+    torch.cuda.synchronize()
+    ge, gp, gc = host(r.eps_used), host(r.ep_used), host(r.cost)
+    pref = orc.predict(feat_ref["feat"], orc.COS, **hw, mode="curve", eps_cand=cand, lam=lam,
+                       eps_min=0.0, eps_max=1.0, e0=30.0, we=20.0)
+    first_ok = feat_ref["margin"] >= TOL          # the probe expansion took the same decisions
+    pm = dict(pref)
+    pm["margin"] = np.where(first_ok, pref["margin"], 0.0)
+    sure_pred = _check_predictor(ge, gp, gc, pm, "curve")
+    say("predictor ties:", int((~sure_pred).sum()), "of", nq)
+    assert sure_pred.sum() >= 20
+    assert np.mean(ge.astype(np.float64) == pref["eps"]) >= 0.9
+    assert len(np.unique(ge)) > 1
+    # the budget after the switch: the smaller of the scalar one and the
+    # kernel's f32 product of the factor and its cost, truncated to int32
+    rel = np.maximum(64, (np.float32(factor) * gc.astype(np.float32)).astype(np.int64))
+    bud = np.minimum(np.minimum(rel, 2 ** 31 - 1), scalar).astype(np.int32)
+    hit = (host(r.flags) & Lb.QF_BUDGET) != 0
+    say("queries that spent the budget:", int(hit.sum()), "; the relative one binding:",
+        int((hit & (rel < scalar)).sum()))
+    assert hit.sum() >= 10
+    eps_q = np.where(sure_pred, pref["eps"], ge).astype(np.float32)
+    ep_q = np.where(sure_pred, pref["ep"], gp).astype(np.uint32)
+    ref = orc.search(C["lbv"], C["off"], C["nb"], C["qv"], C["seeds"], 10, eps_q, ep_q,
+                     eps1=np.inf, ep1=EPF, probe_hops=1, max_dc=bud, pool_k=40)
+    rid, rd, gap = _pool_rerank_ref(C, ref, 40)
+    gi, gd = host(r.ids), host(r.dists)
+    sure = sure_pred & (ref["margin"] >= TOL) & (ref["pool_margin"] >= TOL) & (gap >= TOL)
+    same = np.array([set(a.tolist()) == set(b.tolist()) for a, b in zip(gi, rid)])
+    say("queries certain end to end:", int(sure.sum()), "of", nq, "; same ids:", int(same.sum()))
+    assert sure.sum() >= 5
+    assert np.all(same[sure]), np.flatnonzero(sure & ~same)
+    assert same.mean() >= 0.85
+    for qi in np.flatnonzero(same):
+        assert np.all(_rel_close(np.sort(gd[qi]), rd[qi], tol=1e-5))
+    assert np.array_equal(host(r.dc)[sure], ref["dc"][sure])
+    # the captured single-pass pipeline equals the eager search
+    say("learned fused search (captured)")
+    piv = to_dev(dg.pivots(C["cfg"], 256))
+    pl = A.Pipeline(C["lp"], C["G"], C["Q"], piv, 8, single_pass=True, **kw)
+    for rep in range(2):
+        out = pl.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(pl.seeds), C["seeds"])
+        assert np.array_equal(host(out.ids), gi)
+        assert np.array_equal(host(out.dists), gd)
+        out.ids.fill_(-9)
+    pl.close()
+
+
 def test_label_sweep_matches_oracle_u8():
     """The sweep that labels the training queries (every range of a grid,
     probe expansion with an unlimited range first) on 1,000 u8 training
