@@ -286,9 +286,12 @@ onng_status onng_vptree_seeds(const onng_vectors *base, const onng_vptree *tree,
  *    log10(eps + 0.01); eps = 10^(y + shift[head]) - 0.01.
  *  mode 1 (ONNG_PRED_CURVE): n_cand candidate ranges eps_cand[g]; head g
  *    predicts the query's recall at eps_cand[g] and head n_cand + g the
- *    log(1 + distance computations) there; the query takes the candidate
- *    maximising recall_g - lambda * (exp(y_{n_cand+g}) - 1), with lambda
- *    from lambda_per_query[q] when given.
+ *    log(1 + cost) there, the cost in distance-computation units (the count
+ *    itself, or a search time scaled to it: the library only evaluates it);
+ *    the query takes the candidate maximising
+ *    recall_g - lambda * (exp(y_{n_cand+g}) - 1), with lambda from
+ *    lambda_per_query[q] when given.  With max_dc_factor > 0 the budget
+ *    after the switch is min(max_dc, max(64, int32(max_dc_factor * cost))).
  * Weights are bf16 (w1: [H][F], w2: [T][H]); biases, feature statistics,
  * shifts and candidates are f32.  The chosen eps is clamped to
  * [eps_min, eps_max]; e_p follows Equation 1 with (e0, we) unless we < 0. */
@@ -310,7 +313,7 @@ typedef struct {
     int32_t mode;                  /* ONNG_PRED_LOG_EPS or ONNG_PRED_CURVE */
     int32_t n_cand;                /* mode 1: candidates, n_heads = 2 * n_cand, <= 8 */
     const float *eps_cand;         /* mode 1: [n_cand] candidate search ranges */
-    float lambda;                  /* mode 1: price of one distance computation in recall */
+    float lambda;                  /* mode 1: price of one unit of cost in recall */
     const float *lambda_per_query; /* mode 1: [nq] or NULL */
 } onng_predictor;
 
@@ -382,9 +385,9 @@ typedef struct {
     const int32_t *max_dc_per_query;
     /* With a learned range (range_from, or the predictor in curve mode):
      * when > 0, each query's budget is further limited to
-     * max(64, (int32)(max_dc_factor * its predicted distance computations)),
-     * the product taken in fp32, so that a query far costlier than predicted
-     * is cut short. */
+     * max(64, (int32)(max_dc_factor * its predicted cost)), the cost in
+     * distance-computation units and the product taken in fp32, so that a
+     * query far costlier than predicted is cut short. */
     float max_dc_factor;
     /* Output ids are id_map[id] when non-NULL (e.g. the permutation of
      * onng_locality_order, to report original row ids). */

@@ -259,8 +259,10 @@ def adjust_path(g: Graph, dtype: int, metric: int) -> Graph:
 class Predictor:
     """Weights of the search-range predictor (bf16 matrices, f32 vectors).
     mode L.PRED_LOG_EPS: head `head` predicts log10(eps + 0.01) (+ shift).
-    mode L.PRED_CURVE: heads [0, G) recall and [G, 2G) log(1 + distance
-    computations) at eps_cand[g]; the query takes argmax recall - lambda*cost."""
+    mode L.PRED_CURVE: heads [0, G) recall and [G, 2G) log(1 + cost) at
+    eps_cand[g] (the cost in distance-computation units: the count itself, or
+    the query's search time scaled to it); the query takes argmax recall -
+    lambda*cost."""
     w1_bf16: torch.Tensor
     b1: torch.Tensor
     w2_bf16: torch.Tensor
