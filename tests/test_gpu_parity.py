@@ -138,15 +138,23 @@ def test_topk_u8_list_and_buffer_sizes(k):
     assert np.array_equal(host(d), rd.astype(np.int32))
 
 
-def test_topk_f32_cosine_and_l2():
+@pytest.mark.parametrize("k,use_cand", [(20, False), (8, True), (3, False)])
+def test_topk_f32_cosine_and_l2(k, use_cand):
+    """k = 20 (lists merged per row), k = 8 over a candidate list (the seeding's
+    shape) and k = 3 (lists of at most 8 keys, flushed after every tile)."""
     for kind, metric in [("f32cos", orc.COS), ("f32l2", orc.L2SQ)]:
-        say("topk float", kind)
+        say("topk float", kind, "k", k, "candidates" if use_cand else "")
         cfg = dg.scaled(dg.PRESETS["c3" if kind == "f32cos" else "c5"], 3000, 40, n_clusters=30)
         x, q = dg.base(cfg), dg.queries(cfg)
         bv, qv = orc.Vectors.from_array(x, metric), orc.Vectors.from_array(q, metric)
-        rid, rd = orc.topk(qv, bv, 20)
-        ids, d = api().topk(gpu_vectors(q, metric), gpu_vectors(x, metric), 20)
+        cand = (np.random.default_rng(k).choice(3000, 1999, replace=False).astype(np.int32)
+                if use_cand else None)
+        rid, rd = orc.topk(qv, bv, k, cand=cand)
+        ids, d = api().topk(gpu_vectors(q, metric), gpu_vectors(x, metric), k,
+                            cand=None if cand is None else to_dev(cand))
         gi, gd = host(ids), host(d)
+        if cand is not None:
+            assert np.all(np.isin(gi, cand))
         # every returned distance within 1e-4 relative of the exact fp64
         # distance of its id (cosine: floor 1e-2 against cancellation near 0)
         floor = 1e-2 if metric == orc.COS else 0.0
