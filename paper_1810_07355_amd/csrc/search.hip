@@ -784,27 +784,50 @@ search_kernel(SearchKArgs a) {
                 if (c0 + lane < npool) lds.ids[lane] = (uint32_t)lds.pool[c0 + lane];
                 wave_sync();
                 int u = min(WAVE, npool - c0);
-                for (int r0 = 0; r0 < u; r0 += 4) {
-                    int row = r0 + (lane >> 4);
-                    int pp = lane & 15;
+                // 16 rows per pass, 4 lanes per row; a lane reads 16-byte
+                // pieces pp, pp + 4, ... of its row, up to 8 at once, so that a
+                // pass waits for memory once (rows of up to 128 components)
+                const int pp = lane & 3;
+                const int n4 = (a.dim + 3) >> 2;
+                const float4 *qf4 = reinterpret_cast<const float4 *>(qrow);
+                for (int r0 = 0; r0 < u; r0 += 16) {
+                    const int row = r0 + (lane >> 2);
+                    const bool rv = row < u;
+                    const uint32_t id = rv ? lds.ids[row] : 0u;
+                    const float4 *xr4 =
+                        reinterpret_cast<const float4 *>(a.rr_base + (size_t)id * a.rr_pitch);
                     float acc = 0.0f;
-                    uint32_t id = 0;
-                    if (row < u) {
-                        id = lds.ids[row];
-                        const float *xr =
-                            reinterpret_cast<const float *>(a.rr_base + (size_t)id * a.rr_pitch);
-                        const float *qf = reinterpret_cast<const float *>(qrow);
-                        for (int c = pp; c < a.dim; c += 16) {
-                            if constexpr (MT == ONNG_L2SQ) {
-                                float df = xr[c] - qf[c];
-                                acc = fmaf(df, df, acc);
-                            } else {
-                                acc = fmaf(xr[c], qf[c], acc);
+                    for (int j0 = 0; j0 < n4; j0 += 32) {
+                        float4 xv[8], qv[8];
+#pragma unroll
+                        for (int t = 0; t < 8; t++) {
+                            const int c4 = j0 + pp + 4 * t;
+                            const bool in = rv && c4 < n4;
+                            xv[t] = in ? xr4[c4] : float4{0.0f, 0.0f, 0.0f, 0.0f};
+                            qv[t] = in ? qf4[c4] : float4{0.0f, 0.0f, 0.0f, 0.0f};
+                        }
+#pragma unroll
+                        for (int t = 0; t < 8; t++) {
+                            const int c = 4 * (j0 + pp + 4 * t);
+                            const float xs[4] = {xv[t].x, xv[t].y, xv[t].z, xv[t].w};
+                            const float qs[4] = {qv[t].x, qv[t].y, qv[t].z, qv[t].w};
+#pragma unroll
+                            for (int e = 0; e < 4; e++) {
+                                // components past dim (a row's padding) count as zero
+                                const float xe = c + e < a.dim ? xs[e] : 0.0f;
+                                const float qe = c + e < a.dim ? qs[e] : 0.0f;
+                                if constexpr (MT == ONNG_L2SQ) {
+                                    const float df = xe - qe;
+                                    acc = fmaf(df, df, acc);
+                                } else {
+                                    acc = fmaf(xe, qe, acc);
+                                }
                             }
                         }
                     }
-                    for (int m = 8; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
-                    if (row < u && pp == 0) {
+                    acc += __shfl_xor(acc, 1);
+                    acc += __shfl_xor(acc, 2);
+                    if (rv && pp == 0) {
                         float d = MT == ONNG_COSINE ? 1.0f - acc : acc;
                         lds.stage2[row] = make_key(ord_f32(d), id);
                     }
