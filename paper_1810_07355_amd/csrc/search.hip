@@ -887,7 +887,18 @@ search_kernel(SearchKArgs a) {
         if (log_n > 0) {
             __threadfence_block();   // the log was written by other lanes
             if (log_n <= a.vlog_cap) {
-                for (int i = lane; i < log_n; i += WAVE) gbits[(uint32_t)vlog[i]] = 0u;
+                // eight log entries per lane in flight, then their stores
+                for (int i0 = 0; i0 < log_n; i0 += 8 * WAVE) {
+                    int32_t wd[8];
+#pragma unroll
+                    for (int t = 0; t < 8; t++) {
+                        const int i = i0 + t * WAVE + lane;
+                        wd[t] = i < log_n ? vlog[i] : -1;
+                    }
+#pragma unroll
+                    for (int t = 0; t < 8; t++)
+                        if (wd[t] >= 0) gbits[(uint32_t)wd[t]] = 0u;
+                }
             } else {
                 u32x4 *g4 = reinterpret_cast<u32x4 *>(gbits);
                 for (int64_t i = lane; i < a.gbits_words / 4; i += WAVE) g4[i] = u32x4{0, 0, 0, 0};
