@@ -145,6 +145,33 @@ __global__ void __launch_bounds__(256) topk_kernel(TopkArgs a) {
         if (n == 0) return;
         uint64_t *lst = lists + (size_t)lr * a.kcap;
         int nl = uni(nlist[lr]);
+        if (a.kcap <= 16) {
+            // short lists (k <= 16): the first kcap lanes hold the list (none
+            // while it is empty), the other lanes candidates; one sort of the
+            // 64 lanes, the first kcap stay (no merge through LDS)
+            const int kl = a.kcap;
+            for (int c0 = 0; c0 < n;) {
+                const int lo = nl == 0 ? 0 : kl;
+                uint64_t key = KEY_MAX;
+                if (lane < lo) {
+                    if (lane < nl) key = lst[lane];
+                } else if (c0 + lane - lo < n) {
+                    key = cands[(size_t)lr * a.cb + c0 + lane - lo];
+                }
+                key = wave_sort(key, WAVE);
+                nl = min(nl + min(WAVE - lo, n - c0), a.k);
+                if (lane < kl) lst[lane] = key;
+                wave_sync();
+                c0 += WAVE - lo;
+            }
+            if (lane == 0) {
+                cnt[lr] = 0;
+                nlist[lr] = nl;
+                tau[lr] = nl == a.k ? lst[a.k - 1] : KEY_MAX;
+            }
+            wave_sync();
+            return;
+        }
         for (int c0 = 0; c0 < n; c0 += WAVE) {
             uint64_t key = c0 + lane < n ? cands[(size_t)lr * a.cb + c0 + lane] : KEY_MAX;
             int nb = min(WAVE, n - c0);
