@@ -1006,6 +1006,48 @@ def test_search_low_precision_against_decoded_oracle(dt):
         assert rec_rr >= rec_gpu - 1e-9
 
 
+@pytest.mark.parametrize("dim,kind", [(37, "f32cos"), (130, "f32l2")])
+def test_fused_rerank_odd_dims_ignores_row_padding(dim, kind):
+    """The fused rerank reads its f32 rows and the query in 16-byte pieces and
+    counts components past dim as zero: with rows and queries whose padding
+    holds garbage (dim 37: a partial last piece; dim 130: two rounds of
+    pieces and a partial one) the results equal those over zero padding, and
+    every returned distance is the exact distance of its id."""
+    A, Lb = api(), L()
+    metric = orc.COS if kind == "f32cos" else orc.L2SQ
+    lm = Lb.COSINE if kind == "f32cos" else Lb.L2SQ
+    x = dg.random_vectors(3000, dim, kind, 31 + dim)
+    q = dg.random_vectors(60, dim, kind, 32 + dim)
+    say("fused rerank, padding, dim", dim, kind)
+    B = gpu_vectors(x, metric)
+    ids, d = A.build_knn(B, 16)
+    graph = A.adjust_path(A.adjust_degree(ids, d, B.dtype, lm, 8, 16), B.dtype, lm)
+    Q = gpu_vectors(q, metric)
+    seeds, _ = A.topk(Q, B, 8)
+    lp = A.encode(B.data[:, :dim].contiguous(), Lb.F16, lm)
+
+    def padded(v, fill):
+        cols = (dim + 3) // 4 * 4 + 4              # at least one padding column
+        buf = torch.full((v.shape[0], cols), fill, dtype=torch.float32, device=dev())
+        buf[:, :dim] = to_dev(v)
+        return A.Vectors(buf, Lb.F32, lm, dim)
+
+    out = {}
+    for fill in (0.0, 7.5):
+        r = A.search(lp, graph, padded(q, fill), seeds, k=10, eps=0.1,
+                     rerank_base=padded(x, fill), pool_factor=4)
+        out[fill] = (host(r.ids), host(r.dists))
+    assert np.array_equal(out[0.0][0], out[7.5][0])
+    assert np.array_equal(out[0.0][1], out[7.5][1])
+    bv, qv = orc.Vectors.from_array(x, metric), orc.Vectors.from_array(q, metric)
+    gi, gd = out[7.5]
+    assert (gi >= 0).all()
+    for qi in range(len(q)):
+        for t in range(10):
+            exact = orc.lib().or_dist(bv.ref, int(gi[qi, t]), qv.ref, qi)
+            assert abs(gd[qi, t] - exact) <= 1e-5 * max(1.0, abs(exact))
+
+
 def test_rerank_standalone_matches_oracle():
     say("rerank")
     A = api()
