@@ -200,3 +200,23 @@ def test_recall_by_ids_definition():
     rep = [sum(1 for x in a[i].tolist() if x in set(b[i].tolist())) for i in range(20)]
     assert np.allclose(LR.recall_by_ids(a, b, 10) * 10, rep)
     assert all(r >= u for r, u in zip(rep, brute))
+
+
+def test_time_cost_and_curve_targets():
+    """The curve heads' time cost: each query's time at each range, scaled so
+    that the sweep's total equals its total distance computations (a
+    per-query ratio of times is kept); curve targets put the recalls of the
+    candidate ranges first, then log(1 + cost)."""
+    from paper_1810_07355_amd import learned as LR
+    us = np.array([[10.0, 30.0, 0.0], [20.0, 40.0, 100.0]])
+    dcs = np.array([[100, 300, 50], [200, 350, 1000]])
+    c = LR.time_cost(us, dcs)
+    assert c.shape == us.shape
+    assert np.isclose(c.sum(), dcs.sum())
+    assert np.allclose(c / c.sum(), us / us.sum())
+    assert c[0, 2] == 0.0
+    rec = np.array([[0.5, 0.9, 1.0], [0.7, 1.0, 1.0]])
+    t = LR.curve_targets(rec, c, [1, 0])
+    assert t.shape == (3, 4)
+    assert np.allclose(t[:, :2], rec[[1, 0]].T)
+    assert np.allclose(t[:, 2:], np.log1p(c[[1, 0]].T))
