@@ -172,6 +172,43 @@ def test_topk_f32_cosine_and_l2(k, use_cand):
                     assert abs(dj - kth) <= 1e-4 * max(abs(kth), floor), (kind, r, j)
 
 
+@pytest.mark.parametrize("kind,k", [("u8", 8), ("u8", 16), ("f32cos", 8), ("f32l2", 1),
+                                    ("f32cos", 16)])
+def test_topk_long_candidate_list(kind, k):
+    """Top-k over a long candidate list (the seeds' shape: thousands of
+    pivots, k <= 16, few query rows, so the candidate tiles are split over
+    several blocks and the parts merged).  u8 results, on tie-heavy data,
+    are bit-exact against the oracle; float ones meet the float rule (ids
+    differ only at ties within 1e-4)."""
+    say("topk long candidate list", kind, k)
+    metric = orc.COS if kind == "f32cos" else orc.L2SQ
+    if kind == "u8":
+        x = dg.random_tie_u8(20000, 48, 7)
+        q = dg.random_tie_u8(300, 48, 8)
+    else:
+        cfg = dg.scaled(dg.PRESETS["c3" if kind == "f32cos" else "c5"], 20000, 300, n_clusters=40)
+        x, q = dg.base(cfg), dg.queries(cfg)
+    bv, qv = orc.Vectors.from_array(x, metric), orc.Vectors.from_array(q, metric)
+    cand = np.sort(np.random.default_rng(k + len(kind)).choice(20000, 6000, replace=False)).astype(np.int32)
+    rid, rd = orc.topk(qv, bv, k, cand=cand)
+    ids, d = api().topk(gpu_vectors(q, metric), gpu_vectors(x, metric), k, cand=to_dev(cand))
+    gi, gd = host(ids), host(d)
+    if kind == "u8":
+        assert np.array_equal(gi, rid)
+        assert np.array_equal(gd, rd.astype(np.int32))
+        return
+    floor = 1e-2 if metric == orc.COS else 0.0
+    full = orc.lib()
+    ex = np.array([[full.or_dist(bv.ref, int(j), qv.ref, r) for j in gi[r]] for r in range(len(q))])
+    assert np.all(np.abs(gd - ex) <= 1e-4 * np.maximum(np.abs(ex), floor))
+    for r in range(len(q)):
+        if set(gi[r]) != set(rid[r]):
+            kth = rd[r, -1]
+            for j in set(gi[r]) ^ set(rid[r]):
+                dj = full.or_dist(bv.ref, int(j), qv.ref, r)
+                assert abs(dj - kth) <= 1e-4 * max(abs(kth), floor), (kind, r, j)
+
+
 FW_N = 40_001       # above 128 query rows per compute unit: the bf16-screened f32 kernel
 
 
