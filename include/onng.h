@@ -96,9 +96,11 @@ typedef struct {
  * ConstructGraph (Algorithm 8) derives from an ANNG; Section 2.6 notes that
  * the exact graph is the costly ideal.
  * ids: [n][k] int32; dists: [n][k] in the distance type.  Requires
- * 1 <= k <= n - 1 and k <= 256.  On float data the distances are computed in
- * f32 on the matrix cores (|x|^2 + |y|^2 - 2<x, y>), so rows can differ from an
- * exact computation by rounding near ties.  u8 data is exact. */
+ * 1 <= k <= n - 1 and k <= 256.  On float data the distances are f32: from
+ * f32 matrix-core products (|x|^2 + |y|^2 - 2<x, y>), or, for many rows, from
+ * a bf16 matrix-core screen with a bound on its rounding whose survivors are
+ * recomputed in f32 from the rows; rows can differ from an exact computation
+ * by rounding near ties.  u8 data is exact. */
 onng_status onng_build_knn(const onng_vectors *base, int32_t k, int32_t *ids, void *dists,
                            void *ws, size_t ws_bytes, void *stream);
 
